@@ -1,0 +1,307 @@
+"""Benchmark: GEMM TFLOP/s through the selected variant vs the plain FP32 variant, and the
+selector's regret against exhaustive timing, on one MI355X.
+
+Phases (all on cuda:0, synthetic seeded inputs, no files read):
+  1. time-and-record: every variant on the square sweep N in {128, ..., 8192}
+     (normal(0,1) operands, 3 warm-up + 20 timed reps, median) -> history;
+  2. timed region: `--steps` steps after `--warmup` steps; one step is one
+     cmp_gemm per tolerance class {1e-5, 1e-3, 1e-2} at M = N = K = `--size`
+     with the history nearest-neighbour selector, operands resident in HBM;
+     per-kernel HIP-event timing is on during this region;
+  3. selector experiment (skipped with --no-selector): 2000 training and 500
+     held-out shapes with M, N, K log-uniform in [64, 8192], all variants timed,
+     network trained on the GPU from the training table, regret of each selector
+     on the held-out rows of the measured table;
+  4. CPU baseline: the FP64 CPU oracle on a bounded row panel of the same product.
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+
+PEAK = {  # MI355X published dense peaks (TFLOP/s) and HBM bandwidth (GB/s)
+    "bf16": 2516.6, "fp8": 5033.2, "fp32_vector": 157.3, "fp64_vector": 78.6, "hbm_gbs": 8000.0,
+}
+BOUNDS = [1e-5, 1e-5, 1e-3, 1e-2]
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_roofline(name: str, M: int, N: int, K: int):
+    """(bound, algorithmic work per launch, peak, unit) of a built-in kernel at M x N x K."""
+    Kp64 = -(-K // 64) * 64
+    Kp128 = -(-K // 128) * 128
+    if name == "gemm_f32_simt":
+        return "alu", 2.0 * M * N * K, PEAK["fp32_vector"], "TFLOP/s"
+    if name == "gemm_bf16_tn":
+        return "mfma", 2.0 * M * N * K, PEAK["bf16"], "TFLOP/s"
+    if name == "gemm_bf16x3_tn":
+        return "mfma", 3 * 2.0 * M * N * K, PEAK["bf16"], "TFLOP/s"
+    if name == "gemm_fp8r_tn":
+        return "mfma", 4 * 2.0 * M * N * K, PEAK["fp8"], "TFLOP/s"
+    # pre-pass kernels: bytes read + written (HBM-bound)
+    if name == "split_a_bf16":
+        return "hbm", 4.0 * M * K + 2.0 * M * Kp64, PEAK["hbm_gbs"], "GB/s"
+    if name == "split_a_bf16_hilo":
+        return "hbm", 4.0 * M * K + 4.0 * M * Kp64, PEAK["hbm_gbs"], "GB/s"
+    if name == "split_bt_bf16":
+        return "hbm", 4.0 * K * N + 2.0 * N * Kp64, PEAK["hbm_gbs"], "GB/s"
+    if name == "split_bt_bf16_hilo":
+        return "hbm", 4.0 * K * N + 4.0 * N * Kp64, PEAK["hbm_gbs"], "GB/s"
+    if name == "quant_fp8_a":
+        return "hbm", 4.0 * M * K + 2.0 * M * Kp128, PEAK["hbm_gbs"], "GB/s"
+    if name == "quant_fp8_bt":
+        return "hbm", 4.0 * K * N + 2.0 * N * Kp128, PEAK["hbm_gbs"], "GB/s"
+    return None
+
+
+def regret(T, choices, tols):
+    """Aggregate sum T[s, choice] / sum T[s, best admissible] - 1, plus mean and p95 per shape."""
+    best = []
+    for s in range(T.shape[0]):
+        adm = [v for v in range(4) if BOUNDS[v] <= tols[s]]
+        best.append(min(adm, key=lambda v: (T[s, v], BOUNDS[v], v)))
+    sel = np.array([T[s, c] for s, c in enumerate(choices)])
+    opt = np.array([T[s, b] for s, b in enumerate(best)])
+    per = sel / opt - 1.0
+    return dict(aggregate_pct=100.0 * float(sel.sum() / opt.sum() - 1.0),
+                mean_pct=100.0 * float(per.mean()), p95_pct=100.0 * float(np.percentile(per, 95)))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--size", type=int, default=8192)
+    ap.add_argument("--reps", type=int, default=20, help="timed reps per variant and shape")
+    ap.add_argument("--no-selector", action="store_true")
+    ap.add_argument("--train-shapes", type=int, default=2000)
+    ap.add_argument("--heldout-shapes", type=int, default=500)
+    ap.add_argument("--mlp-steps", type=int, default=5000)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus > 1 or world > 1:
+        print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported by this "
+              "single-GPU build (a GEMM shards by row panels of C with no exchange, one process per GPU)",
+              file=sys.stderr, flush=True)
+        sys.exit(2)
+
+    import torch
+    import paper_2311_03543_amd as pa
+
+    cx = pa.Compar(0)
+    dev = cx.device()
+    log(f"device {dev}")
+    n = args.size
+
+    # ---- 1. time and record: square sweep -----------------------------------------
+    sweep = {}
+    sizes = [s for s in synth.square_sweep_sizes() if s <= n] or [n]
+    if n not in sizes:
+        sizes.append(n)
+    big = {}
+    for s in sizes:
+        A, B = synth.gemm_operands(s, s, s, seed=synth.square_sweep_seed(s))
+        dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+        dC = torch.zeros((s, s), dtype=torch.float32, device="cuda")
+        row = {}
+        for vid, name in enumerate(pa.BUILTIN_VARIANTS):
+            med, mn, mean = cx.time_variant(vid, dA, dB, dC, warmup=3, reps=args.reps)
+            cx.history_add(s, s, s, vid, args.reps, med, mn, mean)
+            row[name] = dict(median_ms=med, min_ms=mn, mean_ms=mean, tflops=2.0 * s ** 3 / (med * 1e-3) / 1e12)
+        sweep[s] = row
+        log(f"sweep N={s}: " + ", ".join(f"{k} {v['tflops']:.1f} TF" for k, v in row.items()))
+        if s == n:
+            big = dict(A=A, B=B, dA=dA, dB=dB, dC=dC)
+        else:
+            del dA, dB, dC
+
+    # ---- 2. timed region ----------------------------------------------------------
+    dA, dB, dC = big["dA"], big["dB"], big["dC"]
+    cx.selector_set(pa.CMP_SEL_NN)
+    tols = list(synth.TOL_CLASSES)
+    for _ in range(args.warmup):
+        for tol in tols:
+            cx.gemm(dA, dB, dC, tol=tol)
+    torch.cuda.synchronize()
+    cx.kernel_stats(reset=True)
+    cx.kernel_timing(True)
+    chosen = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for tol in tols:
+            chosen[tol] = cx.gemm(dA, dB, dC, tol=tol)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    cx.kernel_timing(False)
+    kstats = cx.kernel_stats(reset=True)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    flops_step = len(tols) * 2.0 * n ** 3
+    value = flops_step / (ms_per_step * 1e-3) / 1e12
+    log(f"timed: {ms_per_step:.3f} ms/step, {value:.1f} TFLOP/s; chosen "
+        + ", ".join(f"{t:g}->{pa.BUILTIN_VARIANTS[v]}" for t, v in chosen.items()))
+
+    kernels = {}
+    for name, (cnt, tot) in kstats.items():
+        kernels[name] = dict(launches=cnt, avg_ms=tot / cnt, share=tot / (ms_per_step * args.steps))
+    dominant = max(kstats, key=lambda k: kstats[k][1])
+    bound, work, peak, unit = kernel_roofline(dominant, n, n, n)
+    avg_s = kernels[dominant]["avg_ms"] * 1e-3
+    achieved = work / avg_s / (1e12 if unit == "TFLOP/s" else 1e9)
+    roofline = dict(kernel=dominant, bound=bound, achieved=achieved, peak=peak, unit=unit,
+                    frac=achieved / peak, traffic=None)
+    for name, k in kernels.items():
+        r = kernel_roofline(name, n, n, n)
+        if r:
+            kb, kw, kp, ku = r
+            ach = kw / (k["avg_ms"] * 1e-3) / (1e12 if ku == "TFLOP/s" else 1e9)
+            k.update(achieved=ach, unit=ku, frac=ach / kp)
+    log("kernels: " + ", ".join(f"{k} {v['avg_ms']:.3f} ms ({v.get('frac', 0):.1%})" for k, v in kernels.items()))
+
+    fp32_tflops = sweep[n]["f32_simt"]["tflops"]
+    per_tol = {f"{t:g}": dict(variant=pa.BUILTIN_VARIANTS[v], median_ms=sweep[n][pa.BUILTIN_VARIANTS[v]]["median_ms"],
+                              tflops=sweep[n][pa.BUILTIN_VARIANTS[v]]["tflops"]) for t, v in chosen.items()}
+    del big
+    torch.cuda.empty_cache()
+
+    # ---- 3. selector experiment -----------------------------------------------------
+    selector = None
+    if not args.no_selector:
+        selector = selector_experiment(cx, pa, torch, args)
+
+    # ---- 4. CPU baseline: the oracle on a bounded row panel ----------------------------
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(n, args.cpu_seconds)
+
+    out = {
+        "metric": "GEMM TFLOP/s via selected variant vs plain FP32; selector regret % vs oracle",
+        "value": value,
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"square GEMM M=N=K={n}, FP32 in/out, normal(0,1) operands, one cmp_gemm "
+                               f"per tolerance class {{1e-5,1e-3,1e-2}} per step, history nearest-neighbour "
+                               f"selection", "M": n, "N": n, "K": n, "tolerances": tols},
+        "per_tolerance": per_tol,
+        "fp32_simt_tflops": fp32_tflops,
+        "speedup_vs_fp32": value / fp32_tflops,
+        "selector": selector,
+        "roofline": roofline,
+        "kernels": kernels,
+        "sweep_tflops": {str(s): {k: round(v["tflops"], 2) for k, v in row.items()} for s, row in sweep.items()},
+        "cpu_baseline": cpu,
+        "device": dev,
+    }
+    cx.close()
+    print(json.dumps(out), flush=True)
+
+
+def selector_experiment(cx, pa, torch, args):
+    ntr, nho = args.train_shapes, args.heldout_shapes
+    train = synth.log_uniform_shapes(ntr, 64, 8192, 2)
+    held = synth.log_uniform_shapes(nho, 64, 8192, 3, avoid={tuple(r) for r in train})
+    tol_tr = synth.tol_classes(ntr, 12)
+    tol_ho = synth.tol_classes(nho, 13)
+    # operands: the largest shape's A and B; each shape uses a tight prefix
+    need_a = int(max((s[0] * s[2] for s in np.vstack([train, held]))))
+    need_b = int(max((s[2] * s[1] for s in np.vstack([train, held]))))
+    need_c = int(max((s[0] * s[1] for s in np.vstack([train, held]))))
+    g = torch.Generator(device="cuda").manual_seed(4)
+    dA = torch.randn(need_a, device="cuda", generator=g)
+    dB = torch.randn(need_b, device="cuda", generator=g)
+    dC = torch.zeros(need_c, device="cuda")
+    sel = pa.Compar(0)
+    t0 = time.perf_counter()
+    shapes = np.vstack([train, held])
+    chunk = 100
+    for i in range(0, len(shapes), chunk):
+        sel.calibrate([tuple(map(int, s)) for s in shapes[i:i + chunk]], dA, dB, dC, warmup=2, reps=args.reps)
+        log(f"selector: timed {min(i + chunk, len(shapes))}/{len(shapes)} shapes ({time.perf_counter() - t0:.1f} s)")
+    rows = sel.history()
+    T = {}
+    for (M, N, K, vid, reps, med, mn, mean) in rows:
+        T.setdefault((M, N, K), [0.0] * 4)[vid] = med
+    Ttr = np.array([T[tuple(map(int, s))] for s in train])
+    Tho = np.array([T[tuple(map(int, s))] for s in held])
+    # training history only
+    sel.history_clear()
+    for s, trow in zip(train, Ttr):
+        for v in range(4):
+            sel.history_add(int(s[0]), int(s[1]), int(s[2]), v, args.reps, float(trow[v]))
+    q = [(int(m), int(nn), int(k), float(t)) for (m, nn, k), t in zip(held, tol_ho)]
+    res = {}
+    for kind, label in [(pa.CMP_SEL_NN, "nn"), (pa.CMP_SEL_STATIC, "static")]:
+        sel.selector_set(kind)
+        res[label] = regret(Tho, sel.select_batch(q), tol_ho)
+    t1 = time.perf_counter()
+    loss = sel.mlp_fit_history(steps=args.mlp_steps, lr=1e-3, seed=0)
+    t2 = time.perf_counter()
+    sel.selector_set(pa.CMP_SEL_MLP)
+    t3 = time.perf_counter()
+    mlp_choice = sel.select_batch(q)
+    t4 = time.perf_counter()
+    res["mlp"] = regret(Tho, mlp_choice, tol_ho)
+    res["always_fp32"] = regret(Tho, [0] * len(q), tol_ho)
+    # the best variant differs across shapes: how often each is the held-out optimum
+    best_counts = {}
+    for s in range(len(held)):
+        adm = [v for v in range(4) if BOUNDS[v] <= tol_ho[s]]
+        b = min(adm, key=lambda v: (Tho[s, v], BOUNDS[v], v))
+        best_counts[pa.BUILTIN_VARIANTS[b]] = best_counts.get(pa.BUILTIN_VARIANTS[b], 0) + 1
+    sel.close()
+    log(f"selector regret: " + ", ".join(f"{k} {v['aggregate_pct']:.2f}%" for k, v in res.items()))
+    return dict(train_shapes=ntr, heldout_shapes=nho, reps=args.reps, mlp_steps=args.mlp_steps,
+                mlp_final_loss=loss, mlp_train_s=t2 - t1, mlp_select_500_ms=(t4 - t3) * 1e3,
+                calibration_s=t1 - t0, regret=res, heldout_best_counts=best_counts,
+                regret_pct=res["mlp"]["aggregate_pct"])
+
+
+def cpu_baseline(n, seconds):
+    """The FP64 oracle (cpu_baseline leg) on rows [0, r) of the n^3 product, r sized for ~`seconds`."""
+    import oracle
+    A, B = synth.gemm_operands(n, n, n, seed=synth.square_sweep_seed(n))
+    probe = 16
+    t0 = time.perf_counter()
+    oracle.gemm(A[:probe], B)
+    dt = time.perf_counter() - t0
+    rows = int(max(probe, min(n, probe * seconds / max(dt, 1e-6))))
+    rows = max(probe, (rows // 32) * 32)
+    t0 = time.perf_counter()
+    oracle.gemm(A[:rows], B)
+    dt = time.perf_counter() - t0
+    flops = 2.0 * rows * n * n
+    log(f"cpu baseline: {rows} rows of {n}^3 in {dt:.1f} s = {flops / dt / 1e9:.1f} GFLOP/s")
+    return dict(value=flops / dt / 1e12, unit="TFLOP/s", cores=oracle.threads(), kind="oracle",
+                sample=f"FP64 oracle (blocked triple loop) on rows 0..{rows} of the {n}x{n}x{n} product "
+                       f"({flops / 1e9:.0f} GFLOP, {dt:.1f} s)", seconds=dt)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,307 @@
+/*
+ * compar.h -- C ABI of libcompar, a runtime that exposes several implementation
+ * variants of a component interface and picks one per call from the runtime
+ * context, after COMPAR (Memeti, "Enabling Dynamic Selection of Implementation
+ * Variants in Component-Based Parallel Programming for Heterogeneous Systems").
+ *
+ * The paper's directives become calls:
+ *   - method_declare(interface, name, target)   -> cmp_variant_register   (Sec. 2.1)
+ *   - parameter(name, type, size, access_mode)  -> cmp_param_desc lists    (Sec. 2.1)
+ *   - compar initialize / terminate             -> cmp_init / cmp_terminate (Sec. 2.1)
+ *   - generated task creation and submission    -> cmp_gemm / cmp_call_host (Sec. 2.2.2)
+ *   - the runtime's choice of codelet per task  -> cmp_select              (Sec. 2.2.2)
+ *   - resource restriction by environment       -> cmp_set_variant_mask    (Sec. 3.2)
+ *
+ * The built-in interface is "gemm": C = alpha * A * B + beta * C over float
+ * matrices (the paper's matrix-multiplication interface of Sec. 2.1, in BLAS
+ * form), with four hand-written HIP variants for gfx950 registered by cmp_init:
+ *
+ *   id 0 "f32_simt"  FP32 FMA on the vector ALUs            stated bound 1e-5
+ *   id 1 "bf16x3"    bf16 hi/lo split, three MFMA products  stated bound 1e-5
+ *   id 2 "fp8r"      E4M3 + one residual pass, four MFMA
+ *                    products with per-128x128-tile scales  stated bound 1e-3
+ *   id 3 "bf16"      bf16 operands, one MFMA product        stated bound 1e-2
+ *
+ * "Stated bound" is the relative Frobenius error ||C - C_exact||_F/||C_exact||_F
+ * the variant is registered with; a call with tolerance tol may only run
+ * variants whose bound is <= tol (the "context match" step of OpenMP's
+ * declare variant, which COMPAR extends, Sec. 2.1), and among those the
+ * selector picks the one with the lowest measured or predicted time.
+ *
+ * Conventions for every function:
+ *   - Returns a cmp_status; CMP_OK is 0 and every error is negative.  No C++
+ *     exception crosses this boundary.  cmp_last_error(ctx) returns a message
+ *     for the last failing call on that context.
+ *   - Matrices are row-major with leading dimensions in elements.  A, B, C in
+ *     cmp_gemm_args are DEVICE pointers owned by the caller; they must stay
+ *     valid until the work queued on `stream` has finished.  The library never
+ *     frees caller memory.  Host arrays (history rows, network parameters,
+ *     features) are read or written during the call only.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     GEMM calls are asynchronous on that stream unless stated otherwise.
+ *   - A cmp_ctx is not thread-safe: use one context per host thread.
+ *   - Name strings are copied on registration.
+ */
+#ifndef COMPAR_H
+#define COMPAR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum cmp_status {
+    CMP_OK = 0,
+    CMP_EINVAL = -1,        /* null pointer, negative size, ld < columns, tol <= 0, bad id */
+    CMP_EDUP = -2,          /* duplicate interface, parameter or variant name (Sec. 2.2.1) */
+    CMP_ESIG = -3,          /* variant signature differs from the interface's (Sec. 2.1) */
+    CMP_ENOTFOUND = -4,     /* unknown interface or variant name */
+    CMP_ENOVARIANT = -5,    /* no enabled variant's stated bound is within tol */
+    CMP_EUNSUPPORTED = -6,  /* operation needs a GPU context, or an unsupported dtype */
+    CMP_EHIP = -7,          /* a HIP runtime call failed (message has hipGetErrorString) */
+    CMP_ENOMEM = -8,        /* workspace allocation failed */
+    CMP_ECHECK = -9,        /* verify mode: residual check failed after the fallback */
+    CMP_ENODATA = -10       /* selector has no history / network to use */
+} cmp_status;
+
+typedef enum cmp_target {           /* target clause of method_declare (Sec. 2.1) */
+    CMP_TARGET_HIP = 1,             /* variant enqueues HIP work on the given stream */
+    CMP_TARGET_HOST = 2             /* variant runs synchronously on the calling host thread */
+} cmp_target;
+
+typedef enum cmp_dtype {            /* type clause of parameter (Sec. 2.1) */
+    CMP_F32 = 0, CMP_BF16 = 1, CMP_F8E4M3 = 2, CMP_F64 = 3, CMP_I32 = 4, CMP_I64 = 5
+} cmp_dtype;
+
+typedef enum cmp_access {           /* access_mode clause of parameter (Sec. 2.1) */
+    CMP_READ = 1, CMP_WRITE = 2, CMP_READWRITE = 3
+} cmp_access;
+
+typedef enum cmp_selector_kind {
+    CMP_SEL_STATIC = 0,     /* fixed choice per tolerance: lowest total recorded time */
+    CMP_SEL_NN = 1,         /* history nearest neighbour in (log2 M, log2 N, log2 K) */
+    CMP_SEL_MLP = 2         /* learned network predicting ln(time) per variant */
+} cmp_selector_kind;
+
+enum {
+    CMP_FLAG_VERIFY = 1u    /* after each cmp_gemm, run the FP64 Freivalds probe and fall
+                               back to the next tighter variant if it exceeds tol */
+};
+
+/* One parameter of an interface (the parameter directive, Sec. 2.1).  `extent`
+ * lists 0..4 sizes (0 = scalar, 1 = vector, 2 = matrix, ...); each is the name
+ * of another parameter of the interface or a decimal literal. */
+typedef struct cmp_param_desc {
+    const char *name;
+    int32_t type;           /* cmp_dtype */
+    int32_t ndim;           /* 0..4 */
+    const char *extent[4];
+    int32_t mode;           /* cmp_access */
+} cmp_param_desc;
+
+/* Arguments of the built-in "gemm" interface: C = alpha * A * B + beta * C.
+ * A is M x K (lda >= K), B is K x N (ldb >= N), C is M x N (ldc >= N), all
+ * float32 row-major device pointers.  BLAS semantics: beta == 0 never reads C;
+ * alpha == 0 or K == 0 never reads A or B; M == 0 or N == 0 is a no-op. */
+typedef struct cmp_gemm_args {
+    int64_t M, N, K;
+    int64_t lda, ldb, ldc;
+    float alpha, beta;
+    const float *A;
+    const float *B;
+    float *C;
+} cmp_gemm_args;
+
+/* The runtime context a selection is made for (Sec. 1: input size and
+ * system configuration; here also the caller's error tolerance). */
+typedef struct cmp_context {
+    int64_t M, N, K;
+    int32_t dtype;          /* cmp_dtype of the operands; only CMP_F32 is supported */
+    double tol;             /* relative Frobenius tolerance, > 0 */
+} cmp_context;
+
+/* A variant of an interface.  `args` points to the interface's argument
+ * struct (cmp_gemm_args for "gemm"); `workspace` is library-owned device
+ * memory of at least the size the variant's cmp_ws_fn asked for (NULL if it
+ * asked for 0); `user` is the pointer given at registration. */
+typedef int (*cmp_variant_fn)(const void *args, void *workspace, size_t ws_bytes,
+                              void *stream, void *user);
+/* Workspace bytes a variant needs for `args` (may be NULL: none). */
+typedef size_t (*cmp_ws_fn)(const void *args, void *user);
+
+typedef struct cmp_ctx cmp_ctx;
+
+/* ---- lifetime (compar initialize / terminate, Sec. 2.1) ---------------- */
+
+/* Create a context on HIP device `device` and register the "gemm" interface
+ * with its four built-in variants.  device < 0 creates a host-only context
+ * (no GPU touched, no built-in variants): host variants, registry, history
+ * and selection logic work; GPU entry points return CMP_EUNSUPPORTED.
+ * Environment: COMPAR_VARIANTS=<name,name,...> restricts the enabled gemm
+ * variants, COMPAR_SELECTOR=static|nn|mlp picks the selector,
+ * COMPAR_FORCE=<name> forces one variant, COMPAR_FAULT=<name>:<n> makes every
+ * n-th call of that variant fail with CMP_EHIP (for testing the fallback). */
+int cmp_init(int device, cmp_ctx **out);
+/* Release the workspace, history and network; `ctx` is invalid afterwards.
+ * Waits for the library's own streams, not for the caller's. NULL is a no-op. */
+int cmp_terminate(cmp_ctx *ctx);
+const char *cmp_last_error(const cmp_ctx *ctx);
+const char *cmp_status_string(int status);
+/* Library version string, and the device this context runs on (-1 = host). */
+const char *cmp_version(void);
+int cmp_device(const cmp_ctx *ctx, int *device, char *arch, size_t arch_len,
+               int *cu_count, int *clock_khz);
+
+/* ---- registry (method_declare and parameter, Sec. 2.1; semantic checks, Sec. 2.2.1) */
+
+/* Declare an interface with its parameter list.  CMP_EDUP if the interface
+ * exists or two parameters share a name; CMP_EINVAL on a bad descriptor or an
+ * extent naming no parameter. */
+int cmp_interface_declare(cmp_ctx *ctx, const char *iface, int nparams,
+                          const cmp_param_desc *params);
+/* Register a variant.  `params` may be NULL when the interface already exists
+ * (later variants share the first one's signature, Sec. 2.1); if given, it must
+ * equal the interface's list (CMP_ESIG otherwise), and if the interface does not
+ * exist yet it is declared with it.  err_bound > 0 is the stated relative
+ * Frobenius bound.  *id_out receives the variant's index in its interface. */
+int cmp_variant_register(cmp_ctx *ctx, const char *iface, const char *name, int target,
+                         int nparams, const cmp_param_desc *params,
+                         cmp_variant_fn fn, cmp_ws_fn ws, double err_bound,
+                         void *user, int *id_out);
+int cmp_variant_count(cmp_ctx *ctx, const char *iface, int *n);
+/* Name (pointer valid until cmp_terminate), target and stated bound of a variant. */
+int cmp_variant_info(cmp_ctx *ctx, const char *iface, int id, const char **name,
+                     int *target, double *err_bound);
+int cmp_variant_find(cmp_ctx *ctx, const char *iface, const char *name, int *id);
+/* Enable only the variants whose bit is set (bit i = id i); the analogue of the
+ * paper's CPU-only / GPU-only runs (Sec. 3.2). */
+int cmp_set_variant_mask(cmp_ctx *ctx, const char *iface, uint64_t mask);
+/* Force one variant for every call of the interface (id < 0 clears it). */
+int cmp_force_variant(cmp_ctx *ctx, const char *iface, int id);
+
+/* ---- selection (the runtime's choice of codelet, Sec. 2.2.2) ------------ */
+
+int cmp_selector_set(cmp_ctx *ctx, int kind);
+int cmp_set_flags(cmp_ctx *ctx, uint32_t flags);
+/* Admissible variants for ctx->tol as a bit mask (bit i = id i). */
+int cmp_admissible(cmp_ctx *ctx, const char *iface, const cmp_context *c, uint64_t *mask);
+/* Choose a variant for one context: admissible set, then the selector's
+ * argmin of time; ties go to the tighter stated bound, then the lower id.
+ * Falls back STATIC <- NN <- MLP when a selector has no data. */
+int cmp_select(cmp_ctx *ctx, const char *iface, const cmp_context *c, int *id_out);
+/* Same for n contexts at once; with the MLP selector all cache misses are
+ * predicted by one launch of the inference kernel. */
+int cmp_select_batch(cmp_ctx *ctx, const char *iface, int n, const cmp_context *c, int *ids_out);
+
+/* ---- execution (task creation and submission, Sec. 2.2.2) --------------- */
+
+/* Run "gemm" with the variant selected for (M, N, K, F32, tol).  Asynchronous
+ * on `stream` (except in verify mode, which synchronises the stream to read
+ * the probe).  *chosen (may be NULL) receives the variant id that ran. */
+int cmp_gemm(cmp_ctx *ctx, const cmp_gemm_args *args, double tol, void *stream, int *chosen);
+/* Run one named variant of "gemm" by id, bypassing selection. */
+int cmp_gemm_variant(cmp_ctx *ctx, int id, const cmp_gemm_args *args, void *stream);
+/* Run a host-target variant of any interface (synchronous), bypassing selection. */
+int cmp_call_host(cmp_ctx *ctx, const char *iface, int id, const void *args);
+
+/* ---- timing and history (performance history, Sec. 3.2) --------------- */
+
+/* Time one variant: `warmup` untimed calls, then `reps` calls each bracketed
+ * by HIP events on `stream` (host variants: steady clock).  Outputs in ms. */
+int cmp_time_variant(cmp_ctx *ctx, int id, const cmp_gemm_args *args, int warmup, int reps,
+                     void *stream, float *median_ms, float *min_ms, float *mean_ms);
+/* Time every enabled gemm variant on each of `nshapes` (M, N, K) triples
+ * (mnk[3*s + 0..2]) and append the results to the history.  A, B, C are device
+ * buffers holding at least max(M*K), max(K*N), max(M*N) floats; each shape uses
+ * them with tight leading dimensions, alpha = 1, beta = 0.  Shapes already in
+ * the history for a variant are skipped, so an interrupted calibration resumes. */
+int cmp_calibrate(cmp_ctx *ctx, int nshapes, const int64_t *mnk, const float *A,
+                  const float *B, float *C, int warmup, int reps, void *stream);
+int cmp_history_add(cmp_ctx *ctx, int64_t M, int64_t N, int64_t K, int id, int reps,
+                    float median_ms, float min_ms, float mean_ms);
+int cmp_history_count(cmp_ctx *ctx, int *n);
+int cmp_history_get(cmp_ctx *ctx, int row, int64_t *mnk, int *id, int *reps,
+                    float *median_ms, float *min_ms, float *mean_ms);
+int cmp_history_clear(cmp_ctx *ctx);
+/* Persist / reload the history as text with a header naming the device
+ * (arch, CU count, clock) and library version; load rejects (CMP_EINVAL) a
+ * file recorded on a different device signature unless `force` is non-zero. */
+int cmp_history_save(cmp_ctx *ctx, const char *path);
+int cmp_history_load(cmp_ctx *ctx, const char *path, int force);
+
+/* ---- learned selector (performance models trained from history, Sec. 3.2, 5) */
+
+/* The network is 4 -> 64 -> 64 -> 4 with ReLU, 4740 float parameters packed
+ * layer by layer as [W (out x in, row-major), b (out)].  Inputs are
+ * (log2 M, log2 N, log2 K, log10 tol) standardised by per-feature mean and
+ * population deviation; outputs are ln(median microseconds) of variants 0..3,
+ * standardised per output the same way. */
+int cmp_mlp_param_count(void);
+int cmp_mlp_set_params(cmp_ctx *ctx, const float *params, int n);
+int cmp_mlp_get_params(cmp_ctx *ctx, float *params, int n);
+/* Standardisation statistics (4 floats each); get works after training. */
+int cmp_mlp_set_norm(cmp_ctx *ctx, const float *mu_x, const float *sd_x,
+                     const float *mu_y, const float *sd_y);
+int cmp_mlp_get_norm(cmp_ctx *ctx, float *mu_x, float *sd_x, float *mu_y, float *sd_y);
+/* Train on the GPU from the current parameters: computes the standardisation
+ * of raw features X (n x 4) and raw targets Y (n x 4, ln microseconds) on the
+ * host, then runs `steps` full-batch Adam steps (beta1 0.9, beta2 0.999,
+ * eps 1e-8, fresh moments) in one resident kernel.  loss_trace (may be NULL)
+ * receives the loss before each step.  Synchronous.  n <= 8192. */
+int cmp_mlp_train(cmp_ctx *ctx, int n, const float *X, const float *Y, int steps, float lr,
+                  float *loss_trace);
+/* One loss and gradient evaluation on the GPU for standardised X, Y (n x 4). */
+int cmp_mlp_grad(cmp_ctx *ctx, int n, const float *Xs, const float *Ys, float *loss, float *grad);
+/* Batched inference kernel: standardised network outputs for standardised X. */
+int cmp_mlp_infer(cmp_ctx *ctx, int n, const float *Xs, float *Yout);
+/* Build features and ln-time targets from the history (shapes with a
+ * recorded time for all four built-in variants; tol feature drawn per row from
+ * the three classes by splitmix64(seed)), initialise the parameters
+ * Kaiming-uniform from splitmix64(seed), train, and enable the network for
+ * CMP_SEL_MLP.  *final_loss (may be NULL) receives the last loss. */
+int cmp_mlp_fit_history(cmp_ctx *ctx, int steps, float lr, uint64_t seed, float *final_loss);
+
+/* ---- verification (FP64 residual probe) -------------------------------- */
+
+/* Freivalds probe of a finished product: with x = probe (host array of N
+ * doubles, copied to the device), returns ||C x - (alpha A (B x) + beta C0 x)||
+ * / ||alpha A (B x) + beta C0 x|| computed in FP64 on the GPU.  c0 (device,
+ * ld = args->ldc) is the C before the product; it is read only if beta != 0.
+ * Synchronises `stream`. */
+int cmp_freivalds(cmp_ctx *ctx, const cmp_gemm_args *args, const float *c0, const double *probe,
+                  void *stream, double *estimate);
+/* Probe estimate of the last cmp_gemm in verify mode, and the number of
+ * fallbacks verify mode has taken on this context. */
+int cmp_last_verify(cmp_ctx *ctx, double *estimate, int *fallbacks);
+
+/* ---- operand pre-pass (exposed for bit-exact checking) ------------------ */
+
+/* bf16 split of a rows x cols float32 device matrix X (ld ldx) into hi and lo
+ * (device, rows x cols uint16 bit patterns, row-major, tight): hi = RNE(x),
+ * lo = RNE(x - hi).  lo may be NULL.  Asynchronous on stream. */
+int cmp_split_bf16(cmp_ctx *ctx, int64_t rows, int64_t cols, const float *X, int64_t ldx,
+                   uint16_t *hi, uint16_t *lo, void *stream);
+/* E4M3 tile quantisation with one residual pass (128 x 128 tiles, OCP E4M3,
+ * power-of-two scales 2^e with amax * 2^e <= 448 < amax * 2^(e+1)): q and rq
+ * are rows x cols bytes (device, tight), qscale and rscale the E8M0 bytes
+ * (127 - e) per tile, tile-row-major ceil(rows/128) x ceil(cols/128). */
+int cmp_quant_fp8(cmp_ctx *ctx, int64_t rows, int64_t cols, const float *X, int64_t ldx,
+                  uint8_t *q, uint8_t *qscale, uint8_t *rq, uint8_t *rscale, void *stream);
+
+/* ---- per-kernel timing (tracing of the built-in variants) ---------------- */
+
+/* When enabled, every kernel launch of the built-in variants is bracketed by
+ * a HIP event pair on its launch stream (adds two event records per launch). */
+int cmp_kernel_timing(cmp_ctx *ctx, int enable);
+/* Totals per kernel name, in name order: idx-th kernel's name, launch count and
+ * summed duration in ms (waits for the recorded events).  CMP_ENOTFOUND past
+ * the last kernel; idx < 0 resets the totals. */
+int cmp_kernel_stats(cmp_ctx *ctx, int idx, char *name, size_t name_len, long long *launches,
+                     double *total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* COMPAR_H */

@@ -228,3 +228,23 @@ def freivalds(A, B, Cout, x, alpha=1.0, beta=0.0, C0=None) -> float:
     return float(lib().oracle_freivalds(M, N, K, alpha, A, max(K, 1), B, max(N, 1), beta,
                                         None if c0 is None else c0.ctypes.data,
                                         Cout, max(N, 1), x))
+
+
+# ---------------------------------------------------------------------------
+# splitmix64 (Steele, Lea and Flood, "Fast splittable pseudorandom number
+# generators", 2014): output j of the generator seeded with s is
+# mix(s + (j + 1) * 0x9e3779b97f4a7c15) with the 64-bit finaliser below.
+_GOLDEN = 0x9E3779B97F4A7C15
+_MASK = (1 << 64) - 1
+
+
+def splitmix64(seed: int, j: int) -> int:
+    z = (seed + (j + 1) * _GOLDEN) & _MASK
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _MASK
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _MASK
+    return z ^ (z >> 31)
+
+
+def rademacher_splitmix(n: int, seed: int) -> np.ndarray:
+    """Probe vector x[j] = -1 if the top bit of splitmix64(seed, j) is set, else +1."""
+    return np.array([-1.0 if splitmix64(seed, j) >> 63 else 1.0 for j in range(n)])

@@ -1,0 +1,294 @@
+// MFMA GEMM kernels for gfx950 over the pre-pass images (both operands
+// K-contiguous: A image Mp x Kp, B image Np x Kp = B transposed).
+//
+//   bf16 / bf16x3:  C = alpha * sum_t A_t B_t^T + beta * C with one (bf16) or
+//                   three (hi.hi + hi.lo + lo.hi, the split-precision product)
+//                   operand pairs, v_mfma_f32_32x32x16_bf16, FP32 accumulation.
+//   fp8 refined:    C = alpha * (Aq.Bq + Ar.Bq + Aq.Br + Ar.Br) + beta * C over
+//                   E4M3 images with one E8M0 scale byte per 128 x 128 tile,
+//                   v_mfma_scale_f32_32x32x64_f8f6f4, FP32 accumulation.
+//
+// The extra products are K-concatenated: the main loop walks nterms * Kp / BK
+// steps and each step picks its operand pair, so one accumulator set and one
+// pipeline serve every term.
+//
+// Tiling: 256 x 256 C tile per workgroup of 4 wave64 (2 x 2 waves, 128 x 128
+// per wave = 4 x 4 MFMA blocks of 32 x 32, 256 FP32 accumulators per lane).
+// Each K step stages a 256-row A slab and a 256-row B slab (128 bytes of K per
+// row) in LDS with direct global->LDS loads (global_load_lds_dwordx4), so the
+// next step's tiles stream into the other buffer while the current step's
+// MFMAs run without occupying any registers.  Inside a slab row, 16-byte chunk
+// c of row r sits at position c ^ (r % 8): the 32 rows one fragment read
+// touches then spread over all bank groups.
+#include "common.h"
+#include "kernels.h"
+
+namespace cmp {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef int intx8 __attribute__((ext_vector_type(8)));
+
+constexpr int TM = 256, TN = 256;
+constexpr int ROWB = 128;           // bytes of K per row per step
+constexpr int THREADS = 256;
+constexpr int SLAB = TM * ROWB;     // bytes per operand slab (32 KiB)
+
+typedef const __attribute__((address_space(1))) void* gptr_t;
+typedef __attribute__((address_space(3))) void* lptr_t;
+
+// Stage rows [row0, row0 + 256) x bytes [kbyte, kbyte + 128) of an image with
+// row pitch ld_bytes into `slab`.  One wave instruction fills 1 KiB = 8 rows;
+// wave w issues instructions q = 8 w .. 8 w + 7.  Lane l of instruction q
+// lands at slab + 1024 q + 16 l, i.e. row 8 q + l / 8, position l % 8, which
+// holds global chunk (l % 8) ^ (l / 8).
+__device__ __forceinline__ void stage(const uint8_t* __restrict__ img, int64_t ld_bytes,
+                                      int64_t row0, int64_t kbyte, uint8_t* slab, int wave,
+                                      int lane) {
+    const int chunk = (lane & 7) ^ (lane >> 3);
+    const uint8_t* src = img + (row0 + wave * 64 + (lane >> 3)) * ld_bytes + kbyte + chunk * 16;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int q = wave * 8 + i;
+        __builtin_amdgcn_global_load_lds((gptr_t)(src + (int64_t)i * 8 * ld_bytes),
+                                         (lptr_t)(slab + q * 1024), 16, 0, 0);
+    }
+}
+
+// Byte address of 16-byte chunk c of slab row r.
+__device__ __forceinline__ int swz(int r, int c) { return r * ROWB + ((c ^ (r & 7)) << 4); }
+
+// Wait for this wave's outstanding global->LDS loads (vmcnt = 0).
+__device__ __forceinline__ void wait_loads() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// 32 x 32 accumulator block layout: lane l holds column l % 32 and rows
+// 8 (r / 4) + 4 (l / 32) + (r % 4), r = 0..15.
+__device__ __forceinline__ void epilogue(const floatx16 (&acc)[4][4], int64_t M, int64_t N,
+                                         int64_t m0, int64_t n0, int wm, int wn, int lane,
+                                         float alpha, float beta, float* __restrict__ C,
+                                         int64_t ldc) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t col = n0 + wn * 128 + j * 32 + (lane & 31);
+            if (col >= N) continue;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t row = m0 + wm * 128 + i * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+                if (row < M) {
+                    float* p = C + row * ldc + col;
+                    float v = alpha * acc[i][j][r];
+                    if (beta != 0.f) v = __builtin_fmaf(beta, *p, v);
+                    *p = v;
+                }
+            }
+        }
+}
+
+__device__ __forceinline__ void tile_coords(int tiles_m, int tiles_n, int& tm, int& tn) {
+    grouped_tile(xcd_remap(blockIdx.x, tiles_m * tiles_n), tiles_m, tiles_n, 8, tm, tn);
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void gemm_bf16_tn_kernel(int64_t M, int64_t N, int64_t Kp, int nterms, float alpha,
+                         const uint16_t* __restrict__ Ah, const uint16_t* __restrict__ Al,
+                         const uint16_t* __restrict__ Bh, const uint16_t* __restrict__ Bl,
+                         float beta, float* __restrict__ C, int64_t ldc, int tiles_m,
+                         int tiles_n) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    // LDS: [A slab 0 | A slab 1 | B slab 0 | B slab 1]
+
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    int tm, tn;
+    tile_coords(tiles_m, tiles_n, tm, tn);
+    const int64_t m0 = (int64_t)tm * TM, n0 = (int64_t)tn * TN;
+    const int64_t ldb = Kp * 2;                 // row pitch of both images in bytes
+    const int nk = (int)(Kp / 64);              // 64 bf16 = 128 bytes per step
+    const int steps = nterms * nk;
+
+    floatx16 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+    auto a_img = [&](int s) -> const uint8_t* {
+        return reinterpret_cast<const uint8_t*>((s / nk) == 2 ? Al : Ah);
+    };
+    auto b_img = [&](int s) -> const uint8_t* {
+        return reinterpret_cast<const uint8_t*>((s / nk) == 1 ? Bl : Bh);
+    };
+
+    stage(a_img(0), ldb, m0, 0, smem, wave, lane);
+    stage(b_img(0), ldb, n0, 0, smem + 2 * SLAB, wave, lane);
+    wait_loads();
+    __syncthreads();
+
+    const int frag_row = lane & 31;
+    const int frag_c = lane >> 5;               // chunk (8 bf16) within a 16-k sub-step
+    for (int s = 0; s < steps; ++s) {
+        const int cur = s & 1;
+        if (s + 1 < steps) {
+            const int64_t kb = (int64_t)((s + 1) % nk) * ROWB;
+            stage(a_img(s + 1), ldb, m0, kb, smem + (cur ^ 1) * SLAB, wave, lane);
+            stage(b_img(s + 1), ldb, n0, kb, smem + (2 + (cur ^ 1)) * SLAB, wave, lane);
+        }
+        const uint8_t* sa = smem + cur * SLAB;
+        const uint8_t* sb = smem + (2 + cur) * SLAB;
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {        // 16 k per MFMA = 2 chunks per row
+            bf16x8 af[4], bf[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                af[i] = *reinterpret_cast<const bf16x8*>(sa + swz(wm * 128 + i * 32 + frag_row, 2 * ks + frag_c));
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                bf[j] = *reinterpret_cast<const bf16x8*>(sb + swz(wn * 128 + j * 32 + frag_row, 2 * ks + frag_c));
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
+        }
+        wait_loads();
+        __syncthreads();
+    }
+    epilogue(acc, M, N, m0, n0, wm, wn, lane, alpha, beta, C, ldc);
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void gemm_fp8r_tn_kernel(int64_t M, int64_t N, int64_t Kp, float alpha,
+                         const uint8_t* __restrict__ Aq, const uint8_t* __restrict__ Ar,
+                         const uint8_t* __restrict__ Asq, const uint8_t* __restrict__ Asr,
+                         const uint8_t* __restrict__ Bq, const uint8_t* __restrict__ Br,
+                         const uint8_t* __restrict__ Bsq, const uint8_t* __restrict__ Bsr,
+                         float beta, float* __restrict__ C, int64_t ldc, int tiles_m,
+                         int tiles_n) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    // LDS: [A slab 0 | A slab 1 | B slab 0 | B slab 1]
+
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    int tm, tn;
+    tile_coords(tiles_m, tiles_n, tm, tn);
+    const int64_t m0 = (int64_t)tm * TM, n0 = (int64_t)tn * TN;
+    const int nk = (int)(Kp / 128);             // 128 E4M3 bytes per step
+    const int steps = 4 * nk;
+    // this wave's 128 rows of A (and columns of C) lie in one 128-row scale tile
+    const int64_t a_tile = m0 / 128 + wm, b_tile = n0 / 128 + wn;
+
+    floatx16 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+    // term s / nk: 0 = q.q, 1 = r.q, 2 = q.r, 3 = r.r
+    auto a_img = [&](int s) { return ((s / nk) & 1) ? Ar : Aq; };
+    auto b_img = [&](int s) { return ((s / nk) & 2) ? Br : Bq; };
+
+    stage(a_img(0), Kp, m0, 0, smem, wave, lane);
+    stage(b_img(0), Kp, n0, 0, smem + 2 * SLAB, wave, lane);
+    wait_loads();
+    __syncthreads();
+
+    const int frag_row = lane & 31;
+    const int frag_c = (lane >> 5) * 2;         // this lane's 2 chunks (32 bytes) of a 64-k sub-step
+    for (int s = 0; s < steps; ++s) {
+        const int cur = s & 1;
+        const int kt = s % nk;
+        const int term = s / nk;
+        if (s + 1 < steps) {
+            const int64_t kb = (int64_t)((s + 1) % nk) * ROWB;
+            stage(a_img(s + 1), Kp, m0, kb, smem + (cur ^ 1) * SLAB, wave, lane);
+            stage(b_img(s + 1), Kp, n0, kb, smem + (2 + (cur ^ 1)) * SLAB, wave, lane);
+        }
+        const int sca = (term & 1) ? Asr[a_tile * nk + kt] : Asq[a_tile * nk + kt];
+        const int scb = (term & 2) ? Bsr[b_tile * nk + kt] : Bsq[b_tile * nk + kt];
+        const uint8_t* sa = smem + cur * SLAB;
+        const uint8_t* sb = smem + (2 + cur) * SLAB;
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {        // 64 k per MFMA = 4 chunks per row
+            intx8 af[4], bf[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = wm * 128 + i * 32 + frag_row;
+                const uint4 lo = *reinterpret_cast<const uint4*>(sa + swz(r, 4 * ks + frag_c));
+                const uint4 hi = *reinterpret_cast<const uint4*>(sa + swz(r, 4 * ks + frag_c + 1));
+                af[i] = intx8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w,
+                              (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int r = wn * 128 + j * 32 + frag_row;
+                const uint4 lo = *reinterpret_cast<const uint4*>(sb + swz(r, 4 * ks + frag_c));
+                const uint4 hi = *reinterpret_cast<const uint4*>(sb + swz(r, 4 * ks + frag_c + 1));
+                bf[j] = intx8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w,
+                              (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                        af[i], bf[j], acc[i][j], 0, 0, 0, sca, 0, scb);
+        }
+        wait_loads();
+        __syncthreads();
+    }
+    epilogue(acc, M, N, m0, n0, wm, wn, lane, alpha, beta, C, ldc);
+}
+
+constexpr size_t kSmem = 4 * (size_t)SLAB;   // 131072 bytes
+
+}  // namespace
+
+hipError_t launch_gemm_bf16_tn(int64_t M, int64_t N, int64_t Kp, int nterms, float alpha,
+                               const uint16_t* Ah, const uint16_t* Al, const uint16_t* Bh,
+                               const uint16_t* Bl, float beta, float* C, int64_t ldc,
+                               hipStream_t stream) {
+    if (Kp % 64 || Kp <= 0 || (nterms != 1 && nterms != 3) || (nterms == 3 && (!Al || !Bl)))
+        return hipErrorInvalidValue;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)gemm_bf16_tn_kernel,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmem);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const int tiles_m = (int)((M + TM - 1) / TM), tiles_n = (int)((N + TN - 1) / TN);
+    hipLaunchKernelGGL(gemm_bf16_tn_kernel, dim3(tiles_m * tiles_n), dim3(THREADS), kSmem, stream,
+                       M, N, Kp, nterms, alpha, Ah, Al, Bh, Bl, beta, C, ldc, tiles_m, tiles_n);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_fp8r_tn(int64_t M, int64_t N, int64_t Kp, float alpha, const uint8_t* Aq,
+                               const uint8_t* Ar, const uint8_t* Asq, const uint8_t* Asr,
+                               const uint8_t* Bq, const uint8_t* Br, const uint8_t* Bsq,
+                               const uint8_t* Bsr, float beta, float* C, int64_t ldc,
+                               hipStream_t stream) {
+    if (Kp % 128 || Kp <= 0) return hipErrorInvalidValue;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)gemm_fp8r_tn_kernel,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmem);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const int tiles_m = (int)((M + TM - 1) / TM), tiles_n = (int)((N + TN - 1) / TN);
+    hipLaunchKernelGGL(gemm_fp8r_tn_kernel, dim3(tiles_m * tiles_n), dim3(THREADS), kSmem, stream,
+                       M, N, Kp, alpha, Aq, Ar, Asq, Asr, Bq, Br, Bsq, Bsr, beta, C, ldc, tiles_m,
+                       tiles_n);
+    return hipGetLastError();
+}
+
+}  // namespace cmp

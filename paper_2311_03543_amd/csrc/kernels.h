@@ -1,0 +1,93 @@
+// Internal launch interface between the host runtime (runtime.cpp) and the
+// gfx950 kernels.  Every launch_* function only enqueues work on `stream` and
+// returns the hipError_t of the launch; shapes are validated by the caller.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace cmp {
+
+// ---- FP32 SIMT GEMM (vector-ALU FMA, LDS-staged tiles) -------------------
+hipError_t launch_gemm_f32_simt(int64_t M, int64_t N, int64_t K, float alpha,
+                                const float* A, int64_t lda, const float* B, int64_t ldb,
+                                float beta, float* C, int64_t ldc, hipStream_t stream);
+
+// C = beta * C (or 0 when beta == 0) for the alpha == 0 / K == 0 cases.
+hipError_t launch_scale_c(int64_t M, int64_t N, float beta, float* C, int64_t ldc,
+                          hipStream_t stream);
+
+// ---- operand pre-pass -------------------------------------------------------
+// Padded, K-contiguous operand images used by the MFMA kernels:
+//   A  (M x K, ld lda)  ->  Ah / Al  (Mp x Kp bf16, row-major)
+//   B  (K x N, ld ldb)  ->  Bh / Bl  (Np x Kp bf16, i.e. B transposed)
+// Padding rows / columns are zero.  lo pointers may be null (bf16 only).
+hipError_t launch_split_a_bf16(int64_t M, int64_t K, const float* A, int64_t lda,
+                               int64_t Mp, int64_t Kp, uint16_t* hi, uint16_t* lo,
+                               hipStream_t stream);
+hipError_t launch_split_bt_bf16(int64_t K, int64_t N, const float* B, int64_t ldb,
+                                int64_t Np, int64_t Kp, uint16_t* hi, uint16_t* lo,
+                                hipStream_t stream);
+// Plain bf16 split of a row-major matrix, tight output (bit-exact checking).
+hipError_t launch_split_bf16_plain(int64_t rows, int64_t cols, const float* X, int64_t ldx,
+                                   uint16_t* hi, uint16_t* lo, hipStream_t stream);
+
+// E4M3 tile quantisation with one residual pass, 128 x 128 tiles.
+//   transpose = false: X is rows x cols (ld ldx); q/rq are out_rows x out_cols with
+//                      out_rows >= rows, out_cols >= cols (row-major, ld out_cols);
+//                      scales are indexed [row_tile * (out_cols/128) + col_tile].
+//   transpose = true:  q/rq receive X transposed (out_rows >= cols, out_cols >= rows),
+//                      scales indexed [col_tile_of_X * (out_cols/128) + row_tile_of_X].
+// Padding in q/rq is written as zero codes (scale bytes of all-padding tiles 127).
+hipError_t launch_quant_fp8(int64_t rows, int64_t cols, const float* X, int64_t ldx,
+                            bool transpose, int64_t out_rows, int64_t out_cols,
+                            uint8_t* q, uint8_t* qscale, uint8_t* rq, uint8_t* rscale,
+                            hipStream_t stream);
+
+// ---- MFMA GEMMs over pre-pass images -------------------------------------
+// bf16: C = alpha * sum_t A_t * B_t^T + beta * C over `nterms` (1 or 3) operand
+// pairs (t = 0: hi*hi, 1: hi*lo, 2: lo*hi); Ah/Al are Mp x Kp, Bh/Bl Np x Kp.
+hipError_t launch_gemm_bf16_tn(int64_t M, int64_t N, int64_t Kp, int nterms, float alpha,
+                               const uint16_t* Ah, const uint16_t* Al,
+                               const uint16_t* Bh, const uint16_t* Bl,
+                               float beta, float* C, int64_t ldc, hipStream_t stream);
+// fp8 with refinement: C = alpha * (Aq.Bq + Ar.Bq + Aq.Br + Ar.Br) + beta * C,
+// each operand dequantised by its 128 x 128 tile's E8M0 scale byte.
+hipError_t launch_gemm_fp8r_tn(int64_t M, int64_t N, int64_t Kp, float alpha,
+                               const uint8_t* Aq, const uint8_t* Ar,
+                               const uint8_t* Asq, const uint8_t* Asr,
+                               const uint8_t* Bq, const uint8_t* Br,
+                               const uint8_t* Bsq, const uint8_t* Bsr,
+                               float beta, float* C, int64_t ldc, hipStream_t stream);
+
+// Tile sizes the MFMA kernels assume for padding.
+constexpr int kMfmaTileM = 256;
+constexpr int kMfmaTileN = 256;
+constexpr int kBf16TileK = 64;
+constexpr int kFp8TileK = 128;
+
+// ---- FP64 Freivalds probe -------------------------------------------------
+// out[0] = ||C x - (alpha A (B x) + beta C0 x)||^2, out[1] = ||alpha A(Bx) + beta C0 x||^2.
+// x: N doubles on the device; ws: at least (K + 2) doubles; out: 2 doubles (device).
+hipError_t launch_freivalds(int64_t M, int64_t N, int64_t K, float alpha, const float* A,
+                            int64_t lda, const float* B, int64_t ldb, float beta,
+                            const float* C0, const float* C, int64_t ldc, const double* x,
+                            double* ws, double* out, hipStream_t stream);
+// x[j] = +-1 from splitmix64(seed + j): the top bit set gives -1.
+hipError_t launch_rademacher(int64_t n, uint64_t seed, double* x, hipStream_t stream);
+
+// ---- selector network -------------------------------------------------------
+// Parameters are 4740 floats (see compar.h).  Training runs `steps` Adam steps
+// in one resident workgroup; X, Y standardised (n x 4) device arrays.
+constexpr int kMlpParams = 4 * 64 + 64 + 64 * 64 + 64 + 64 * 4 + 4;
+constexpr int kMlpMaxRows = 8192;
+// partial-gradient scratch: one (params + loss) record per 32-row workgroup
+constexpr int kMlpPartFloats = (kMlpMaxRows / 32) * (kMlpParams + 1);
+hipError_t launch_mlp_train(int n, const float* X, const float* Y, float* params, float* m,
+                            float* v, float* part, int steps, int t0, float lr, float* loss_trace,
+                            float* grad_out, hipStream_t stream);
+hipError_t launch_mlp_infer(int n, const float* X, const float* params, float* Y,
+                            hipStream_t stream);
+
+}  // namespace cmp

@@ -1,0 +1,1640 @@
+// libcompar host runtime: interface/variant registry, selection by runtime
+// context, performance history, timing, verify mode and the built-in "gemm"
+// variants.  Plays the part COMPAR gives to its generated glue code plus the
+// StarPU runtime (Sec. 2.2): variants are registered at run time instead of
+// being declared by pragmas, and the runtime picks one per call.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <tuple>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/compar.h"
+#include "kernels.h"
+
+#define CMP_API extern "C" __attribute__((visibility("default")))
+
+namespace {
+
+constexpr const char* kVersion = "compar-mi355x 0.1.0";
+constexpr const char* kGemm = "gemm";
+constexpr int kNumBuiltin = 4;
+constexpr double kTolClasses[3] = {1e-5, 1e-3, 1e-2};
+
+struct Param {
+    std::string name;
+    int type = 0, ndim = 0, mode = 0;
+    std::string extent[4];
+    bool operator==(const Param& o) const {
+        if (name != o.name || type != o.type || ndim != o.ndim || mode != o.mode) return false;
+        for (int i = 0; i < ndim; ++i)
+            if (extent[i] != o.extent[i]) return false;
+        return true;
+    }
+};
+
+enum BuiltinKind { kNone = -1, kF32Simt = 0, kBf16x3 = 1, kFp8r = 2, kBf16 = 3 };
+
+struct Variant {
+    std::string name;
+    int target = CMP_TARGET_HIP;
+    cmp_variant_fn fn = nullptr;
+    cmp_ws_fn ws = nullptr;
+    double bound = 0;
+    void* user = nullptr;
+    uint64_t calls = 0;
+};
+
+struct Interface {
+    std::string name;
+    std::vector<Param> params;
+    std::vector<Variant> variants;
+    uint64_t mask = ~0ull;
+    int forced = -1;
+};
+
+struct HistRow {
+    int64_t M, N, K;
+    int id, reps;
+    float med, mn, mean;
+};
+
+struct CacheKey {
+    int64_t M, N, K;
+    double tol;
+    bool operator==(const CacheKey& o) const {
+        return M == o.M && N == o.N && K == o.K && tol == o.tol;
+    }
+};
+struct CacheHash {
+    size_t operator()(const CacheKey& k) const {
+        uint64_t h = 1469598103934665603ull;
+        auto mix = [&](uint64_t v) { h = (h ^ v) * 1099511628211ull; };
+        mix((uint64_t)k.M);
+        mix((uint64_t)k.N);
+        mix((uint64_t)k.K);
+        uint64_t t;
+        std::memcpy(&t, &k.tol, 8);
+        mix(t);
+        return (size_t)h;
+    }
+};
+
+// splitmix64 (Steele, Lea and Flood 2014): output j of a generator seeded
+// with `seed` is mix(seed + (j + 1) * golden).
+inline uint64_t splitmix64_at(uint64_t seed, uint64_t j) {
+    uint64_t z = seed + (j + 1) * 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+inline double u01(uint64_t z) { return (double)(z >> 11) * (1.0 / 9007199254740992.0); }
+
+}  // namespace
+
+struct cmp_ctx {
+    int device = -1;
+    bool gpu = false;
+    hipDeviceProp_t props{};
+    std::vector<Interface> ifaces;
+    std::string last_error;
+    int selector = CMP_SEL_NN;
+    uint32_t flags = 0;
+    std::vector<HistRow> history;
+    std::unordered_map<CacheKey, int, CacheHash> cache;
+    // learned selector
+    std::vector<float> mlp_params;
+    float mu_x[4] = {0, 0, 0, 0}, sd_x[4] = {1, 1, 1, 1};
+    float mu_y[4] = {0, 0, 0, 0}, sd_y[4] = {1, 1, 1, 1};
+    bool mlp_ready = false;
+    // device memory owned by the library
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    void* vws = nullptr;     // verify-mode workspace (C0 copy, probe vector, partial sums)
+    size_t vws_bytes = 0;
+    float* mlp_dev = nullptr;  // params | m | v | X | Y | loss | grad | infer io
+    hipStream_t side = nullptr;
+    // verify mode and fault injection
+    double last_verify = -1.0;
+    int fallbacks = 0;
+    uint64_t verify_calls = 0;
+    std::string fault_name;
+    uint64_t fault_every = 0;
+    // per-kernel timing of the built-in variants (HIP events around each launch)
+    bool ktime = false;
+    struct KEv {
+        std::string name;
+        hipEvent_t a, b;
+    };
+    std::vector<KEv> kpending;
+    std::vector<hipEvent_t> kpool;
+    std::map<std::string, std::pair<long long, double>> kstats;  // launches, total ms
+    // COMPAR_VARIANTS / COMPAR_FORCE, applied by name to gemm variants as they register
+    bool env_restrict = false;
+    std::vector<std::string> env_allow;
+    std::string env_force;
+};
+
+namespace {
+
+int fail(cmp_ctx* c, int st, const char* fmt, ...) {
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        std::vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->last_error = buf;
+    }
+    return st;
+}
+
+int hip_fail(cmp_ctx* c, hipError_t e, const char* what) {
+    return fail(c, CMP_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(ctx, expr)                                   \
+    do {                                                     \
+        hipError_t _e = (expr);                              \
+        if (_e != hipSuccess) return hip_fail(ctx, _e, #expr); \
+    } while (0)
+
+// Optional per-kernel timing: a scope that records a HIP event pair on the
+// launch stream around one kernel launch of a built-in variant.
+hipEvent_t kev_get(cmp_ctx* c) {
+    if (!c->kpool.empty()) {
+        hipEvent_t e = c->kpool.back();
+        c->kpool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+struct KTimer {
+    cmp_ctx* c;
+    hipStream_t s;
+    const char* name;
+    hipEvent_t a = nullptr;
+    KTimer(cmp_ctx* c_, hipStream_t s_, const char* n) : c(c_), s(s_), name(n) {
+        if (c && c->ktime && (a = kev_get(c))) (void)hipEventRecord(a, s);
+    }
+    ~KTimer() {
+        if (!a) return;
+        hipEvent_t b = kev_get(c);
+        if (!b) {
+            c->kpool.push_back(a);
+            return;
+        }
+        (void)hipEventRecord(b, s);
+        c->kpending.push_back({name, a, b});
+    }
+};
+
+Interface* find_iface(cmp_ctx* c, const char* name) {
+    if (!name) return nullptr;
+    for (auto& f : c->ifaces)
+        if (f.name == name) return &f;
+    return nullptr;
+}
+
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// ---------------------------------------------------------------------------
+// Built-in gemm variants.  `user` is the context.
+
+size_t ws_none(const void*, void*) { return 0; }
+
+struct Bf16Layout {
+    int64_t Mp, Np, Kp;
+    size_t a_elems, b_elems;
+};
+Bf16Layout bf16_layout(const cmp_gemm_args* a) {
+    Bf16Layout L;
+    L.Mp = round_up(std::max<int64_t>(a->M, 1), cmp::kMfmaTileM);
+    L.Np = round_up(std::max<int64_t>(a->N, 1), cmp::kMfmaTileN);
+    L.Kp = round_up(std::max<int64_t>(a->K, 1), cmp::kBf16TileK);
+    L.a_elems = (size_t)L.Mp * L.Kp;
+    L.b_elems = (size_t)L.Np * L.Kp;
+    return L;
+}
+size_t ws_bf16(const void* args, void*) {
+    auto L = bf16_layout((const cmp_gemm_args*)args);
+    return (L.a_elems + L.b_elems) * 2;
+}
+size_t ws_bf16x3(const void* args, void*) { return 2 * ws_bf16(args, nullptr); }
+
+struct Fp8Layout {
+    int64_t Mp, Np, Kp;
+    size_t a_bytes, b_bytes, as_bytes, bs_bytes;
+};
+Fp8Layout fp8_layout(const cmp_gemm_args* a) {
+    Fp8Layout L;
+    L.Mp = round_up(std::max<int64_t>(a->M, 1), cmp::kMfmaTileM);
+    L.Np = round_up(std::max<int64_t>(a->N, 1), cmp::kMfmaTileN);
+    L.Kp = round_up(std::max<int64_t>(a->K, 1), cmp::kFp8TileK);
+    L.a_bytes = (size_t)L.Mp * L.Kp;
+    L.b_bytes = (size_t)L.Np * L.Kp;
+    L.as_bytes = round_up((L.Mp / 128) * (L.Kp / 128), 256);
+    L.bs_bytes = round_up((L.Np / 128) * (L.Kp / 128), 256);
+    return L;
+}
+size_t ws_fp8r(const void* args, void*) {
+    auto L = fp8_layout((const cmp_gemm_args*)args);
+    return 2 * (L.a_bytes + L.b_bytes + L.as_bytes + L.bs_bytes);
+}
+
+// Degenerate shapes shared by every built-in: nothing to do, or C = beta * C.
+bool gemm_trivial(const cmp_gemm_args* a, hipStream_t s, int* st) {
+    if (a->M == 0 || a->N == 0) {
+        *st = CMP_OK;
+        return true;
+    }
+    if (a->alpha == 0.f || a->K == 0) {
+        *st = cmp::launch_scale_c(a->M, a->N, a->beta, a->C, a->ldc, s) == hipSuccess ? CMP_OK
+                                                                                      : CMP_EHIP;
+        return true;
+    }
+    return false;
+}
+
+int v_f32_simt(const void* args, void*, size_t, void* stream, void* user) {
+    auto a = (const cmp_gemm_args*)args;
+    auto s = (hipStream_t)stream;
+    int st;
+    if (gemm_trivial(a, s, &st)) return st;
+    KTimer kt((cmp_ctx*)user, s, "gemm_f32_simt");
+    return cmp::launch_gemm_f32_simt(a->M, a->N, a->K, a->alpha, a->A, a->lda, a->B, a->ldb,
+                                     a->beta, a->C, a->ldc, s) == hipSuccess
+               ? CMP_OK
+               : CMP_EHIP;
+}
+
+int run_bf16(cmp_ctx* c, const cmp_gemm_args* a, void* ws, hipStream_t s, int nterms) {
+    int st;
+    if (gemm_trivial(a, s, &st)) return st;
+    auto L = bf16_layout(a);
+    auto* base = (uint16_t*)ws;
+    uint16_t* Ah = base;
+    uint16_t* Bh = Ah + L.a_elems;
+    uint16_t* Al = nterms > 1 ? Bh + L.b_elems : nullptr;
+    uint16_t* Bl = nterms > 1 ? Al + L.a_elems : nullptr;
+    {
+        KTimer kt(c, s, nterms > 1 ? "split_a_bf16_hilo" : "split_a_bf16");
+        if (cmp::launch_split_a_bf16(a->M, a->K, a->A, a->lda, L.Mp, L.Kp, Ah, Al, s) != hipSuccess)
+            return CMP_EHIP;
+    }
+    {
+        KTimer kt(c, s, nterms > 1 ? "split_bt_bf16_hilo" : "split_bt_bf16");
+        if (cmp::launch_split_bt_bf16(a->K, a->N, a->B, a->ldb, L.Np, L.Kp, Bh, Bl, s) != hipSuccess)
+            return CMP_EHIP;
+    }
+    {
+        KTimer kt(c, s, nterms > 1 ? "gemm_bf16x3_tn" : "gemm_bf16_tn");
+        if (cmp::launch_gemm_bf16_tn(a->M, a->N, L.Kp, nterms, a->alpha, Ah, Al, Bh, Bl, a->beta,
+                                     a->C, a->ldc, s) != hipSuccess)
+            return CMP_EHIP;
+    }
+    return CMP_OK;
+}
+int v_bf16(const void* args, void* ws, size_t, void* stream, void* user) {
+    return run_bf16((cmp_ctx*)user, (const cmp_gemm_args*)args, ws, (hipStream_t)stream, 1);
+}
+int v_bf16x3(const void* args, void* ws, size_t, void* stream, void* user) {
+    return run_bf16((cmp_ctx*)user, (const cmp_gemm_args*)args, ws, (hipStream_t)stream, 3);
+}
+
+int v_fp8r(const void* args, void* ws, size_t, void* stream, void* user) {
+    auto* c = (cmp_ctx*)user;
+    auto a = (const cmp_gemm_args*)args;
+    auto s = (hipStream_t)stream;
+    int st;
+    if (gemm_trivial(a, s, &st)) return st;
+    auto L = fp8_layout(a);
+    auto* p = (uint8_t*)ws;
+    uint8_t* Aq = p;
+    p += L.a_bytes;
+    uint8_t* Ar = p;
+    p += L.a_bytes;
+    uint8_t* Bq = p;
+    p += L.b_bytes;
+    uint8_t* Br = p;
+    p += L.b_bytes;
+    uint8_t* Asq = p;
+    p += L.as_bytes;
+    uint8_t* Asr = p;
+    p += L.as_bytes;
+    uint8_t* Bsq = p;
+    p += L.bs_bytes;
+    uint8_t* Bsr = p;
+    {
+        KTimer kt(c, s, "quant_fp8_a");
+        if (cmp::launch_quant_fp8(a->M, a->K, a->A, a->lda, false, L.Mp, L.Kp, Aq, Asq, Ar, Asr, s) !=
+            hipSuccess)
+            return CMP_EHIP;
+    }
+    {
+        KTimer kt(c, s, "quant_fp8_bt");
+        if (cmp::launch_quant_fp8(a->K, a->N, a->B, a->ldb, true, L.Np, L.Kp, Bq, Bsq, Br, Bsr, s) !=
+            hipSuccess)
+            return CMP_EHIP;
+    }
+    {
+        KTimer kt(c, s, "gemm_fp8r_tn");
+        if (cmp::launch_gemm_fp8r_tn(a->M, a->N, L.Kp, a->alpha, Aq, Ar, Asq, Asr, Bq, Br, Bsq, Bsr,
+                                     a->beta, a->C, a->ldc, s) != hipSuccess)
+            return CMP_EHIP;
+    }
+    return CMP_OK;
+}
+
+// ---------------------------------------------------------------------------
+
+int validate_params(cmp_ctx* c, int n, const cmp_param_desc* p, std::vector<Param>* out) {
+    if (n < 0 || (n > 0 && !p)) return fail(c, CMP_EINVAL, "bad parameter list");
+    std::vector<Param> v;
+    for (int i = 0; i < n; ++i) {
+        if (!p[i].name || !*p[i].name) return fail(c, CMP_EINVAL, "parameter %d has no name", i);
+        if (p[i].ndim < 0 || p[i].ndim > 4)
+            return fail(c, CMP_EINVAL, "parameter %s: ndim must be 0..4", p[i].name);
+        if (p[i].type < CMP_F32 || p[i].type > CMP_I64)
+            return fail(c, CMP_EINVAL, "parameter %s: unknown type", p[i].name);
+        if (p[i].mode < CMP_READ || p[i].mode > CMP_READWRITE)
+            return fail(c, CMP_EINVAL, "parameter %s: unknown access mode", p[i].name);
+        Param q;
+        q.name = p[i].name;
+        q.type = p[i].type;
+        q.ndim = p[i].ndim;
+        q.mode = p[i].mode;
+        for (int d = 0; d < q.ndim; ++d) {
+            if (!p[i].extent[d] || !*p[i].extent[d])
+                return fail(c, CMP_EINVAL, "parameter %s: missing extent %d", p[i].name, d);
+            q.extent[d] = p[i].extent[d];
+        }
+        for (auto& o : v)
+            if (o.name == q.name) return fail(c, CMP_EDUP, "duplicate parameter %s", q.name.c_str());
+        v.push_back(q);
+    }
+    // every extent is a literal or names a scalar parameter of the interface
+    for (auto& q : v)
+        for (int d = 0; d < q.ndim; ++d) {
+            const std::string& e = q.extent[d];
+            bool lit = std::all_of(e.begin(), e.end(), [](char ch) { return ch >= '0' && ch <= '9'; });
+            if (lit) continue;
+            bool found = false;
+            for (auto& o : v)
+                if (o.name == e && o.ndim == 0) found = true;
+            if (!found)
+                return fail(c, CMP_EINVAL, "parameter %s: extent %s names no scalar parameter",
+                            q.name.c_str(), e.c_str());
+        }
+    *out = std::move(v);
+    return CMP_OK;
+}
+
+int register_variant(cmp_ctx* c, const char* iface, const char* name, int target, int nparams,
+                     const cmp_param_desc* params, cmp_variant_fn fn, cmp_ws_fn ws,
+                     double bound, void* user, int* id_out);
+void apply_env_to_variant(cmp_ctx* c, Interface* f, int id);
+
+void register_builtins(cmp_ctx* c) {
+    static const cmp_param_desc gemm_params[] = {
+        {"M", CMP_I64, 0, {nullptr, nullptr, nullptr, nullptr}, CMP_READ},
+        {"N", CMP_I64, 0, {nullptr, nullptr, nullptr, nullptr}, CMP_READ},
+        {"K", CMP_I64, 0, {nullptr, nullptr, nullptr, nullptr}, CMP_READ},
+        {"alpha", CMP_F32, 0, {nullptr, nullptr, nullptr, nullptr}, CMP_READ},
+        {"beta", CMP_F32, 0, {nullptr, nullptr, nullptr, nullptr}, CMP_READ},
+        {"A", CMP_F32, 2, {"M", "K", nullptr, nullptr}, CMP_READ},
+        {"B", CMP_F32, 2, {"K", "N", nullptr, nullptr}, CMP_READ},
+        {"C", CMP_F32, 2, {"M", "N", nullptr, nullptr}, CMP_READWRITE},
+    };
+    cmp_interface_declare(c, kGemm, 8, gemm_params);
+    if (!c->gpu) return;
+    int id;
+    register_variant(c, kGemm, "f32_simt", CMP_TARGET_HIP, 0, nullptr, v_f32_simt, ws_none, 1e-5, c, &id);
+    register_variant(c, kGemm, "bf16x3", CMP_TARGET_HIP, 0, nullptr, v_bf16x3, ws_bf16x3, 1e-5, c, &id);
+    register_variant(c, kGemm, "fp8r", CMP_TARGET_HIP, 0, nullptr, v_fp8r, ws_fp8r, 1e-3, c, &id);
+    register_variant(c, kGemm, "bf16", CMP_TARGET_HIP, 0, nullptr, v_bf16, ws_bf16, 1e-2, c, &id);
+}
+
+int register_variant(cmp_ctx* c, const char* iface, const char* name, int target, int nparams,
+                     const cmp_param_desc* params, cmp_variant_fn fn, cmp_ws_fn ws,
+                     double bound, void* user, int* id_out) {
+    if (!iface || !name || !*name || !fn) return fail(c, CMP_EINVAL, "null interface, name or function");
+    if (target != CMP_TARGET_HIP && target != CMP_TARGET_HOST)
+        return fail(c, CMP_EINVAL, "unknown target %d", target);
+    if (!(bound > 0) || !std::isfinite(bound)) return fail(c, CMP_EINVAL, "error bound must be > 0");
+    if (target == CMP_TARGET_HIP && !c->gpu)
+        return fail(c, CMP_EUNSUPPORTED, "HIP variant on a host-only context");
+    Interface* f = find_iface(c, iface);
+    if (params) {
+        std::vector<Param> v;
+        int st = validate_params(c, nparams, params, &v);
+        if (st) return st;
+        if (!f) {
+            c->ifaces.push_back(Interface{});
+            f = &c->ifaces.back();
+            f->name = iface;
+            f->params = std::move(v);
+        } else if (!(f->params == v)) {
+            return fail(c, CMP_ESIG, "variant %s: signature differs from interface %s", name, iface);
+        }
+    } else if (!f) {
+        return fail(c, CMP_ENOTFOUND, "interface %s not declared and no parameters given", iface);
+    }
+    for (auto& v : f->variants)
+        if (v.name == name) return fail(c, CMP_EDUP, "duplicate variant %s of %s", name, iface);
+    if (f->variants.size() >= 64) return fail(c, CMP_EINVAL, "at most 64 variants per interface");
+    Variant v;
+    v.name = name;
+    v.target = target;
+    v.fn = fn;
+    v.ws = ws;
+    v.bound = bound;
+    v.user = user;
+    f->variants.push_back(v);
+    const int id = (int)f->variants.size() - 1;
+    apply_env_to_variant(c, f, id);
+    if (id_out) *id_out = id;
+    c->cache.clear();
+    return CMP_OK;
+}
+
+// Resource restriction and forcing by name (the paper's STARPU_NCUDA /
+// STARPU_NCPU runs, Sec. 3.2): read once at cmp_init, applied to every gemm
+// variant when it registers.
+void read_env(cmp_ctx* c) {
+    if (const char* s = std::getenv("COMPAR_SELECTOR")) {
+        std::string v = s;
+        if (v == "static") c->selector = CMP_SEL_STATIC;
+        else if (v == "nn") c->selector = CMP_SEL_NN;
+        else if (v == "mlp") c->selector = CMP_SEL_MLP;
+    }
+    if (const char* s = std::getenv("COMPAR_VARIANTS")) {
+        c->env_restrict = true;
+        std::stringstream ss(s);
+        std::string tok;
+        while (std::getline(ss, tok, ','))
+            if (!tok.empty()) c->env_allow.push_back(tok);
+    }
+    if (const char* s = std::getenv("COMPAR_FORCE")) c->env_force = s;
+    if (const char* s = std::getenv("COMPAR_FAULT")) {
+        std::string v = s;
+        auto p = v.find(':');
+        if (p != std::string::npos) {
+            c->fault_name = v.substr(0, p);
+            c->fault_every = std::strtoull(v.c_str() + p + 1, nullptr, 10);
+        }
+    }
+}
+
+void apply_env_to_variant(cmp_ctx* c, Interface* f, int id) {
+    if (f->name != kGemm) return;
+    const std::string& n = f->variants[id].name;
+    if (c->env_restrict &&
+        std::find(c->env_allow.begin(), c->env_allow.end(), n) == c->env_allow.end())
+        f->mask &= ~(1ull << id);
+    if (!c->env_force.empty() && n == c->env_force) f->forced = id;
+}
+
+// ---------------------------------------------------------------------------
+// Selection
+
+double tie_key_bound(const Interface& f, int i) { return f.variants[i].bound; }
+
+// argmin of t over the candidate ids; ties -> tighter bound, then lower id.
+int argmin_tiebreak(const Interface& f, const std::vector<int>& cand, const std::vector<double>& t) {
+    int best = -1;
+    for (int i : cand) {
+        if (!std::isfinite(t[i])) continue;
+        if (best < 0 || std::make_tuple(t[i], tie_key_bound(f, i), i) <
+                            std::make_tuple(t[best], tie_key_bound(f, best), best))
+            best = i;
+    }
+    return best;
+}
+
+std::vector<int> admissible_ids(const Interface& f, double tol) {
+    std::vector<int> v;
+    for (size_t i = 0; i < f.variants.size(); ++i)
+        if ((f.mask >> i & 1) && f.variants[i].bound <= tol) v.push_back((int)i);
+    return v;
+}
+
+// Distinct shapes of the history in order of first appearance, with the last
+// recorded median per variant (NaN where none).
+struct ShapeTable {
+    std::vector<std::tuple<int64_t, int64_t, int64_t>> shapes;
+    std::vector<std::vector<double>> med;
+};
+ShapeTable shape_table(const cmp_ctx* c, size_t nvar) {
+    ShapeTable T;
+    std::map<std::tuple<int64_t, int64_t, int64_t>, size_t> idx;
+    for (auto& r : c->history) {
+        auto key = std::make_tuple(r.M, r.N, r.K);
+        auto it = idx.find(key);
+        size_t s;
+        if (it == idx.end()) {
+            s = T.shapes.size();
+            idx[key] = s;
+            T.shapes.push_back(key);
+            T.med.emplace_back(nvar, NAN);
+        } else {
+            s = it->second;
+        }
+        if (r.id >= 0 && (size_t)r.id < nvar) T.med[s][r.id] = r.med;
+    }
+    return T;
+}
+
+int select_static(const cmp_ctx* c, const Interface& f, const std::vector<int>& adm) {
+    ShapeTable T = shape_table(c, f.variants.size());
+    std::vector<double> tot(f.variants.size(), 0.0);
+    size_t used = 0;
+    for (size_t s = 0; s < T.shapes.size(); ++s) {
+        bool complete = true;
+        for (int i : adm)
+            if (!std::isfinite(T.med[s][i])) complete = false;
+        if (!complete) continue;
+        ++used;
+        for (int i : adm) tot[i] += T.med[s][i];
+    }
+    if (used == 0) {
+        std::vector<double> z(f.variants.size(), 0.0);
+        return argmin_tiebreak(f, adm, z);
+    }
+    return argmin_tiebreak(f, adm, tot);
+}
+
+int select_nn(const cmp_ctx* c, const Interface& f, const std::vector<int>& adm, int64_t M,
+              int64_t N, int64_t K) {
+    ShapeTable T = shape_table(c, f.variants.size());
+    const double q0 = std::log2((double)M), q1 = std::log2((double)N), q2 = std::log2((double)K);
+    int best = -1;
+    double bd = 0;
+    for (size_t s = 0; s < T.shapes.size(); ++s) {
+        bool any = false;
+        for (int i : adm)
+            if (std::isfinite(T.med[s][i])) any = true;
+        if (!any) continue;
+        const double d0 = std::log2((double)std::get<0>(T.shapes[s])) - q0;
+        const double d1 = std::log2((double)std::get<1>(T.shapes[s])) - q1;
+        const double d2 = std::log2((double)std::get<2>(T.shapes[s])) - q2;
+        const double d = d0 * d0 + d1 * d1 + d2 * d2;
+        if (best < 0 || d < bd) {
+            best = (int)s;
+            bd = d;
+        }
+    }
+    if (best < 0) return -1;
+    return argmin_tiebreak(f, adm, T.med[best]);
+}
+
+}  // namespace
+
+int mlp_predict(cmp_ctx* c, int n, const float* Xraw, float* Yraw);
+
+namespace {
+
+int do_select_batch(cmp_ctx* c, Interface* f, int n, const cmp_context* q, int* ids) {
+    std::vector<int> pending;
+    for (int r = 0; r < n; ++r) {
+        const cmp_context& x = q[r];
+        if (x.M < 0 || x.N < 0 || x.K < 0) return fail(c, CMP_EINVAL, "negative dimension");
+        if (!(x.tol > 0)) return fail(c, CMP_EINVAL, "tolerance must be > 0");
+        if (x.dtype != CMP_F32) return fail(c, CMP_EUNSUPPORTED, "only CMP_F32 operands are supported");
+        std::vector<int> adm = admissible_ids(*f, x.tol);
+        if (adm.empty())
+            return fail(c, CMP_ENOVARIANT, "no enabled variant meets tol %g", x.tol);
+        if (f->forced >= 0) {
+            if (std::find(adm.begin(), adm.end(), f->forced) == adm.end())
+                return fail(c, CMP_ENOVARIANT, "forced variant %s does not meet tol %g",
+                            f->variants[f->forced].name.c_str(), x.tol);
+            ids[r] = f->forced;
+            continue;
+        }
+        if (adm.size() == 1) {
+            ids[r] = adm[0];
+            continue;
+        }
+        auto it = c->cache.find(CacheKey{x.M, x.N, x.K, x.tol});
+        if (it != c->cache.end()) {
+            ids[r] = it->second;
+            continue;
+        }
+        ids[r] = -1;
+        pending.push_back(r);
+    }
+    if (pending.empty()) return CMP_OK;
+
+    std::vector<float> pred;  // MLP predictions (ln us) for pending rows
+    const bool use_mlp = c->selector == CMP_SEL_MLP && c->mlp_ready && f->name == kGemm && c->gpu;
+    if (use_mlp) {
+        std::vector<float> X(pending.size() * 4);
+        for (size_t p = 0; p < pending.size(); ++p) {
+            const cmp_context& x = q[pending[p]];
+            X[4 * p + 0] = (float)std::log2((double)std::max<int64_t>(x.M, 1));
+            X[4 * p + 1] = (float)std::log2((double)std::max<int64_t>(x.N, 1));
+            X[4 * p + 2] = (float)std::log2((double)std::max<int64_t>(x.K, 1));
+            X[4 * p + 3] = (float)std::log10(x.tol);
+        }
+        pred.resize(pending.size() * 4);
+        int st = mlp_predict(c, (int)pending.size(), X.data(), pred.data());
+        if (st) return st;
+    }
+    for (size_t p = 0; p < pending.size(); ++p) {
+        const cmp_context& x = q[pending[p]];
+        std::vector<int> adm = admissible_ids(*f, x.tol);
+        int id = -1;
+        if (use_mlp) {
+            std::vector<double> t(f->variants.size(), INFINITY);
+            for (int i : adm)
+                if (i < kNumBuiltin) t[i] = pred[4 * p + i];
+            id = argmin_tiebreak(*f, adm, t);
+        }
+        if (id < 0 && c->selector != CMP_SEL_STATIC) id = select_nn(c, *f, adm, x.M, x.N, x.K);
+        if (id < 0) id = select_static(c, *f, adm);
+        if (id < 0) return fail(c, CMP_ENOVARIANT, "selection failed");
+        ids[pending[p]] = id;
+        c->cache[CacheKey{x.M, x.N, x.K, x.tol}] = id;
+    }
+    return CMP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Workspace
+
+int ensure_ws(cmp_ctx* c, size_t need) {
+    if (need <= c->ws_bytes) return CMP_OK;
+    // in-flight work on any stream may still read the old buffer
+    HIP_TRY(c, hipDeviceSynchronize());
+    if (c->ws) HIP_TRY(c, hipFree(c->ws));
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+    size_t sz = std::max<size_t>(need + need / 4, 1 << 20);
+    if (hipMalloc(&c->ws, sz) != hipSuccess) {
+        c->ws = nullptr;
+        (void)hipGetLastError();
+        return fail(c, CMP_ENOMEM, "workspace allocation of %zu bytes failed", sz);
+    }
+    c->ws_bytes = sz;
+    return CMP_OK;
+}
+
+int ensure_vws(cmp_ctx* c, size_t need) {
+    if (need <= c->vws_bytes) return CMP_OK;
+    HIP_TRY(c, hipDeviceSynchronize());
+    if (c->vws) HIP_TRY(c, hipFree(c->vws));
+    c->vws = nullptr;
+    c->vws_bytes = 0;
+    size_t sz = std::max<size_t>(need + need / 4, 1 << 16);
+    if (hipMalloc(&c->vws, sz) != hipSuccess) {
+        c->vws = nullptr;
+        (void)hipGetLastError();
+        return fail(c, CMP_ENOMEM, "verify workspace allocation of %zu bytes failed", sz);
+    }
+    c->vws_bytes = sz;
+    return CMP_OK;
+}
+
+int check_gemm_args(cmp_ctx* c, const cmp_gemm_args* a) {
+    if (!a) return fail(c, CMP_EINVAL, "null args");
+    if (a->M < 0 || a->N < 0 || a->K < 0) return fail(c, CMP_EINVAL, "negative dimension");
+    if (a->M == 0 || a->N == 0) return CMP_OK;
+    if (!a->C) return fail(c, CMP_EINVAL, "null C");
+    if (a->ldc < std::max<int64_t>(a->N, 1)) return fail(c, CMP_EINVAL, "ldc < N");
+    if (a->alpha != 0.f && a->K > 0) {
+        if (!a->A || !a->B) return fail(c, CMP_EINVAL, "null A or B");
+        if (a->lda < std::max<int64_t>(a->K, 1)) return fail(c, CMP_EINVAL, "lda < K");
+        if (a->ldb < std::max<int64_t>(a->N, 1)) return fail(c, CMP_EINVAL, "ldb < N");
+    }
+    if (a->M > (int64_t)1 << 31 || a->N > (int64_t)1 << 31 || a->K > (int64_t)1 << 31)
+        return fail(c, CMP_EINVAL, "dimension above 2^31");
+    return CMP_OK;
+}
+
+int run_variant(cmp_ctx* c, Interface& f, int id, const void* args, void* stream) {
+    Variant& v = f.variants[id];
+    ++v.calls;
+    if (c->fault_every && v.name == c->fault_name && v.calls % c->fault_every == 0)
+        return fail(c, CMP_EHIP, "injected fault in variant %s (call %llu)", v.name.c_str(),
+                    (unsigned long long)v.calls);
+    size_t need = v.ws ? v.ws(args, v.user) : 0;
+    if (need && v.target == CMP_TARGET_HIP) {
+        int st = ensure_ws(c, need);
+        if (st) return st;
+    }
+    int st = v.fn(args, need ? c->ws : nullptr, need, stream, v.user);
+    if (st != CMP_OK) {
+        if (c->last_error.empty() || st == CMP_EHIP) {
+            hipError_t e = hipGetLastError();
+            return fail(c, st, "variant %s failed (%d): %s", v.name.c_str(), st,
+                        e != hipSuccess ? hipGetErrorString(e) : "");
+        }
+        return st;
+    }
+    return CMP_OK;
+}
+
+double verify_threshold(double tol, int64_t M) {
+    // one Rademacher probe: the estimate's relative spread is about 1/sqrt(2M);
+    // allow four standard deviations before calling it a failure
+    return tol * (1.0 + 4.0 / std::sqrt(2.0 * (double)std::max<int64_t>(M, 1)));
+}
+
+// Verify workspace: [y: K doubles | pad] [out: 2 doubles | pad] [x: N doubles]
+// [old C: M x N floats, only when beta != 0]
+struct VLayout {
+    size_t out_d, x_d, c0_b, total_b;
+};
+VLayout vlayout(const cmp_gemm_args* a, bool keep_c0) {
+    VLayout L;
+    L.out_d = (size_t)round_up(a->K + 2, 32);
+    L.x_d = L.out_d + 32;
+    L.c0_b = (size_t)round_up((int64_t)((L.x_d + (size_t)a->N) * 8), 256);
+    L.total_b = L.c0_b + (keep_c0 ? (size_t)a->M * (size_t)a->N * 4 : 0);
+    return L;
+}
+
+int probe(cmp_ctx* c, const cmp_gemm_args* a, const float* c0, const double* x_dev, hipStream_t s,
+          double* est) {
+    const VLayout L = vlayout(a, false);
+    double* base = (double*)c->vws;  // sized by the caller (ensure_vws with vlayout)
+    double* out = base + L.out_d;
+    HIP_TRY(c, cmp::launch_freivalds(a->M, a->N, a->K, a->alpha, a->A, a->lda, a->B, a->ldb,
+                                     a->beta, c0, a->C, a->ldc, x_dev, base, out, s));
+    double h[2];
+    HIP_TRY(c, hipMemcpyAsync(h, out, sizeof h, hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    *est = h[1] > 0 ? std::sqrt(h[0]) / std::sqrt(h[1]) : std::sqrt(h[0]);
+    return CMP_OK;
+}
+
+// Re-select among `allowed` (a subset of the admissible ids) without touching
+// the decision cache or the caller-visible mask / forced state.
+int reselect(cmp_ctx* c, Interface* f, const cmp_context& q, const std::vector<int>& allowed,
+             int* id) {
+    uint64_t m = 0;
+    for (int i : allowed) m |= 1ull << i;
+    const uint64_t saved = f->mask;
+    const int saved_forced = f->forced;
+    auto cache = std::move(c->cache);
+    c->cache.clear();
+    f->mask = m;
+    f->forced = -1;
+    int st = do_select_batch(c, f, 1, &q, id);
+    f->mask = saved;
+    f->forced = saved_forced;
+    c->cache = std::move(cache);
+    return st;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+
+CMP_API const char* cmp_version(void) { return kVersion; }
+
+CMP_API const char* cmp_status_string(int s) {
+    switch (s) {
+        case CMP_OK: return "CMP_OK";
+        case CMP_EINVAL: return "CMP_EINVAL";
+        case CMP_EDUP: return "CMP_EDUP";
+        case CMP_ESIG: return "CMP_ESIG";
+        case CMP_ENOTFOUND: return "CMP_ENOTFOUND";
+        case CMP_ENOVARIANT: return "CMP_ENOVARIANT";
+        case CMP_EUNSUPPORTED: return "CMP_EUNSUPPORTED";
+        case CMP_EHIP: return "CMP_EHIP";
+        case CMP_ENOMEM: return "CMP_ENOMEM";
+        case CMP_ECHECK: return "CMP_ECHECK";
+        case CMP_ENODATA: return "CMP_ENODATA";
+        default: return "unknown status";
+    }
+}
+
+CMP_API int cmp_init(int device, cmp_ctx** out) {
+    if (!out) return CMP_EINVAL;
+    *out = nullptr;
+    cmp_ctx* c = new (std::nothrow) cmp_ctx();
+    if (!c) return CMP_ENOMEM;
+    c->device = device;
+    if (device >= 0) {
+        int n = 0;
+        hipError_t e = hipGetDeviceCount(&n);
+        if (e != hipSuccess || device >= n) {
+            delete c;
+            return CMP_EHIP;
+        }
+        if (hipSetDevice(device) != hipSuccess || hipGetDeviceProperties(&c->props, device) != hipSuccess) {
+            delete c;
+            return CMP_EHIP;
+        }
+        if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return CMP_EHIP;
+        }
+        c->gpu = true;
+    }
+    read_env(c);
+    register_builtins(c);
+    *out = c;
+    return CMP_OK;
+}
+
+CMP_API int cmp_terminate(cmp_ctx* c) {
+    if (!c) return CMP_OK;
+    if (c->gpu) {
+        (void)hipSetDevice(c->device);
+        if (c->side) (void)hipStreamSynchronize(c->side);
+        (void)hipDeviceSynchronize();
+        if (c->ws) (void)hipFree(c->ws);
+        if (c->vws) (void)hipFree(c->vws);
+        if (c->mlp_dev) (void)hipFree(c->mlp_dev);
+        for (auto& k : c->kpending) {
+            (void)hipEventDestroy(k.a);
+            (void)hipEventDestroy(k.b);
+        }
+        for (auto e : c->kpool) (void)hipEventDestroy(e);
+        if (c->side) (void)hipStreamDestroy(c->side);
+    }
+    delete c;
+    return CMP_OK;
+}
+
+CMP_API const char* cmp_last_error(const cmp_ctx* c) { return c ? c->last_error.c_str() : "null context"; }
+
+CMP_API int cmp_device(const cmp_ctx* c, int* device, char* arch, size_t arch_len, int* cus,
+                       int* clock_khz) {
+    if (!c) return CMP_EINVAL;
+    if (device) *device = c->device;
+    if (arch && arch_len) {
+        std::snprintf(arch, arch_len, "%s", c->gpu ? c->props.gcnArchName : "host");
+    }
+    if (cus) *cus = c->gpu ? c->props.multiProcessorCount : 0;
+    if (clock_khz) *clock_khz = c->gpu ? c->props.clockRate : 0;
+    return CMP_OK;
+}
+
+CMP_API int cmp_interface_declare(cmp_ctx* c, const char* iface, int n, const cmp_param_desc* p) {
+    if (!c) return CMP_EINVAL;
+    if (!iface || !*iface) return fail(c, CMP_EINVAL, "null interface name");
+    if (find_iface(c, iface)) return fail(c, CMP_EDUP, "duplicate interface %s", iface);
+    std::vector<Param> v;
+    int st = validate_params(c, n, p, &v);
+    if (st) return st;
+    c->ifaces.push_back(Interface{});
+    c->ifaces.back().name = iface;
+    c->ifaces.back().params = std::move(v);
+    return CMP_OK;
+}
+
+CMP_API int cmp_variant_register(cmp_ctx* c, const char* iface, const char* name, int target,
+                                 int nparams, const cmp_param_desc* params, cmp_variant_fn fn,
+                                 cmp_ws_fn ws, double bound, void* user, int* id_out) {
+    if (!c) return CMP_EINVAL;
+    return register_variant(c, iface, name, target, nparams, params, fn, ws, bound, user, id_out);
+}
+
+CMP_API int cmp_variant_count(cmp_ctx* c, const char* iface, int* n) {
+    if (!c || !n) return CMP_EINVAL;
+    Interface* f = find_iface(c, iface);
+    if (!f) return fail(c, CMP_ENOTFOUND, "unknown interface");
+    *n = (int)f->variants.size();
+    return CMP_OK;
+}
+
+CMP_API int cmp_variant_info(cmp_ctx* c, const char* iface, int id, const char** name, int* target,
+                             double* bound) {
+    if (!c) return CMP_EINVAL;
+    Interface* f = find_iface(c, iface);
+    if (!f) return fail(c, CMP_ENOTFOUND, "unknown interface");
+    if (id < 0 || id >= (int)f->variants.size()) return fail(c, CMP_EINVAL, "bad variant id %d", id);
+    if (name) *name = f->variants[id].name.c_str();
+    if (target) *target = f->variants[id].target;
+    if (bound) *bound = f->variants[id].bound;
+    return CMP_OK;
+}
+
+CMP_API int cmp_variant_find(cmp_ctx* c, const char* iface, const char* name, int* id) {
+    if (!c || !name || !id) return CMP_EINVAL;
+    Interface* f = find_iface(c, iface);
+    if (!f) return fail(c, CMP_ENOTFOUND, "unknown interface");
+    for (size_t i = 0; i < f->variants.size(); ++i)
+        if (f->variants[i].name == name) {
+            *id = (int)i;
+            return CMP_OK;
+        }
+    return fail(c, CMP_ENOTFOUND, "no variant %s", name);
+}
+
+CMP_API int cmp_set_variant_mask(cmp_ctx* c, const char* iface, uint64_t mask) {
+    if (!c) return CMP_EINVAL;
+    Interface* f = find_iface(c, iface);
+    if (!f) return fail(c, CMP_ENOTFOUND, "unknown interface");
+    f->mask = mask;
+    c->cache.clear();
+    return CMP_OK;
+}
+
+CMP_API int cmp_force_variant(cmp_ctx* c, const char* iface, int id) {
+    if (!c) return CMP_EINVAL;
+    Interface* f = find_iface(c, iface);
+    if (!f) return fail(c, CMP_ENOTFOUND, "unknown interface");
+    if (id >= (int)f->variants.size()) return fail(c, CMP_EINVAL, "bad variant id %d", id);
+    f->forced = id < 0 ? -1 : id;
+    return CMP_OK;
+}
+
+CMP_API int cmp_selector_set(cmp_ctx* c, int kind) {
+    if (!c) return CMP_EINVAL;
+    if (kind < CMP_SEL_STATIC || kind > CMP_SEL_MLP) return fail(c, CMP_EINVAL, "unknown selector");
+    c->selector = kind;
+    c->cache.clear();
+    return CMP_OK;
+}
+
+CMP_API int cmp_set_flags(cmp_ctx* c, uint32_t flags) {
+    if (!c) return CMP_EINVAL;
+    c->flags = flags;
+    return CMP_OK;
+}
+
+CMP_API int cmp_admissible(cmp_ctx* c, const char* iface, const cmp_context* q, uint64_t* mask) {
+    if (!c || !q || !mask) return CMP_EINVAL;
+    Interface* f = find_iface(c, iface);
+    if (!f) return fail(c, CMP_ENOTFOUND, "unknown interface");
+    if (!(q->tol > 0)) return fail(c, CMP_EINVAL, "tolerance must be > 0");
+    uint64_t m = 0;
+    for (int i : admissible_ids(*f, q->tol)) m |= 1ull << i;
+    *mask = m;
+    return CMP_OK;
+}
+
+CMP_API int cmp_select(cmp_ctx* c, const char* iface, const cmp_context* q, int* id) {
+    if (!c || !q || !id) return CMP_EINVAL;
+    Interface* f = find_iface(c, iface);
+    if (!f) return fail(c, CMP_ENOTFOUND, "unknown interface");
+    return do_select_batch(c, f, 1, q, id);
+}
+
+CMP_API int cmp_select_batch(cmp_ctx* c, const char* iface, int n, const cmp_context* q, int* ids) {
+    if (!c || n < 0 || (n > 0 && (!q || !ids))) return CMP_EINVAL;
+    Interface* f = find_iface(c, iface);
+    if (!f) return fail(c, CMP_ENOTFOUND, "unknown interface");
+    return do_select_batch(c, f, n, q, ids);
+}
+
+CMP_API int cmp_gemm_variant(cmp_ctx* c, int id, const cmp_gemm_args* a, void* stream) {
+    if (!c) return CMP_EINVAL;
+    Interface* f = find_iface(c, kGemm);
+    int st = check_gemm_args(c, a);
+    if (st) return st;
+    if (id < 0 || id >= (int)f->variants.size()) return fail(c, CMP_EINVAL, "bad variant id %d", id);
+    if (f->variants[id].target == CMP_TARGET_HIP && !c->gpu)
+        return fail(c, CMP_EUNSUPPORTED, "HIP variant on a host-only context");
+    return run_variant(c, *f, id, a, stream);
+}
+
+CMP_API int cmp_call_host(cmp_ctx* c, const char* iface, int id, const void* args) {
+    if (!c) return CMP_EINVAL;
+    Interface* f = find_iface(c, iface);
+    if (!f) return fail(c, CMP_ENOTFOUND, "unknown interface");
+    if (id < 0 || id >= (int)f->variants.size()) return fail(c, CMP_EINVAL, "bad variant id %d", id);
+    if (f->variants[id].target != CMP_TARGET_HOST) return fail(c, CMP_EINVAL, "not a host variant");
+    return run_variant(c, *f, id, args, nullptr);
+}
+
+CMP_API int cmp_gemm(cmp_ctx* c, const cmp_gemm_args* a, double tol, void* stream, int* chosen) {
+    if (!c) return CMP_EINVAL;
+    int st = check_gemm_args(c, a);
+    if (st) return st;
+    if (!(tol > 0)) return fail(c, CMP_EINVAL, "tolerance must be > 0");
+    Interface* f = find_iface(c, kGemm);
+    const cmp_context q{a->M, a->N, a->K, CMP_F32, tol};
+    int id = -1;
+    st = do_select_batch(c, f, 1, &q, &id);
+    if (st) return st;
+    const bool verify = (c->flags & CMP_FLAG_VERIFY) && c->gpu && a->M > 0 && a->N > 0;
+    auto s = (hipStream_t)stream;
+    float* c0 = nullptr;
+    double* xdev = nullptr;
+    auto restore_c = [&]() -> int {
+        if (c0)
+            HIP_TRY(c, hipMemcpy2DAsync(a->C, (size_t)a->ldc * 4, c0, (size_t)a->N * 4,
+                                        (size_t)a->N * 4, (size_t)a->M, hipMemcpyDeviceToDevice, s));
+        return CMP_OK;
+    };
+    if (verify) {
+        // keep the old C when beta != 0: the probe and a re-run both need it
+        const VLayout L = vlayout(a, a->beta != 0.f);
+        st = ensure_vws(c, L.total_b);
+        if (st) return st;
+        xdev = (double*)c->vws + L.x_d;
+        if (a->beta != 0.f) {
+            c0 = (float*)((char*)c->vws + L.c0_b);
+            HIP_TRY(c, hipMemcpy2DAsync(c0, (size_t)a->N * 4, a->C, (size_t)a->ldc * 4,
+                                        (size_t)a->N * 4, (size_t)a->M, hipMemcpyDeviceToDevice, s));
+        }
+        HIP_TRY(c, cmp::launch_rademacher(a->N, 0x5eedull + c->verify_calls++, xdev, s));
+    }
+    st = run_variant(c, *f, id, a, stream);
+    if (st != CMP_OK && st != CMP_EINVAL) {
+        // a failing variant gets one fallback: the best other admissible variant
+        std::vector<int> rest;
+        for (int i : admissible_ids(*f, tol))
+            if (i != id) rest.push_back(i);
+        if (rest.empty()) return st;
+        int id2 = -1;
+        if ((st = reselect(c, f, q, rest, &id2))) return st;
+        ++c->fallbacks;
+        if ((st = restore_c())) return st;
+        if ((st = run_variant(c, *f, id2, a, stream))) return st;
+        id = id2;
+    }
+    if (verify) {
+        double est = 0;
+        if ((st = probe(c, a, c0, xdev, s, &est))) return st;
+        c->last_verify = est;
+        if (est > verify_threshold(tol, a->M)) {
+            // rerun once with the best admissible variant of strictly tighter bound
+            const double b = f->variants[id].bound;
+            std::vector<int> tighter;
+            for (int i : admissible_ids(*f, tol))
+                if (f->variants[i].bound < b) tighter.push_back(i);
+            if (tighter.empty())
+                return fail(c, CMP_ECHECK, "residual probe %.3g exceeds tol %g (variant %s)", est,
+                            tol, f->variants[id].name.c_str());
+            int id2 = -1;
+            if ((st = reselect(c, f, q, tighter, &id2))) return st;
+            ++c->fallbacks;
+            if ((st = restore_c())) return st;
+            if ((st = run_variant(c, *f, id2, a, stream))) return st;
+            id = id2;
+            if ((st = probe(c, a, c0, xdev, s, &est))) return st;
+            c->last_verify = est;
+            if (est > verify_threshold(tol, a->M))
+                return fail(c, CMP_ECHECK, "residual probe %.3g exceeds tol %g after fallback", est, tol);
+        }
+    }
+    if (chosen) *chosen = id;
+    return CMP_OK;
+}
+
+CMP_API int cmp_time_variant(cmp_ctx* c, int id, const cmp_gemm_args* a, int warmup, int reps,
+                             void* stream, float* med, float* mn, float* mean) {
+    if (!c) return CMP_EINVAL;
+    if (reps < 1 || warmup < 0) return fail(c, CMP_EINVAL, "reps must be >= 1");
+    Interface* f = find_iface(c, kGemm);
+    int st = check_gemm_args(c, a);
+    if (st) return st;
+    if (id < 0 || id >= (int)f->variants.size()) return fail(c, CMP_EINVAL, "bad variant id %d", id);
+    const bool host = f->variants[id].target == CMP_TARGET_HOST;
+    if (!host && !c->gpu) return fail(c, CMP_EUNSUPPORTED, "HIP variant on a host-only context");
+    auto s = (hipStream_t)stream;
+    for (int w = 0; w < warmup; ++w)
+        if ((st = run_variant(c, *f, id, a, stream))) return st;
+    std::vector<float> t(reps);
+    if (host) {
+        for (int r = 0; r < reps; ++r) {
+            auto t0 = std::chrono::steady_clock::now();
+            if ((st = run_variant(c, *f, id, a, stream))) return st;
+            auto t1 = std::chrono::steady_clock::now();
+            t[r] = std::chrono::duration<float, std::milli>(t1 - t0).count();
+        }
+    } else {
+        std::vector<hipEvent_t> ev(2 * reps);
+        for (auto& e : ev) HIP_TRY(c, hipEventCreate(&e));
+        int rst = CMP_OK;
+        for (int r = 0; r < reps && !rst; ++r) {
+            (void)hipEventRecord(ev[2 * r], s);
+            rst = run_variant(c, *f, id, a, stream);
+            (void)hipEventRecord(ev[2 * r + 1], s);
+        }
+        hipError_t se = hipStreamSynchronize(s);
+        for (int r = 0; r < reps && !rst && se == hipSuccess; ++r)
+            (void)hipEventElapsedTime(&t[r], ev[2 * r], ev[2 * r + 1]);
+        for (auto& e : ev) (void)hipEventDestroy(e);
+        if (rst) return rst;
+        if (se != hipSuccess) return hip_fail(c, se, "hipStreamSynchronize");
+    }
+    std::vector<float> srt = t;
+    std::sort(srt.begin(), srt.end());
+    const float m = (reps % 2) ? srt[reps / 2] : 0.5f * (srt[reps / 2 - 1] + srt[reps / 2]);
+    double sum = 0;
+    for (float v : t) sum += v;
+    if (med) *med = m;
+    if (mn) *mn = srt[0];
+    if (mean) *mean = (float)(sum / reps);
+    return CMP_OK;
+}
+
+CMP_API int cmp_history_add(cmp_ctx* c, int64_t M, int64_t N, int64_t K, int id, int reps, float med,
+                            float mn, float mean) {
+    if (!c) return CMP_EINVAL;
+    Interface* f = find_iface(c, kGemm);
+    if (M <= 0 || N <= 0 || K <= 0) return fail(c, CMP_EINVAL, "history shape must be positive");
+    if (id < 0 || id >= (int)f->variants.size()) return fail(c, CMP_EINVAL, "bad variant id %d", id);
+    if (!(med > 0) || !std::isfinite(med)) return fail(c, CMP_EINVAL, "median must be > 0");
+    c->history.push_back(HistRow{M, N, K, id, reps, med, mn, mean});
+    c->cache.clear();
+    return CMP_OK;
+}
+
+CMP_API int cmp_calibrate(cmp_ctx* c, int nshapes, const int64_t* mnk, const float* A,
+                          const float* B, float* C, int warmup, int reps, void* stream) {
+    if (!c) return CMP_EINVAL;
+    if (nshapes < 0 || (nshapes > 0 && !mnk)) return fail(c, CMP_EINVAL, "bad shape list");
+    Interface* f = find_iface(c, kGemm);
+    std::map<std::tuple<int64_t, int64_t, int64_t, int>, bool> have;
+    for (auto& r : c->history) have[std::make_tuple(r.M, r.N, r.K, r.id)] = true;
+    for (int s = 0; s < nshapes; ++s) {
+        cmp_gemm_args a{};
+        a.M = mnk[3 * s];
+        a.N = mnk[3 * s + 1];
+        a.K = mnk[3 * s + 2];
+        a.lda = a.K;
+        a.ldb = a.N;
+        a.ldc = a.N;
+        a.alpha = 1.f;
+        a.beta = 0.f;
+        a.A = A;
+        a.B = B;
+        a.C = C;
+        if (a.M <= 0 || a.N <= 0 || a.K <= 0) return fail(c, CMP_EINVAL, "calibration shape must be positive");
+        for (size_t v = 0; v < f->variants.size(); ++v) {
+            if (!(f->mask >> v & 1)) continue;
+            if (have.count(std::make_tuple(a.M, a.N, a.K, (int)v))) continue;
+            float med, mn, mean;
+            int st = cmp_time_variant(c, (int)v, &a, warmup, reps, stream, &med, &mn, &mean);
+            if (st) return st;
+            c->history.push_back(HistRow{a.M, a.N, a.K, (int)v, reps, med, mn, mean});
+        }
+    }
+    c->cache.clear();
+    return CMP_OK;
+}
+
+CMP_API int cmp_history_count(cmp_ctx* c, int* n) {
+    if (!c || !n) return CMP_EINVAL;
+    *n = (int)c->history.size();
+    return CMP_OK;
+}
+
+CMP_API int cmp_history_get(cmp_ctx* c, int row, int64_t* mnk, int* id, int* reps, float* med,
+                            float* mn, float* mean) {
+    if (!c) return CMP_EINVAL;
+    if (row < 0 || row >= (int)c->history.size()) return fail(c, CMP_EINVAL, "bad history row");
+    const HistRow& r = c->history[row];
+    if (mnk) {
+        mnk[0] = r.M;
+        mnk[1] = r.N;
+        mnk[2] = r.K;
+    }
+    if (id) *id = r.id;
+    if (reps) *reps = r.reps;
+    if (med) *med = r.med;
+    if (mn) *mn = r.mn;
+    if (mean) *mean = r.mean;
+    return CMP_OK;
+}
+
+CMP_API int cmp_history_clear(cmp_ctx* c) {
+    if (!c) return CMP_EINVAL;
+    c->history.clear();
+    c->cache.clear();
+    return CMP_OK;
+}
+
+namespace {
+std::string device_signature(const cmp_ctx* c) {
+    char buf[256];
+    if (c->gpu)
+        std::snprintf(buf, sizeof buf, "arch=%s cus=%d clock_khz=%d", c->props.gcnArchName,
+                      c->props.multiProcessorCount, c->props.clockRate);
+    else
+        std::snprintf(buf, sizeof buf, "arch=host cus=0 clock_khz=0");
+    return buf;
+}
+}  // namespace
+
+CMP_API int cmp_history_save(cmp_ctx* c, const char* path) {
+    if (!c || !path) return CMP_EINVAL;
+    Interface* f = find_iface(c, kGemm);
+    std::ofstream o(path);
+    if (!o) return fail(c, CMP_EINVAL, "cannot open %s", path);
+    o << "# compar-history v1\n";
+    o << "# device " << device_signature(c) << "\n";
+    o << "# lib " << kVersion << "\n";
+    o << "# M N K variant reps median_ms min_ms mean_ms\n";
+    char line[256];
+    for (auto& r : c->history) {
+        std::snprintf(line, sizeof line, "%lld %lld %lld %s %d %.9g %.9g %.9g\n", (long long)r.M,
+                      (long long)r.N, (long long)r.K, f->variants[r.id].name.c_str(), r.reps, r.med,
+                      r.mn, r.mean);
+        o << line;
+    }
+    if (!o) return fail(c, CMP_EINVAL, "write to %s failed", path);
+    return CMP_OK;
+}
+
+CMP_API int cmp_history_load(cmp_ctx* c, const char* path, int force) {
+    if (!c || !path) return CMP_EINVAL;
+    Interface* f = find_iface(c, kGemm);
+    std::ifstream in(path);
+    if (!in) return fail(c, CMP_EINVAL, "cannot open %s", path);
+    std::string line;
+    std::vector<HistRow> rows;
+    bool header = false;
+    while (std::getline(in, line)) {
+        if (line.empty()) continue;
+        if (line[0] == '#') {
+            if (line.rfind("# compar-history v1", 0) == 0) header = true;
+            if (line.rfind("# device ", 0) == 0 && !force) {
+                std::string sig = line.substr(9);
+                if (sig != device_signature(c))
+                    return fail(c, CMP_EINVAL, "history recorded on '%s', this device is '%s'",
+                                sig.c_str(), device_signature(c).c_str());
+            }
+            continue;
+        }
+        std::istringstream ss(line);
+        long long M, N, K;
+        std::string name;
+        HistRow r{};
+        if (!(ss >> M >> N >> K >> name >> r.reps >> r.med >> r.mn >> r.mean))
+            return fail(c, CMP_EINVAL, "malformed history line: %s", line.c_str());
+        r.M = M;
+        r.N = N;
+        r.K = K;
+        r.id = -1;
+        for (size_t i = 0; i < f->variants.size(); ++i)
+            if (f->variants[i].name == name) r.id = (int)i;
+        if (r.id < 0) {
+            if (force) continue;
+            return fail(c, CMP_ENOTFOUND, "history names unknown variant %s", name.c_str());
+        }
+        rows.push_back(r);
+    }
+    if (!header) return fail(c, CMP_EINVAL, "%s is not a compar history file", path);
+    c->history.insert(c->history.end(), rows.begin(), rows.end());
+    c->cache.clear();
+    return CMP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Learned selector
+
+namespace {
+
+constexpr int kMlpP = cmp::kMlpParams;
+
+// device block: params | m | v | X | Y | loss(steps) | grad | infer-out
+struct MlpDev {
+    float *params, *m, *v, *X, *Y, *grad, *part;
+};
+
+int mlp_dev(cmp_ctx* c, MlpDev* d) {
+    if (!c->gpu) return fail(c, CMP_EUNSUPPORTED, "learned selector needs a GPU context");
+    const size_t floats =
+        3 * (size_t)kMlpP + 2 * 4 * (size_t)cmp::kMlpMaxRows + kMlpP + (size_t)cmp::kMlpPartFloats;
+    if (!c->mlp_dev) {
+        if (hipMalloc(&c->mlp_dev, floats * sizeof(float)) != hipSuccess) {
+            c->mlp_dev = nullptr;
+            (void)hipGetLastError();
+            return fail(c, CMP_ENOMEM, "network buffers");
+        }
+    }
+    d->params = c->mlp_dev;
+    d->m = d->params + kMlpP;
+    d->v = d->m + kMlpP;
+    d->X = d->v + kMlpP;
+    d->Y = d->X + 4 * cmp::kMlpMaxRows;
+    d->grad = d->Y + 4 * cmp::kMlpMaxRows;
+    d->part = d->grad + kMlpP;
+    return CMP_OK;
+}
+
+void stats(const float* X, int n, float* mu, float* sd) {
+    for (int j = 0; j < 4; ++j) {
+        double s = 0;
+        for (int i = 0; i < n; ++i) s += X[4 * i + j];
+        const double m = s / n;
+        double q = 0;
+        for (int i = 0; i < n; ++i) q += ((double)X[4 * i + j] - m) * ((double)X[4 * i + j] - m);
+        const double d = std::sqrt(q / n);
+        mu[j] = (float)m;
+        sd[j] = d > 0 ? (float)d : 1.f;
+    }
+}
+
+}  // namespace
+
+int mlp_predict(cmp_ctx* c, int n, const float* Xraw, float* Yraw) {
+    MlpDev d;
+    int st = mlp_dev(c, &d);
+    if (st) return st;
+    if (c->mlp_params.size() != (size_t)kMlpP) return fail(c, CMP_ENODATA, "network has no parameters");
+    HIP_TRY(c, hipMemcpyAsync(d.params, c->mlp_params.data(), kMlpP * 4, hipMemcpyHostToDevice, c->side));
+    for (int off = 0; off < n; off += cmp::kMlpMaxRows) {
+        const int cnt = std::min(n - off, cmp::kMlpMaxRows);
+        std::vector<float> Xs(4 * (size_t)cnt);
+        for (int i = 0; i < cnt; ++i)
+            for (int j = 0; j < 4; ++j)
+                Xs[4 * i + j] = (Xraw[4 * (size_t)(off + i) + j] - c->mu_x[j]) / c->sd_x[j];
+        HIP_TRY(c, hipMemcpyAsync(d.X, Xs.data(), Xs.size() * 4, hipMemcpyHostToDevice, c->side));
+        HIP_TRY(c, cmp::launch_mlp_infer(cnt, d.X, d.params, d.Y, c->side));
+        HIP_TRY(c, hipMemcpyAsync(Yraw + 4 * (size_t)off, d.Y, 4 * (size_t)cnt * 4,
+                                  hipMemcpyDeviceToHost, c->side));
+        HIP_TRY(c, hipStreamSynchronize(c->side));
+        for (int i = 0; i < cnt; ++i)
+            for (int j = 0; j < 4; ++j) {
+                float& y = Yraw[4 * (size_t)(off + i) + j];
+                y = y * c->sd_y[j] + c->mu_y[j];
+            }
+    }
+    return CMP_OK;
+}
+
+CMP_API int cmp_mlp_param_count(void) { return kMlpP; }
+
+CMP_API int cmp_mlp_set_params(cmp_ctx* c, const float* p, int n) {
+    if (!c || !p) return CMP_EINVAL;
+    if (n != kMlpP) return fail(c, CMP_EINVAL, "expected %d parameters", kMlpP);
+    c->mlp_params.assign(p, p + n);
+    c->mlp_ready = true;
+    c->cache.clear();
+    return CMP_OK;
+}
+
+CMP_API int cmp_mlp_get_params(cmp_ctx* c, float* p, int n) {
+    if (!c || !p) return CMP_EINVAL;
+    if (n != kMlpP) return fail(c, CMP_EINVAL, "expected %d parameters", kMlpP);
+    if (c->mlp_params.size() != (size_t)kMlpP) return fail(c, CMP_ENODATA, "network has no parameters");
+    std::copy(c->mlp_params.begin(), c->mlp_params.end(), p);
+    return CMP_OK;
+}
+
+CMP_API int cmp_mlp_set_norm(cmp_ctx* c, const float* mx, const float* sx, const float* my,
+                             const float* sy) {
+    if (!c || !mx || !sx || !my || !sy) return CMP_EINVAL;
+    for (int j = 0; j < 4; ++j)
+        if (!(sx[j] > 0) || !(sy[j] > 0)) return fail(c, CMP_EINVAL, "deviations must be > 0");
+    std::copy(mx, mx + 4, c->mu_x);
+    std::copy(sx, sx + 4, c->sd_x);
+    std::copy(my, my + 4, c->mu_y);
+    std::copy(sy, sy + 4, c->sd_y);
+    c->cache.clear();
+    return CMP_OK;
+}
+
+CMP_API int cmp_mlp_get_norm(cmp_ctx* c, float* mx, float* sx, float* my, float* sy) {
+    if (!c || !mx || !sx || !my || !sy) return CMP_EINVAL;
+    std::copy(c->mu_x, c->mu_x + 4, mx);
+    std::copy(c->sd_x, c->sd_x + 4, sx);
+    std::copy(c->mu_y, c->mu_y + 4, my);
+    std::copy(c->sd_y, c->sd_y + 4, sy);
+    return CMP_OK;
+}
+
+CMP_API int cmp_mlp_train(cmp_ctx* c, int n, const float* X, const float* Y, int steps, float lr,
+                          float* loss_trace) {
+    if (!c || !X || !Y) return CMP_EINVAL;
+    if (n < 1 || n > cmp::kMlpMaxRows) return fail(c, CMP_EINVAL, "n must be 1..%d", cmp::kMlpMaxRows);
+    if (steps < 0 || !(lr > 0)) return fail(c, CMP_EINVAL, "bad steps or lr");
+    if (c->mlp_params.size() != (size_t)kMlpP) return fail(c, CMP_ENODATA, "set initial parameters first");
+    MlpDev d;
+    int st = mlp_dev(c, &d);
+    if (st) return st;
+    stats(X, n, c->mu_x, c->sd_x);
+    stats(Y, n, c->mu_y, c->sd_y);
+    std::vector<float> Xs(4 * (size_t)n), Ys(4 * (size_t)n);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < 4; ++j) {
+            Xs[4 * i + j] = (X[4 * i + j] - c->mu_x[j]) / c->sd_x[j];
+            Ys[4 * i + j] = (Y[4 * i + j] - c->mu_y[j]) / c->sd_y[j];
+        }
+    float* loss_dev = nullptr;
+    if (steps > 0) HIP_TRY(c, hipMalloc(&loss_dev, (size_t)steps * 4));
+    auto cleanup = [&]() {
+        if (loss_dev) (void)hipFree(loss_dev);
+    };
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = hipMemcpyAsync(d.params, c->mlp_params.data(), kMlpP * 4, hipMemcpyHostToDevice, c->side);
+    if (e == hipSuccess) e = hipMemcpyAsync(d.X, Xs.data(), Xs.size() * 4, hipMemcpyHostToDevice, c->side);
+    if (e == hipSuccess) e = hipMemcpyAsync(d.Y, Ys.data(), Ys.size() * 4, hipMemcpyHostToDevice, c->side);
+    if (e == hipSuccess) e = cmp::launch_mlp_train(n, d.X, d.Y, d.params, d.m, d.v, d.part, steps, 0, lr, loss_dev, nullptr, c->side);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->mlp_params.data(), d.params, kMlpP * 4, hipMemcpyDeviceToHost, c->side);
+    if (e == hipSuccess && loss_trace && steps > 0)
+        e = hipMemcpyAsync(loss_trace, loss_dev, (size_t)steps * 4, hipMemcpyDeviceToHost, c->side);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->side);
+    cleanup();
+    if (e != hipSuccess) return hip_fail(c, e, "network training");
+    c->mlp_ready = true;
+    c->cache.clear();
+    return CMP_OK;
+}
+
+CMP_API int cmp_mlp_grad(cmp_ctx* c, int n, const float* Xs, const float* Ys, float* loss,
+                         float* grad) {
+    if (!c || !Xs || !Ys || !grad) return CMP_EINVAL;
+    if (n < 1 || n > cmp::kMlpMaxRows) return fail(c, CMP_EINVAL, "n must be 1..%d", cmp::kMlpMaxRows);
+    if (c->mlp_params.size() != (size_t)kMlpP) return fail(c, CMP_ENODATA, "set parameters first");
+    MlpDev d;
+    int st = mlp_dev(c, &d);
+    if (st) return st;
+    float* scratch = nullptr;  // one float: the loss
+    HIP_TRY(c, hipMalloc(&scratch, 4));
+    hipError_t e = hipMemcpyAsync(d.params, c->mlp_params.data(), kMlpP * 4, hipMemcpyHostToDevice, c->side);
+    if (e == hipSuccess) e = hipMemcpyAsync(d.X, Xs, 4 * (size_t)n * 4, hipMemcpyHostToDevice, c->side);
+    if (e == hipSuccess) e = hipMemcpyAsync(d.Y, Ys, 4 * (size_t)n * 4, hipMemcpyHostToDevice, c->side);
+    if (e == hipSuccess) e = cmp::launch_mlp_train(n, d.X, d.Y, d.params, d.m, d.v, d.part, 0, 0, 0.f, scratch, d.grad, c->side);
+    if (e == hipSuccess) e = hipMemcpyAsync(grad, d.grad, kMlpP * 4, hipMemcpyDeviceToHost, c->side);
+    float h = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, scratch, 4, hipMemcpyDeviceToHost, c->side);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->side);
+    (void)hipFree(scratch);
+    if (e != hipSuccess) return hip_fail(c, e, "network gradient");
+    if (loss) *loss = h;
+    return CMP_OK;
+}
+
+CMP_API int cmp_mlp_infer(cmp_ctx* c, int n, const float* Xs, float* Yout) {
+    if (!c || !Xs || !Yout) return CMP_EINVAL;
+    if (n < 0) return fail(c, CMP_EINVAL, "n must be >= 0");
+    if (c->mlp_params.size() != (size_t)kMlpP) return fail(c, CMP_ENODATA, "set parameters first");
+    MlpDev d;
+    int st = mlp_dev(c, &d);
+    if (st) return st;
+    HIP_TRY(c, hipMemcpyAsync(d.params, c->mlp_params.data(), kMlpP * 4, hipMemcpyHostToDevice, c->side));
+    for (int off = 0; off < n; off += cmp::kMlpMaxRows) {
+        const int cnt = std::min(n - off, cmp::kMlpMaxRows);
+        HIP_TRY(c, hipMemcpyAsync(d.X, Xs + 4 * (size_t)off, 4 * (size_t)cnt * 4, hipMemcpyHostToDevice, c->side));
+        HIP_TRY(c, cmp::launch_mlp_infer(cnt, d.X, d.params, d.Y, c->side));
+        HIP_TRY(c, hipMemcpyAsync(Yout + 4 * (size_t)off, d.Y, 4 * (size_t)cnt * 4, hipMemcpyDeviceToHost, c->side));
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->side));
+    return CMP_OK;
+}
+
+CMP_API int cmp_mlp_fit_history(cmp_ctx* c, int steps, float lr, uint64_t seed, float* final_loss) {
+    if (!c) return CMP_EINVAL;
+    if (!c->gpu) return fail(c, CMP_EUNSUPPORTED, "learned selector needs a GPU context");
+    Interface* f = find_iface(c, kGemm);
+    if ((int)f->variants.size() < kNumBuiltin) return fail(c, CMP_ENODATA, "built-in variants missing");
+    ShapeTable T = shape_table(c, f->variants.size());
+    std::vector<float> X, Y;
+    int n = 0;
+    for (size_t s = 0; s < T.shapes.size() && n < cmp::kMlpMaxRows; ++s) {
+        bool complete = true;
+        for (int i = 0; i < kNumBuiltin; ++i)
+            if (!std::isfinite(T.med[s][i])) complete = false;
+        if (!complete) continue;
+        const double tol = kTolClasses[splitmix64_at(seed, (uint64_t)n) % 3];
+        X.push_back((float)std::log2((double)std::get<0>(T.shapes[s])));
+        X.push_back((float)std::log2((double)std::get<1>(T.shapes[s])));
+        X.push_back((float)std::log2((double)std::get<2>(T.shapes[s])));
+        X.push_back((float)std::log10(tol));
+        for (int i = 0; i < kNumBuiltin; ++i) Y.push_back((float)std::log(T.med[s][i] * 1000.0));
+        ++n;
+    }
+    if (n < 2) return fail(c, CMP_ENODATA, "history holds fewer than 2 fully timed shapes");
+    // Kaiming-uniform initialisation from splitmix64(seed ^ golden)
+    std::vector<float> p;
+    const int sizes[4] = {4, 64, 64, 4};
+    uint64_t j = 0;
+    const uint64_t s2 = seed ^ 0x9e3779b97f4a7c15ull;
+    for (int l = 0; l < 3; ++l) {
+        const int fi = sizes[l], fo = sizes[l + 1];
+        const double wb = std::sqrt(6.0 / fi), bb = 1.0 / std::sqrt((double)fi);
+        for (int i = 0; i < fo * fi; ++i) p.push_back((float)((2 * u01(splitmix64_at(s2, j++)) - 1) * wb));
+        for (int i = 0; i < fo; ++i) p.push_back((float)((2 * u01(splitmix64_at(s2, j++)) - 1) * bb));
+    }
+    c->mlp_params = p;
+    std::vector<float> trace(std::max(steps, 1));
+    int st = cmp_mlp_train(c, n, X.data(), Y.data(), steps, lr, trace.data());
+    if (st) return st;
+    if (final_loss) *final_loss = steps > 0 ? trace[steps - 1] : 0.f;
+    return CMP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Verification and pre-pass entry points
+
+CMP_API int cmp_freivalds(cmp_ctx* c, const cmp_gemm_args* a, const float* c0, const double* x,
+                          void* stream, double* est) {
+    if (!c || !est || !x) return CMP_EINVAL;
+    if (!c->gpu) return fail(c, CMP_EUNSUPPORTED, "needs a GPU context");
+    int st = check_gemm_args(c, a);
+    if (st) return st;
+    if (a->M == 0 || a->N == 0) {
+        *est = 0;
+        return CMP_OK;
+    }
+    if (a->beta != 0.f && !c0) return fail(c, CMP_EINVAL, "beta != 0 needs the old C");
+    auto s = (hipStream_t)stream;
+    const VLayout L = vlayout(a, false);
+    st = ensure_vws(c, L.total_b);
+    if (st) return st;
+    double* xdev = (double*)c->vws + L.x_d;
+    HIP_TRY(c, hipMemcpyAsync(xdev, x, (size_t)a->N * 8, hipMemcpyHostToDevice, s));
+    return probe(c, a, c0, xdev, s, est);
+}
+
+CMP_API int cmp_last_verify(cmp_ctx* c, double* est, int* fallbacks) {
+    if (!c) return CMP_EINVAL;
+    if (est) *est = c->last_verify;
+    if (fallbacks) *fallbacks = c->fallbacks;
+    return CMP_OK;
+}
+
+CMP_API int cmp_split_bf16(cmp_ctx* c, int64_t rows, int64_t cols, const float* X, int64_t ldx,
+                           uint16_t* hi, uint16_t* lo, void* stream) {
+    if (!c) return CMP_EINVAL;
+    if (!c->gpu) return fail(c, CMP_EUNSUPPORTED, "needs a GPU context");
+    if (rows < 0 || cols < 0 || ldx < std::max<int64_t>(cols, 1)) return fail(c, CMP_EINVAL, "bad shape");
+    if (rows == 0 || cols == 0) return CMP_OK;
+    if (!X || !hi) return fail(c, CMP_EINVAL, "null pointer");
+    HIP_TRY(c, cmp::launch_split_bf16_plain(rows, cols, X, ldx, hi, lo, (hipStream_t)stream));
+    return CMP_OK;
+}
+
+CMP_API int cmp_quant_fp8(cmp_ctx* c, int64_t rows, int64_t cols, const float* X, int64_t ldx,
+                          uint8_t* q, uint8_t* qs, uint8_t* rq, uint8_t* rs, void* stream) {
+    if (!c) return CMP_EINVAL;
+    if (!c->gpu) return fail(c, CMP_EUNSUPPORTED, "needs a GPU context");
+    if (rows < 0 || cols < 0 || ldx < std::max<int64_t>(cols, 1)) return fail(c, CMP_EINVAL, "bad shape");
+    if (rows == 0 || cols == 0) return CMP_OK;
+    if (!X || !q || !qs || !rq || !rs) return fail(c, CMP_EINVAL, "null pointer");
+    if ((rows % 128) || (cols % 128)) {
+        // outputs are tight: the kernel writes whole 128 x 128 tiles, so ragged
+        // extents go through a padded staging image in the workspace
+        const int64_t rp = round_up(rows, 128), cp = round_up(cols, 128);
+        const size_t need = 2 * (size_t)rp * cp + 2 * (size_t)(rp / 128) * (cp / 128);
+        int st = ensure_ws(c, need);
+        if (st) return st;
+        auto* q2 = (uint8_t*)c->ws;
+        auto* r2 = q2 + (size_t)rp * cp;
+        auto* s1 = r2 + (size_t)rp * cp;
+        auto* s2 = s1 + (size_t)(rp / 128) * (cp / 128);
+        auto s = (hipStream_t)stream;
+        HIP_TRY(c, cmp::launch_quant_fp8(rows, cols, X, ldx, false, rp, cp, q2, s1, r2, s2, s));
+        HIP_TRY(c, hipMemcpy2DAsync(q, cols, q2, cp, cols, rows, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(c, hipMemcpy2DAsync(rq, cols, r2, cp, cols, rows, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(c, hipMemcpyAsync(qs, s1, (size_t)(rp / 128) * (cp / 128), hipMemcpyDeviceToDevice, s));
+        HIP_TRY(c, hipMemcpyAsync(rs, s2, (size_t)(rp / 128) * (cp / 128), hipMemcpyDeviceToDevice, s));
+        return CMP_OK;
+    }
+    HIP_TRY(c, cmp::launch_quant_fp8(rows, cols, X, ldx, false, rows, cols, q, qs, rq, rs,
+                                     (hipStream_t)stream));
+    return CMP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Per-kernel timing of the built-in variants
+
+CMP_API int cmp_kernel_timing(cmp_ctx* c, int enable) {
+    if (!c) return CMP_EINVAL;
+    if (!c->gpu) return fail(c, CMP_EUNSUPPORTED, "needs a GPU context");
+    c->ktime = enable != 0;
+    return CMP_OK;
+}
+
+CMP_API int cmp_kernel_stats(cmp_ctx* c, int idx, char* name, size_t name_len, long long* launches,
+                             double* total_ms) {
+    if (!c) return CMP_EINVAL;
+    // fold completed event pairs into the totals (waits for the recorded events)
+    for (auto& k : c->kpending) {
+        float ms = 0;
+        if (hipEventSynchronize(k.b) == hipSuccess && hipEventElapsedTime(&ms, k.a, k.b) == hipSuccess) {
+            auto& st = c->kstats[k.name];
+            st.first += 1;
+            st.second += ms;
+        }
+        c->kpool.push_back(k.a);
+        c->kpool.push_back(k.b);
+    }
+    c->kpending.clear();
+    if (idx < 0) {  // reset
+        c->kstats.clear();
+        return CMP_OK;
+    }
+    if (idx >= (int)c->kstats.size()) return CMP_ENOTFOUND;
+    auto it = c->kstats.begin();
+    std::advance(it, idx);
+    if (name && name_len) std::snprintf(name, name_len, "%s", it->first.c_str());
+    if (launches) *launches = it->second.first;
+    if (total_ms) *total_ms = it->second.second;
+    return CMP_OK;
+}

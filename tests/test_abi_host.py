@@ -1,0 +1,302 @@
+"""The C-ABI library on the CPU: exports, registry semantics, selection rules and history.
+
+No GPU is touched: contexts are host-only (device -1) and the variants are
+host functions registered through the ABI, as the runtime allows for any
+interface.  Selection results are compared one by one with the oracle's plain
+rules (oracle.selection), which are index results and must agree exactly.
+"""
+import ctypes as C
+import os
+import re
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import selection as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "compar.h")
+
+pa = pytest.importorskip("paper_2311_03543_amd")
+from paper_2311_03543_amd import _lib  # noqa: E402
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cmp_[a-z0-9_]+)\s*\(", text)) - {"cmp_variant_fn", "cmp_ws_fn"})
+
+
+def test_every_declared_symbol_is_exported():
+    L = _lib.load()
+    names = declared_functions()
+    assert len(names) >= 40
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    # and the binding declares exactly that set
+    assert set(_lib.SIGNATURES) == set(names)
+
+
+def test_version_and_status_strings():
+    L = _lib.load()
+    assert L.cmp_version().decode().startswith("compar-mi355x")
+    assert L.cmp_status_string(-2).decode() == "CMP_EDUP"
+
+
+def host_ctx():
+    return pa.Compar(device=-1)
+
+
+def _noop(args, ws, wsb, stream, user):
+    return 0
+
+
+def test_host_context_has_gemm_interface_and_no_gpu_variants():
+    c = host_ctx()
+    assert c.variant_count("gemm") == 0
+    assert c.device()["arch"] == "host"
+    st = c.L.cmp_gemm_variant(c.ctx, 0, None, None)
+    assert st == pa.CMP_EINVAL
+
+
+def test_registry_errors():
+    c = host_ctx()
+    P = [pa.param("arr", pa.CMP_F32, ["n"], pa.CMP_READWRITE), pa.param("n", pa.CMP_I32)]
+    assert c.interface_declare("sort", P) == 0
+    assert c.interface_declare("sort", P) == pa.CMP_EDUP                     # duplicate interface
+    dup = [pa.param("x", pa.CMP_F32), pa.param("x", pa.CMP_F32)]
+    assert c.interface_declare("other", dup) == pa.CMP_EDUP                  # duplicate parameter
+    bad = [pa.param("a", pa.CMP_F32, ["nope"])]
+    assert c.interface_declare("bad", bad) == pa.CMP_EINVAL                  # extent names nothing
+    st, i0 = c.variant_register("sort", "bubble", pa.CMP_TARGET_HOST, _noop, 1e-5)
+    assert st == 0 and i0 == 0                                               # shares the signature
+    st, _ = c.variant_register("sort", "bubble", pa.CMP_TARGET_HOST, _noop, 1e-5)
+    assert st == pa.CMP_EDUP                                                 # duplicate variant
+    wrong = [pa.param("arr", pa.CMP_F64, ["n"], pa.CMP_READWRITE), pa.param("n", pa.CMP_I32)]
+    st, _ = c.variant_register("sort", "merge", pa.CMP_TARGET_HOST, _noop, 1e-5, params=wrong)
+    assert st == pa.CMP_ESIG                                                 # signature mismatch
+    st, i1 = c.variant_register("sort", "merge", pa.CMP_TARGET_HOST, _noop, 1e-5, params=P)
+    assert st == 0 and i1 == 1                                               # identical list is fine
+    st, _ = c.variant_register("nosuch", "v", pa.CMP_TARGET_HOST, _noop, 1e-5)
+    assert st == pa.CMP_ENOTFOUND                                            # undeclared, no params
+    st, _ = c.variant_register("sort", "gpu", pa.CMP_TARGET_HIP, _noop, 1e-5)
+    assert st == pa.CMP_EUNSUPPORTED                                         # HIP variant, no GPU
+    st, _ = c.variant_register("sort", "neg", pa.CMP_TARGET_HOST, _noop, 0.0)
+    assert st == pa.CMP_EINVAL                                               # bound must be > 0
+    # a first variant may declare the interface itself
+    st, j = c.variant_register("scale", "seq", pa.CMP_TARGET_HOST, _noop, 1e-5,
+                               params=[pa.param("v", pa.CMP_F64, ["m"], pa.CMP_READWRITE),
+                                       pa.param("m", pa.CMP_I64)])
+    assert st == 0 and j == 0
+    assert c.variant_info(1, "sort") == ("merge", pa.CMP_TARGET_HOST, 1e-5)
+    assert c.variant_find("merge", "sort") == 1
+
+
+def register_fakes(c, names=("f32_simt", "bf16x3", "fp8r", "bf16"), bounds=(1e-5, 1e-5, 1e-3, 1e-2)):
+    calls = []
+
+    def make(i):
+        def fn(args, ws, wsb, stream, user):
+            calls.append(i)
+            return 0
+        return fn
+    for i, (n, b) in enumerate(zip(names, bounds)):
+        st, vid = c.variant_register("gemm", n, pa.CMP_TARGET_HOST, make(i), b)
+        assert st == 0 and vid == i
+    return calls
+
+
+def test_admissibility_masks():
+    c = host_ctx()
+    register_fakes(c)
+    assert c.admissible(64, 64, 64, 1e-5) == 0b0011
+    assert c.admissible(64, 64, 64, 1e-3) == 0b0111
+    assert c.admissible(64, 64, 64, 1e-2) == 0b1111
+    with pytest.raises(pa.ComparError) as e:
+        c.select(64, 64, 64, 1e-8)
+    assert e.value.status == pa.CMP_ENOVARIANT
+    with pytest.raises(pa.ComparError) as e:
+        c.select(64, 64, 64, 0.0)
+    assert e.value.status == pa.CMP_EINVAL
+
+
+BOUNDS = [1e-5, 1e-5, 1e-3, 1e-2]
+
+
+def _table(nshapes, seed):
+    shapes = synth.log_uniform_shapes(nshapes, 64, 8192, seed)
+    g = synth.rng(seed + 1)
+    T = g.uniform(0.01, 5.0, (nshapes, 4)).astype(np.float32).astype(np.float64)
+    return shapes, T
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_nn_selector_matches_oracle(seed):
+    c = host_ctx()
+    register_fakes(c)
+    shapes, T = _table(300, seed)
+    for s, (m, n, k) in enumerate(shapes):
+        for v in range(4):
+            c.history_add(int(m), int(n), int(k), v, 20, float(T[s, v]))
+    c.selector_set(pa.CMP_SEL_NN)
+    q = synth.log_uniform_shapes(200, 32, 16384, seed + 50)
+    tols = synth.tol_classes(200, seed + 60)
+    got = c.select_batch([(m, n, k, t) for (m, n, k), t in zip(q, tols)])
+    ref = [S.nn_select(shapes, T, BOUNDS, int(m), int(n), int(k), t) for (m, n, k), t in zip(q, tols)]
+    assert got == ref
+    # one-at-a-time selection agrees with the batch (and the decision cache)
+    for i in range(0, 200, 17):
+        assert c.select(int(q[i][0]), int(q[i][1]), int(q[i][2]), float(tols[i])) == ref[i]
+
+
+def test_static_selector_matches_oracle():
+    c = host_ctx()
+    register_fakes(c)
+    shapes, T = _table(100, 9)
+    for s, (m, n, k) in enumerate(shapes):
+        for v in range(4):
+            c.history_add(int(m), int(n), int(k), v, 20, float(T[s, v]))
+    c.selector_set(pa.CMP_SEL_STATIC)
+    for tol in synth.TOL_CLASSES:
+        ref = S.static_choice(T, [tol] * len(T), BOUNDS, tol)
+        assert c.select(100, 200, 300, tol) == ref
+
+
+def test_nn_on_recorded_shapes_is_exhaustive_best():
+    c = host_ctx()
+    register_fakes(c)
+    shapes, T = _table(80, 4)
+    for s, (m, n, k) in enumerate(shapes):
+        for v in range(4):
+            c.history_add(int(m), int(n), int(k), v, 20, float(T[s, v]))
+    tols = synth.tol_classes(80, 5)
+    got = c.select_batch([(m, n, k, t) for (m, n, k), t in zip(shapes, tols)])
+    assert S.regret(T, got, tols, BOUNDS)["aggregate"] == 0.0
+
+
+def test_no_history_falls_back_to_static_order():
+    c = host_ctx()
+    register_fakes(c)
+    # no data: tightest bound, then lowest id
+    assert c.select(128, 128, 128, 1e-2) == 0
+    assert c.select(128, 128, 128, 1e-3) == 0
+
+
+def test_mask_and_force():
+    c = host_ctx()
+    register_fakes(c)
+    c.set_variant_mask(0b1100)
+    assert c.admissible(8, 8, 8, 1e-2) == 0b1100
+    with pytest.raises(pa.ComparError):
+        c.select(8, 8, 8, 1e-5)
+    c.set_variant_mask(~0 & 0xFFFFFFFFFFFFFFFF)
+    c.force_variant(3)
+    assert c.select(8, 8, 8, 1e-2) == 3
+    with pytest.raises(pa.ComparError):
+        c.select(8, 8, 8, 1e-3)        # forced variant does not meet the tolerance
+    c.force_variant(-1)
+    assert c.select(8, 8, 8, 1e-3) == 0
+
+
+def _host_gemm_args(A, B, Cm, alpha=1.0, beta=0.0):
+    M, K = A.shape
+    N = B.shape[1]
+    return pa.cmp_gemm_args(M, N, K, K, N, N, alpha, beta, A.ctypes.data, B.ctypes.data, Cm.ctypes.data)
+
+
+def test_gemm_dispatch_to_host_variants_and_fallback():
+    c = host_ctx()
+    ran = []
+
+    def matmul(i, fail=False):
+        def fn(args, ws, wsb, stream, user):
+            a = pa.cmp_gemm_args.from_address(args)
+            ran.append(i)
+            if fail:
+                return pa.CMP_EHIP
+            A = np.ctypeslib.as_array(C.cast(a.A, C.POINTER(C.c_float)), (a.M, a.lda))
+            B = np.ctypeslib.as_array(C.cast(a.B, C.POINTER(C.c_float)), (a.K, a.ldb))
+            Cm = np.ctypeslib.as_array(C.cast(a.C, C.POINTER(C.c_float)), (a.M, a.ldc))
+            Cm[:, :a.N] = a.alpha * (A[:, :a.K] @ B[:, :a.N]) + (a.beta * Cm[:, :a.N] if a.beta else 0)
+            return 0
+        return fn
+    assert c.variant_register("gemm", "exact", pa.CMP_TARGET_HOST, matmul(0), 1e-5)[0] == 0
+    assert c.variant_register("gemm", "broken", pa.CMP_TARGET_HOST, matmul(1, fail=True), 1e-3)[0] == 0
+    c.history_add(16, 16, 16, 0, 1, 5.0)
+    c.history_add(16, 16, 16, 1, 1, 1.0)          # broken is "faster"
+    A, B = synth.gemm_operands(16, 16, 16, seed=1)
+    Cm = np.zeros((16, 16), np.float32)
+    st, chosen = c.gemm_raw(_host_gemm_args(A, B, Cm), 1e-3, stream=0)
+    assert st == 0 and chosen == 0 and ran == [1, 0]  # tried the broken one, fell back once
+    assert np.allclose(Cm, A @ B, rtol=1e-5, atol=1e-5)
+    st, chosen = c.gemm_raw(_host_gemm_args(A, B, Cm), 1e-5, stream=0)
+    assert st == 0 and chosen == 0
+
+
+def test_gemm_argument_validation():
+    c = host_ctx()
+    register_fakes(c)
+    A = np.zeros((4, 4), np.float32)
+    a = _host_gemm_args(A, A, A)
+    a.lda = 2
+    assert c.gemm_raw(a, 1e-2, stream=0)[0] == pa.CMP_EINVAL
+    a = _host_gemm_args(A, A, A)
+    a.M = -1
+    assert c.gemm_raw(a, 1e-2, stream=0)[0] == pa.CMP_EINVAL
+    a = _host_gemm_args(A, A, A)
+    assert c.gemm_raw(a, -1.0, stream=0)[0] == pa.CMP_EINVAL
+    a = _host_gemm_args(A, A, A)
+    a.A = None
+    assert c.gemm_raw(a, 1e-2, stream=0)[0] == pa.CMP_EINVAL
+    a.alpha = 0.0                                          # alpha == 0 never reads A or B
+    assert c.gemm_raw(a, 1e-2, stream=0)[0] == 0
+
+
+def test_host_timing():
+    c = host_ctx()
+    register_fakes(c)
+    A = np.zeros((4, 4), np.float32)
+    a = _host_gemm_args(A, A, A)
+    med, mn, mean = C.c_float(), C.c_float(), C.c_float()
+    st = c.L.cmp_time_variant(c.ctx, 2, C.byref(a), 1, 5, None, C.byref(med), C.byref(mn), C.byref(mean))
+    assert st == 0 and 0 <= mn.value <= med.value
+
+
+def test_history_roundtrip_and_signature(tmp_path):
+    c = host_ctx()
+    register_fakes(c)
+    shapes, T = _table(20, 3)
+    for s, (m, n, k) in enumerate(shapes):
+        for v in range(4):
+            c.history_add(int(m), int(n), int(k), v, 20, float(T[s, v]), float(T[s, v]) * 0.9, float(T[s, v]) * 1.1)
+    p = str(tmp_path / "hist.txt")
+    c.history_save(p)
+    d = host_ctx()
+    register_fakes(d)
+    assert d.history_load(p) == 0
+    assert d.history() == c.history()
+    text = open(p).read().replace("arch=host", "arch=gfx950")
+    q = str(tmp_path / "other.txt")
+    open(q, "w").write(text)
+    e = host_ctx()
+    register_fakes(e)
+    assert e.history_load(q) == pa.CMP_EINVAL          # recorded on another device
+    assert e.history_load(q, force=True) == 0
+    open(q, "w").write("garbage\n")
+    assert e.history_load(q) == pa.CMP_EINVAL
+
+
+def test_env_restriction_in_subprocess():
+    code = r"""
+import paper_2311_03543_amd as pa
+c = pa.Compar(-1)
+for i, n in enumerate(["f32_simt", "bf16x3", "fp8r", "bf16"]):
+    c.variant_register("gemm", n, pa.CMP_TARGET_HOST, lambda *a: 0, [1e-5, 1e-5, 1e-3, 1e-2][i])
+print(c.admissible(8, 8, 8, 1e-2))
+"""
+    env = dict(os.environ, COMPAR_VARIANTS="bf16,fp8r", PYTHONPATH=ROOT)
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, check=True)
+    assert out.stdout.strip() == "12"        # fp8r (bit 2) and bf16 (bit 3) only

@@ -1,0 +1,228 @@
+"""GPU parity of every gemm variant against the FP64 CPU oracle, through the C ABI.
+
+Bars:
+  * small-integer operands: bit-exact for all four variants (every product and
+    partial sum is exact in each variant's arithmetic);
+  * random operands: relative Frobenius error within the variant's stated bound,
+    and every entry within the rigorous a-priori rounding bound of its arithmetic
+    (gamma_n times the absolute product of the operands the variant multiplies,
+    which the oracle computes from its own encodings of A and B);
+  * BLAS edge cases (beta == 0 ignores C, alpha == 0 ignores A and B, empty
+    and ragged shapes, padded and misaligned leading dimensions);
+  * bitwise repeatability of each variant.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import dev, gamma, host, say
+
+pytestmark = pytest.mark.gpu
+
+VARIANTS = ["f32_simt", "bf16x3", "fp8r", "bf16"]
+BOUND = {"f32_simt": 1e-5, "bf16x3": 1e-5, "fp8r": 1e-3, "bf16": 1e-2}
+
+
+@pytest.fixture(scope="module")
+def cx():
+    import paper_2311_03543_amd as pa
+    c = pa.Compar(0)
+    assert c.device()["arch"].startswith("gfx950")
+    yield c
+    c.close()
+
+
+def run(cx, name, A, B, C0=None, alpha=1.0, beta=0.0):
+    import torch
+    M, N = A.shape[0], B.shape[1]
+    dA, dB = dev(A), dev(B)
+    dC = dev(C0) if C0 is not None else torch.zeros((M, N), dtype=torch.float32, device="cuda")
+    say(f"  gemm {name} M={M} N={N} K={A.shape[1]} alpha={alpha} beta={beta}")
+    cx.gemm_variant(cx.variant_find(name), dA, dB, dC, alpha, beta)
+    return host(dC)
+
+
+# ---- config: single FP32 GEMM, 256^3, uniform[-1, 1], seed 0 ------------------
+
+def test_f32_simt_256_uniform(cx):
+    A, B = synth.gemm_operands(256, 256, 256, seed=0, dist="uniform")
+    C = run(cx, "f32_simt", A, B)
+    ref = oracle.gemm(A, B)
+    err = oracle.relfro(C, ref)
+    assert err <= 1e-5, err
+    assert np.all(np.abs(C - ref) <= gamma(256) * oracle.absgemm(A, B))
+
+
+# ---- exactness on small integers ---------------------------------------------
+
+INT_SHAPES = [(1, 1, 1), (7, 5, 3), (256, 256, 256), (300, 520, 200), (257, 255, 129),
+              (64, 1000, 33), (513, 130, 640)]
+
+
+@pytest.mark.parametrize("name", VARIANTS)
+@pytest.mark.parametrize("M,N,K", INT_SHAPES)
+def test_integer_exact(cx, name, M, N, K):
+    A = synth.int_matrix(M, K, M * 7 + K)
+    B = synth.int_matrix(K, N, N * 11 + K)
+    C = run(cx, name, A, B)
+    ref = (A.astype(np.int64) @ B.astype(np.int64)).astype(np.float64)
+    assert np.array_equal(C.astype(np.float64), ref)
+
+
+# ---- random operands: stated bound and entrywise rounding bound ----------------
+
+def variant_reference(name, A, B):
+    """(product of the operands the variant multiplies, entrywise rounding bound)."""
+    M, K = A.shape
+    if name == "f32_simt":
+        return oracle.gemm(A, B), gamma(K) * oracle.absgemm(A, B)
+    if name == "bf16":
+        a = oracle.bf16_to_float(oracle.bf16_rne(A))
+        b = oracle.bf16_to_float(oracle.bf16_rne(B))
+        return oracle.gemm(a, b), gamma(K) * oracle.absgemm(a, b)
+    if name == "bf16x3":
+        ah, al = (oracle.bf16_to_float(x) for x in oracle.split_bf16(A))
+        bh, bl = (oracle.bf16_to_float(x) for x in oracle.split_bf16(B))
+        prod = oracle.gemm(ah, bh) + oracle.gemm(ah, bl) + oracle.gemm(al, bh)
+        mag = oracle.absgemm(ah, bh) + oracle.absgemm(ah, bl) + oracle.absgemm(al, bh)
+        return prod, gamma(3 * K) * mag
+    if name == "fp8r":
+        qa, qb = oracle.quant_fp8(A), oracle.quant_fp8(B)
+        a1 = oracle.dequant_fp8(qa["q"], qa["qscale"], *A.shape)
+        a2 = oracle.dequant_fp8(qa["rq"], qa["rscale"], *A.shape)
+        b1 = oracle.dequant_fp8(qb["q"], qb["qscale"], *B.shape)
+        b2 = oracle.dequant_fp8(qb["rq"], qb["rscale"], *B.shape)
+        # dequantised values are exact binary32 numbers (power-of-two scaling)
+        f = [x.astype(np.float32) for x in (a1, a2, b1, b2)]
+        assert all(np.array_equal(x.astype(np.float64), y) for x, y in zip(f, (a1, a2, b1, b2)))
+        prod = sum(oracle.gemm(x, y) for x in f[:2] for y in f[2:])
+        mag = sum(oracle.absgemm(x, y) for x in f[:2] for y in f[2:])
+        return prod, gamma(4 * K) * mag
+    raise ValueError(name)
+
+
+RAND_SHAPES = [(256, 256, 256), (384, 640, 512), (1000, 300, 777), (129, 1031, 260), (512, 512, 2048)]
+
+
+@pytest.mark.parametrize("name", VARIANTS)
+@pytest.mark.parametrize("M,N,K", RAND_SHAPES)
+def test_random_within_bounds(cx, name, M, N, K):
+    A, B = synth.gemm_operands(M, N, K, seed=M + 3 * N + 7 * K)
+    C = run(cx, name, A, B)
+    ref = oracle.gemm(A, B)
+    err = oracle.relfro(C, ref)
+    assert err <= BOUND[name], (name, err)
+    prod, bnd = variant_reference(name, A, B)
+    viol = np.abs(C.astype(np.float64) - prod) - bnd
+    assert np.all(viol <= 0), (name, float(viol.max()))
+
+
+# expected error levels for normal(0,1) operands: a kernel far off these has a
+# rounding bug (for instance truncation instead of round-to-nearest-even)
+LEVEL = {"f32_simt": (1e-8, 2e-6), "bf16x3": (1e-6, 8e-6), "fp8r": (5e-4, 9.6e-4), "bf16": (1.5e-3, 3.5e-3)}
+
+
+@pytest.mark.parametrize("name", VARIANTS)
+def test_error_levels_1024(cx, name):
+    A, B = synth.gemm_operands(1024, 1024, 1024, seed=1010)
+    C = run(cx, name, A, B)
+    err = oracle.relfro(C, oracle.gemm(A, B))
+    lo, hi = LEVEL[name]
+    say(f"  {name} 1024^3 rel-Frobenius {err:.3e}")
+    assert lo <= err <= hi, err
+
+
+# ---- BLAS semantics and edge cases -------------------------------------------
+
+@pytest.mark.parametrize("name", VARIANTS)
+def test_alpha_beta(cx, name):
+    A, B = synth.gemm_operands(200, 300, 150, seed=4)
+    C0 = synth.normal_matrix(200, 300, 5)
+    C = run(cx, name, A, B, C0, alpha=-0.5, beta=2.0)
+    ref = oracle.gemm(A, B, -0.5, 2.0, C0)
+    assert oracle.relfro(C, ref) <= BOUND[name]
+
+
+@pytest.mark.parametrize("name", VARIANTS)
+def test_beta_zero_ignores_nan_c(cx, name):
+    A, B = synth.gemm_operands(130, 140, 150, seed=6)
+    C0 = np.full((130, 140), np.nan, np.float32)
+    C = run(cx, name, A, B, C0, beta=0.0)
+    assert np.all(np.isfinite(C))
+    assert oracle.relfro(C, oracle.gemm(A, B)) <= BOUND[name]
+
+
+@pytest.mark.parametrize("name", VARIANTS)
+def test_alpha_zero_and_k_zero(cx, name):
+    A = np.full((50, 60), np.nan, np.float32)
+    B = np.full((60, 70), np.nan, np.float32)
+    C0 = synth.normal_matrix(50, 70, 7)
+    C = run(cx, name, A, B, C0, alpha=0.0, beta=0.5)
+    assert np.array_equal(C, (0.5 * C0.astype(np.float64)).astype(np.float32))
+    C = run(cx, name, np.zeros((50, 0), np.float32), np.zeros((0, 70), np.float32), C0, beta=3.0)
+    assert np.array_equal(C, (3.0 * C0.astype(np.float64)).astype(np.float32))
+
+
+@pytest.mark.parametrize("name", VARIANTS)
+def test_empty_shapes(cx, name):
+    import torch
+    vid = cx.variant_find(name)
+    for M, N, K in [(0, 5, 5), (5, 0, 5)]:
+        A = torch.zeros((M, K), device="cuda")
+        B = torch.zeros((K, N), device="cuda")
+        C = torch.zeros((M, N), device="cuda")
+        cx.gemm_variant(vid, A, B, C)
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("name", VARIANTS)
+def test_padded_and_misaligned_leading_dims(cx, name):
+    import torch
+    M, N, K = 150, 170, 131        # K % 4 != 0: rows of A are not 16-byte aligned
+    A, B = synth.gemm_operands(M, N, K, seed=8)
+    Abig = np.zeros((M, K + 5), np.float32)
+    Abig[:, :K] = A
+    Bbig = np.zeros((K, N + 3), np.float32)
+    Bbig[:, :N] = B
+    dA, dB = dev(Abig), dev(Bbig)
+    dC = torch.zeros((M, N + 9), device="cuda")
+    vid = cx.variant_find(name)
+    say(f"  gemm {name} with lda={K + 5} ldb={N + 3} ldc={N + 9}")
+    cx.gemm_variant(vid, dA[:, :K], dB[:, :N], dC[:, :N])
+    C = host(dC)
+    assert np.all(C[:, N:] == 0.0)
+    assert oracle.relfro(C[:, :N], oracle.gemm(A, B)) <= BOUND[name]
+
+
+@pytest.mark.parametrize("name", VARIANTS)
+def test_bitwise_repeatable(cx, name):
+    A, B = synth.gemm_operands(300, 400, 500, seed=9)
+    c1 = run(cx, name, A, B)
+    c2 = run(cx, name, A, B)
+    assert np.array_equal(c1.view(np.uint32), c2.view(np.uint32))
+
+
+@pytest.mark.parametrize("name", VARIANTS)
+def test_nan_in_a_propagates(cx, name):
+    A, B = synth.gemm_operands(64, 64, 64, seed=10)
+    A[3, 5] = np.nan
+    C = run(cx, name, A, B)
+    assert np.all(np.isnan(C[3])) and np.all(np.isfinite(np.delete(C, 3, axis=0)))
+
+
+# ---- full-size square sweep point, sampled entries --------------------------------
+
+@pytest.mark.parametrize("name", VARIANTS)
+def test_square_8192_sampled(cx, name):
+    n = 8192
+    A, B = synth.gemm_operands(n, n, n, seed=synth.square_sweep_seed(n))
+    C = run(cx, name, A, B)
+    ij = synth.sample_entries(n, n, 4096, 77)
+    ref = oracle.gemm_entries(A, B, ij)
+    got = C[ij[:, 0], ij[:, 1]]
+    err = oracle.relfro(got, ref)
+    say(f"  {name} 8192^3 sampled rel-Frobenius {err:.3e}")
+    assert err <= BOUND[name], err

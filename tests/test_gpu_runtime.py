@@ -1,0 +1,169 @@
+"""GPU tests of the runtime around the kernels: selection through cmp_gemm, timing and
+calibration, verify mode with its FP64 probe, and the learned selector's kernels against the
+binary64 network oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import dev, host, say
+from oracle import mlp as omlp
+from oracle import selection as S
+
+pytestmark = pytest.mark.gpu
+BOUNDS = [1e-5, 1e-5, 1e-3, 1e-2]
+
+
+@pytest.fixture()
+def cx():
+    import paper_2311_03543_amd as pa
+    c = pa.Compar(0)
+    yield c
+    c.close()
+
+
+def test_builtin_registration(cx):
+    import paper_2311_03543_amd as pa
+    assert [cx.variant_info(i)[0] for i in range(cx.variant_count())] == list(pa.BUILTIN_VARIANTS)
+    assert [cx.variant_info(i)[2] for i in range(4)] == BOUNDS
+
+
+@pytest.mark.parametrize("tol", [1e-5, 1e-3, 1e-2])
+def test_cmp_gemm_selected_variant_is_admissible_and_accurate(cx, tol):
+    import torch
+    A, B = synth.gemm_operands(512, 384, 640, seed=21)
+    dC = torch.zeros((512, 384), device="cuda")
+    say(f"  cmp_gemm tol={tol}")
+    chosen = cx.gemm(dev(A), dev(B), dC, tol=tol)
+    assert BOUNDS[chosen] <= tol
+    assert oracle.relfro(host(dC), oracle.gemm(A, B)) <= tol
+
+
+def test_timing_and_calibration_feed_selection(cx):
+    import torch
+    shapes = [(256, 256, 256), (1024, 1024, 1024), (64, 4096, 128)]
+    A = torch.randn(1024 * 4096, device="cuda")
+    B = torch.randn(4096 * 4096, device="cuda")
+    C = torch.zeros(4096 * 1024, device="cuda")
+    say("  calibrate 3 shapes x 4 variants")
+    cx.calibrate(shapes, A, B, C, warmup=1, reps=5)
+    rows = cx.history()
+    assert len(rows) == 12
+    for (M, N, K, vid, reps, med, mn, mean) in rows:
+        assert reps == 5 and 0 < mn <= med
+    # a second calibration of the same shapes is skipped (resumable)
+    cx.calibrate(shapes, A, B, C, warmup=1, reps=5)
+    assert len(cx.history()) == 12
+    # nearest-neighbour selection on recorded shapes = exhaustive best of the table
+    T = np.zeros((3, 4))
+    for (M, N, K, vid, reps, med, mn, mean) in rows:
+        T[shapes.index((M, N, K)), vid] = med
+    for s, (M, N, K) in enumerate(shapes):
+        for tol in synth.TOL_CLASSES:
+            assert cx.select(M, N, K, tol) == S.exhaustive_best(list(T[s]), BOUNDS, tol)
+
+
+def test_verify_mode_probe_matches_oracle(cx):
+    import torch
+    import paper_2311_03543_amd as pa
+    A, B = synth.gemm_operands(300, 260, 200, seed=22)
+    C0 = synth.normal_matrix(300, 260, 23)
+    dC = dev(C0)
+    cx.set_flags(pa.CMP_FLAG_VERIFY)
+    say("  verify-mode cmp_gemm tol=1e-2, beta=0.5")
+    chosen = cx.gemm(dev(A), dev(B), dC, alpha=1.0, beta=0.5, tol=1e-2)
+    est, fallbacks = cx.last_verify()
+    C = host(dC)
+    assert fallbacks == 0
+    # the library's probe vector is splitmix64-Rademacher with seed 0x5eed (first call)
+    x = oracle.rademacher_splitmix(260, 0x5EED)
+    ref = oracle.freivalds(A, B, C, x, alpha=1.0, beta=0.5, C0=C0)
+    assert abs(est - ref) <= 1e-9 * max(ref, 1e-300), (est, ref)
+    assert oracle.relfro(C, oracle.gemm(A, B, 1.0, 0.5, C0)) <= BOUNDS[chosen]
+
+
+def test_injected_failure_falls_back(monkeypatch):
+    """COMPAR_FAULT=bf16:1 makes every bf16 call fail; cmp_gemm must fall back once to the
+    best other admissible variant (fp8r by the recorded times) and still meet tol."""
+    import torch
+    import paper_2311_03543_amd as pa
+    monkeypatch.setenv("COMPAR_FAULT", "bf16:1")      # read by cmp_init
+    c = pa.Compar(0)
+    try:
+        A, B = synth.gemm_operands(256, 256, 256, seed=5)
+        C = torch.zeros((256, 256), device="cuda")
+        for i, t in enumerate([4.0, 3.0, 2.0, 1.0]):
+            c.history_add(256, 256, 256, i, 1, t)
+        say("  cmp_gemm with injected bf16 failure")
+        chosen = c.gemm(dev(A), dev(B), C, tol=1e-2)
+        assert chosen == 2 and c.last_verify()[1] == 1
+        assert oracle.relfro(host(C), oracle.gemm(A, B)) <= 1e-3
+    finally:
+        c.close()
+
+
+# ---- learned selector kernels vs the binary64 oracle ------------------------------
+
+def _mlp_data(n, seed):
+    shapes = synth.log_uniform_shapes(n, 64, 8192, seed)
+    tols = synth.tol_classes(n, seed + 1)
+    X = omlp.features(shapes[:, 0], shapes[:, 1], shapes[:, 2], tols)
+    # a smooth synthetic log-time surface per variant (stand-in targets)
+    flops = np.log(2.0 * shapes.prod(axis=1))
+    Y = np.stack([flops - 24.0 + 0.1 * X[:, 0], flops - 26.0 + 0.2 * X[:, 1],
+                  flops - 26.5 + 0.05 * X[:, 2], flops - 27.0], axis=1)
+    return X, Y
+
+
+def test_mlp_gradient_matches_oracle(cx):
+    X, Y = _mlp_data(2000, 31)
+    mx, sx = omlp.standardize_stats(X)
+    my, sy = omlp.standardize_stats(Y)
+    Xs, Ys = (X - mx) / sx, (Y - my) / sy
+    p0 = synth.mlp_init(7)
+    cx.mlp_set_params(p0)
+    say("  mlp gradient n=2000")
+    loss, g = cx.mlp_grad(Xs.astype(np.float32), Ys.astype(np.float32))
+    rl, rg = omlp.loss_and_grad(p0.astype(np.float64), Xs.astype(np.float32).astype(np.float64),
+                                Ys.astype(np.float32).astype(np.float64))
+    assert abs(loss - rl) <= 1e-5 * abs(rl)
+    assert np.linalg.norm(g - rg) <= 1e-4 * np.linalg.norm(rg)
+
+
+def test_mlp_training_trajectory_matches_oracle(cx):
+    X, Y = _mlp_data(2000, 33)
+    p0 = synth.mlp_init(8)
+    cx.mlp_set_params(p0)
+    say("  mlp train 50 steps")
+    trace = cx.mlp_train(X.astype(np.float32), Y.astype(np.float32), steps=50, lr=1e-3)
+    p_gpu = cx.mlp_get_params()
+    mx, sx, my, sy = cx.mlp_get_norm()
+    Xf, Yf = X.astype(np.float32).astype(np.float64), Y.astype(np.float32).astype(np.float64)
+    omx, osx = omlp.standardize_stats(Xf)
+    omy, osy = omlp.standardize_stats(Yf)
+    assert np.allclose(mx, omx, rtol=1e-6) and np.allclose(sx, osx, rtol=1e-5)
+    p_ref, losses = omlp.train(p0.astype(np.float64), (Xf - omx) / osx, (Yf - omy) / osy, 50, 1e-3)
+    assert np.allclose(trace, losses, rtol=1e-4)
+    assert np.linalg.norm(p_gpu - p_ref) <= 1e-3 * np.linalg.norm(p_ref)
+
+
+def test_mlp_inference_matches_oracle(cx):
+    X, _ = _mlp_data(3000, 35)
+    p = synth.mlp_init(9)
+    cx.mlp_set_params(p)
+    Xs = ((X - X.mean(0)) / X.std(0)).astype(np.float32)
+    say("  mlp inference n=3000")
+    got = cx.mlp_infer(Xs)
+    ref, _ = omlp.forward(p.astype(np.float64), Xs.astype(np.float64))
+    assert np.max(np.abs(got - ref)) <= 1e-4 * max(1.0, np.max(np.abs(ref)))
+
+
+def test_mlp_selector_uses_network(cx):
+    import paper_2311_03543_amd as pa
+    # a network whose output favours variant 3 everywhere (output bias), zero weights
+    p = np.zeros(synth.mlp_param_count(), np.float32)
+    p[-4:] = [3.0, 2.0, 1.0, 0.0]
+    cx.mlp_set_params(p)
+    cx.mlp_set_norm(np.zeros(4), np.ones(4), np.zeros(4), np.ones(4))
+    cx.selector_set(pa.CMP_SEL_MLP)
+    assert cx.select_batch([(100, 200, 300, 1e-2), (100, 200, 300, 1e-3), (5000, 5000, 64, 1e-5)]) == [3, 2, 1]
