@@ -95,6 +95,8 @@ def main():
     ap.add_argument("--mlp-steps", type=int, default=5000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--sweep", type=str, default="",
+                    help="comma-separated square sizes to time and record (default: 128..--size)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -114,9 +116,12 @@ def main():
 
     # ---- 1. time and record: square sweep -----------------------------------------
     sweep = {}
-    sizes = [s for s in synth.square_sweep_sizes() if s <= n] or [n]
-    if n not in sizes:
-        sizes.append(n)
+    if args.sweep:
+        sizes = sorted({int(v) for v in args.sweep.split(",")} | {n})
+    else:
+        sizes = [s for s in synth.square_sweep_sizes() if s <= n] or [n]
+        if n not in sizes:
+            sizes.append(n)
     big = {}
     for s in sizes:
         A, B = synth.gemm_operands(s, s, s, seed=synth.square_sweep_seed(s))

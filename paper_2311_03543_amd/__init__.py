@@ -41,6 +41,8 @@ def _mat(t, name):
         return None, 0, 0, 1
     if t.dim() != 2:
         raise ValueError(f"{name} must be 2-D")
+    if t.numel() == 0:
+        return t.data_ptr(), t.shape[0], t.shape[1], max(t.shape[1], 1)
     if t.shape[1] > 1 and t.stride(1) != 1:
         raise ValueError(f"{name} must have unit column stride")
     ld = max(t.stride(0), t.shape[1], 1)

@@ -29,6 +29,7 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef int intx8 __attribute__((ext_vector_type(8)));
+typedef int intx4 __attribute__((ext_vector_type(4)));
 
 constexpr int TM = 256, TN = 256;
 constexpr int ROWB = 128;           // bytes of K per row per step
@@ -62,6 +63,20 @@ __device__ __forceinline__ int swz(int r, int c) { return r * ROWB + ((c ^ (r & 
 // Wait for this wave's outstanding global->LDS loads (vmcnt = 0).
 __device__ __forceinline__ void wait_loads() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
+// Scheduling pattern for one sub-step of 16 MFMAs: the `reads` LDS fragment
+// reads of the next sub-step are interleaved one-for-one with the first MFMAs,
+// so their latency hides behind the matrix pipe instead of stalling it.
+template <int READS, int MFMAS = 16>
+__device__ __forceinline__ void mfma_schedule() {
+    constexpr int kMfma = 0x008, kDsRead = 0x100;
+#pragma unroll
+    for (int r = 0; r < READS; ++r) {
+        __builtin_amdgcn_sched_group_barrier(kMfma, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(kDsRead, 1, 0);
+    }
+    if constexpr (MFMAS > READS) __builtin_amdgcn_sched_group_barrier(kMfma, MFMAS - READS, 0);
+}
+
 // 32 x 32 accumulator block layout: lane l holds column l % 32 and rows
 // 8 (r / 4) + 4 (l / 32) + (r % 4), r = 0..15.
 __device__ __forceinline__ void epilogue(const floatx16 (&acc)[4][4], int64_t M, int64_t N,
@@ -92,8 +107,9 @@ __device__ __forceinline__ void tile_coords(int tiles_m, int tiles_n, int& tm, i
 }
 
 // ---------------------------------------------------------------------------
+template <int NTERMS>
 __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(1, 1)))
-void gemm_bf16_tn_kernel(int64_t M, int64_t N, int64_t Kp, int nterms, float alpha,
+void gemm_bf16_tn_kernel(int64_t M, int64_t N, int64_t Kp, float alpha,
                          const uint16_t* __restrict__ Ah, const uint16_t* __restrict__ Al,
                          const uint16_t* __restrict__ Bh, const uint16_t* __restrict__ Bl,
                          float beta, float* __restrict__ C, int64_t ldc, int tiles_m,
@@ -101,14 +117,15 @@ void gemm_bf16_tn_kernel(int64_t M, int64_t N, int64_t Kp, int nterms, float alp
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
     // LDS: [A slab 0 | A slab 1 | B slab 0 | B slab 1]
 
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int t = threadIdx.x, lane = t & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);   // wave-uniform (SGPR)
     const int wm = wave >> 1, wn = wave & 1;
     int tm, tn;
     tile_coords(tiles_m, tiles_n, tm, tn);
     const int64_t m0 = (int64_t)tm * TM, n0 = (int64_t)tn * TN;
     const int64_t ldb = Kp * 2;                 // row pitch of both images in bytes
     const int nk = (int)(Kp / 64);              // 64 bf16 = 128 bytes per step
-    const int steps = nterms * nk;
+    const int steps = NTERMS * nk;
 
     floatx16 acc[4][4];
 #pragma unroll
@@ -141,20 +158,33 @@ void gemm_bf16_tn_kernel(int64_t M, int64_t N, int64_t Kp, int nterms, float alp
         }
         const uint8_t* sa = smem + cur * SLAB;
         const uint8_t* sb = smem + (2 + cur) * SLAB;
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {        // 16 k per MFMA = 2 chunks per row
-            bf16x8 af[4], bf[4];
+        // Fragments are double-buffered in registers: the LDS reads of
+        // sub-step ks + 1 are in flight while the 16 MFMAs of sub-step ks run.
+        bf16x8 fa[2][4], fb[2][4];
+        auto load_frags = [&](int ks, bf16x8 (&a)[4], bf16x8 (&b)[4]) {
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                af[i] = *reinterpret_cast<const bf16x8*>(sa + swz(wm * 128 + i * 32 + frag_row, 2 * ks + frag_c));
+                a[i] = *reinterpret_cast<const bf16x8*>(sa + swz(wm * 128 + i * 32 + frag_row, 2 * ks + frag_c));
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-                bf[j] = *reinterpret_cast<const bf16x8*>(sb + swz(wn * 128 + j * 32 + frag_row, 2 * ks + frag_c));
+                b[j] = *reinterpret_cast<const bf16x8*>(sb + swz(wn * 128 + j * 32 + frag_row, 2 * ks + frag_c));
+        };
+        load_frags(0, fa[0], fb[0]);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {        // 16 k per MFMA = 2 chunks per row
+            // one scheduling region per sub-step: the next sub-step's reads
+            // interleaved with this sub-step's MFMAs
+            if (ks + 1 < 4) load_frags(ks + 1, fa[(ks + 1) & 1], fb[(ks + 1) & 1]);
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[ks & 1][i], fb[ks & 1][j],
+                                                                        acc[i][j], 0, 0, 0);
+            if (ks + 1 < 4) mfma_schedule<8>();
+            else mfma_schedule<0>();
+            __builtin_amdgcn_sched_barrier(0);
         }
         wait_loads();
         __syncthreads();
@@ -174,7 +204,8 @@ void gemm_fp8r_tn_kernel(int64_t M, int64_t N, int64_t Kp, float alpha,
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
     // LDS: [A slab 0 | A slab 1 | B slab 0 | B slab 1]
 
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int t = threadIdx.x, lane = t & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);   // wave-uniform (SGPR)
     const int wm = wave >> 1, wn = wave & 1;
     int tm, tn;
     tile_coords(tiles_m, tiles_n, tm, tn);
@@ -196,6 +227,22 @@ void gemm_fp8r_tn_kernel(int64_t M, int64_t N, int64_t Kp, float alpha,
     auto a_img = [&](int s) { return ((s / nk) & 1) ? Ar : Aq; };
     auto b_img = [&](int s) { return ((s / nk) & 2) ? Br : Bq; };
 
+    // E8M0 scale bytes of step s for this wave's A rows and B columns; read
+    // one step ahead (through the scalar cache: every index is wave-uniform)
+    // (a byte is fetched as its aligned 32-bit word so the load is scalar)
+    auto byte_at = [](const uint8_t* p, int64_t idx) -> int {
+        const uint32_t w = *reinterpret_cast<const uint32_t*>(p + (idx & ~(int64_t)3));
+        return (int)((w >> ((idx & 3) * 8)) & 0xffu);
+    };
+    auto scale_a = [&](int s) -> int {
+        const int kt = s % nk;
+        return byte_at(((s / nk) & 1) ? Asr : Asq, a_tile * nk + kt);
+    };
+    auto scale_b = [&](int s) -> int {
+        const int kt = s % nk;
+        return byte_at(((s / nk) & 2) ? Bsr : Bsq, b_tile * nk + kt);
+    };
+    int sca_next = scale_a(0), scb_next = scale_b(0);
     stage(a_img(0), Kp, m0, 0, smem, wave, lane);
     stage(b_img(0), Kp, n0, 0, smem + 2 * SLAB, wave, lane);
     wait_loads();
@@ -205,42 +252,47 @@ void gemm_fp8r_tn_kernel(int64_t M, int64_t N, int64_t Kp, float alpha,
     const int frag_c = (lane >> 5) * 2;         // this lane's 2 chunks (32 bytes) of a 64-k sub-step
     for (int s = 0; s < steps; ++s) {
         const int cur = s & 1;
-        const int kt = s % nk;
-        const int term = s / nk;
+        const int sca = sca_next, scb = scb_next;
         if (s + 1 < steps) {
+            sca_next = scale_a(s + 1);
+            scb_next = scale_b(s + 1);
             const int64_t kb = (int64_t)((s + 1) % nk) * ROWB;
             stage(a_img(s + 1), Kp, m0, kb, smem + (cur ^ 1) * SLAB, wave, lane);
             stage(b_img(s + 1), Kp, n0, kb, smem + (2 + (cur ^ 1)) * SLAB, wave, lane);
         }
-        const int sca = (term & 1) ? Asr[a_tile * nk + kt] : Asq[a_tile * nk + kt];
-        const int scb = (term & 2) ? Bsr[b_tile * nk + kt] : Bsq[b_tile * nk + kt];
         const uint8_t* sa = smem + cur * SLAB;
         const uint8_t* sb = smem + (2 + cur) * SLAB;
-#pragma unroll
-        for (int ks = 0; ks < 2; ++ks) {        // 64 k per MFMA = 4 chunks per row
-            intx8 af[4], bf[4];
+        intx8 fa[2][4], fb[2][4];
+        auto load_frags = [&](int ks, intx8 (&a)[4], intx8 (&b)[4]) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int r = wm * 128 + i * 32 + frag_row;
-                const uint4 lo = *reinterpret_cast<const uint4*>(sa + swz(r, 4 * ks + frag_c));
-                const uint4 hi = *reinterpret_cast<const uint4*>(sa + swz(r, 4 * ks + frag_c + 1));
-                af[i] = intx8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w,
-                              (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+                const intx4 lo = *reinterpret_cast<const intx4*>(sa + swz(r, 4 * ks + frag_c));
+                const intx4 hi = *reinterpret_cast<const intx4*>(sa + swz(r, 4 * ks + frag_c + 1));
+                a[i] = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
             }
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int r = wn * 128 + j * 32 + frag_row;
-                const uint4 lo = *reinterpret_cast<const uint4*>(sb + swz(r, 4 * ks + frag_c));
-                const uint4 hi = *reinterpret_cast<const uint4*>(sb + swz(r, 4 * ks + frag_c + 1));
-                bf[j] = intx8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w,
-                              (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+                const intx4 lo = *reinterpret_cast<const intx4*>(sb + swz(r, 4 * ks + frag_c));
+                const intx4 hi = *reinterpret_cast<const intx4*>(sb + swz(r, 4 * ks + frag_c + 1));
+                b[j] = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
             }
+        };
+        load_frags(0, fa[0], fb[0]);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {        // 64 k per MFMA = 4 chunks per row
+            if (ks + 1 < 2) load_frags(ks + 1, fa[1], fb[1]);
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-                        af[i], bf[j], acc[i][j], 0, 0, 0, sca, 0, scb);
+                        fa[ks][i], fb[ks][j], acc[i][j], 0, 0, 0, sca, 0, scb);
+            if (ks + 1 < 2) mfma_schedule<16>();
+            else mfma_schedule<0>();
+            __builtin_amdgcn_sched_barrier(0);
         }
         wait_loads();
         __syncthreads();
@@ -250,6 +302,23 @@ void gemm_fp8r_tn_kernel(int64_t M, int64_t N, int64_t Kp, float alpha,
 
 constexpr size_t kSmem = 4 * (size_t)SLAB;   // 131072 bytes
 
+template <int NTERMS>
+hipError_t launch_bf16_terms(int64_t M, int64_t N, int64_t Kp, float alpha, const uint16_t* Ah,
+                             const uint16_t* Al, const uint16_t* Bh, const uint16_t* Bl, float beta,
+                             float* C, int64_t ldc, hipStream_t stream) {
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)gemm_bf16_tn_kernel<NTERMS>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmem);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const int tiles_m = (int)((M + TM - 1) / TM), tiles_n = (int)((N + TN - 1) / TN);
+    hipLaunchKernelGGL(gemm_bf16_tn_kernel<NTERMS>, dim3(tiles_m * tiles_n), dim3(THREADS), kSmem,
+                       stream, M, N, Kp, alpha, Ah, Al, Bh, Bl, beta, C, ldc, tiles_m, tiles_n);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_gemm_bf16_tn(int64_t M, int64_t N, int64_t Kp, int nterms, float alpha,
@@ -258,17 +327,8 @@ hipError_t launch_gemm_bf16_tn(int64_t M, int64_t N, int64_t Kp, int nterms, flo
                                hipStream_t stream) {
     if (Kp % 64 || Kp <= 0 || (nterms != 1 && nterms != 3) || (nterms == 3 && (!Al || !Bl)))
         return hipErrorInvalidValue;
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)gemm_bf16_tn_kernel,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmem);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
-    const int tiles_m = (int)((M + TM - 1) / TM), tiles_n = (int)((N + TN - 1) / TN);
-    hipLaunchKernelGGL(gemm_bf16_tn_kernel, dim3(tiles_m * tiles_n), dim3(THREADS), kSmem, stream,
-                       M, N, Kp, nterms, alpha, Ah, Al, Bh, Bl, beta, C, ldc, tiles_m, tiles_n);
-    return hipGetLastError();
+    if (nterms == 1) return launch_bf16_terms<1>(M, N, Kp, alpha, Ah, Al, Bh, Bl, beta, C, ldc, stream);
+    return launch_bf16_terms<3>(M, N, Kp, alpha, Ah, Al, Bh, Bl, beta, C, ldc, stream);
 }
 
 hipError_t launch_gemm_fp8r_tn(int64_t M, int64_t N, int64_t Kp, float alpha, const uint8_t* Aq,

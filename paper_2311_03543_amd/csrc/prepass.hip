@@ -260,7 +260,8 @@ __global__ __launch_bounds__(256) void quant_fp8_kernel(
     // Residual r = x - q * 2^-e, rounded once to FP32.  In the scaled domain
     // s - q is exact (s = x * 2^e is exact whenever q != 0), and scaling it
     // back rounds once; this also avoids q * 2^-e overflowing FP32 when x is
-    // within rounding distance of FLT_MAX.  A zero code leaves r = x.
+    // within rounding distance of FLT_MAX.  A zero code leaves r = x - (+-0),
+    // which is x except that -0 - (-0) = +0.
     uint32_t qw[16];
     float ramax = 0.f;
 #pragma unroll
@@ -273,7 +274,7 @@ __global__ __launch_bounds__(256) void quant_fp8_kernel(
         for (int j = 0; j < 4; ++j) {
             const float qv = e4m3_byte_val(qw[i], j);
             float r = 0.f;
-            if (__builtin_isfinite(v[i][j])) r = (qv == 0.f) ? v[i][j] : ldexpf(s[j] - qv, -e);
+            if (__builtin_isfinite(v[i][j])) r = (qv == 0.f) ? v[i][j] - qv : ldexpf(s[j] - qv, -e);
             v[i][j] = r;
             ramax = fmaxf(ramax, fabsf(r));
         }

@@ -23,7 +23,8 @@ def _special_values(n, seed):
     x = (g.standard_normal(n) * np.exp2(g.integers(-30, 30, n))).astype(np.float32)
     edge = np.array([0.0, -0.0, 1.0, -1.0, 3.0e38, -3.4e38, 1e-40, -1e-45, 2.0 ** -126, 65504.0,
                      1.0039062, 1.0078125, 448.0, 449.0, 1e-8], np.float32)
-    x[: edge.size] = edge
+    m = min(n, edge.size)
+    x[:m] = edge[:m]
     return x
 
 
