@@ -90,6 +90,10 @@ def main():
     ap.add_argument("--size", type=int, default=8192)
     ap.add_argument("--reps", type=int, default=20, help="timed reps per variant and shape")
     ap.add_argument("--no-selector", action="store_true")
+    ap.add_argument("--no-grouped", action="store_true")
+    ap.add_argument("--no-stream", action="store_true")
+    ap.add_argument("--stream-requests", type=int, default=10000)
+    ap.add_argument("--grouped-problems", type=int, default=1024)
     ap.add_argument("--train-shapes", type=int, default=2000)
     ap.add_argument("--heldout-shapes", type=int, default=500)
     ap.add_argument("--mlp-steps", type=int, default=5000)
@@ -193,6 +197,16 @@ def main():
     if not args.no_selector:
         selector = selector_experiment(cx, pa, torch, args)
 
+    # ---- 3b. batched uneven GEMMs: one grouped launch vs separate launches -----------
+    grouped = None
+    if not args.no_grouped:
+        grouped = grouped_experiment(cx, pa, torch, args)
+
+    # ---- 3c. request stream: per-request tolerance, Zipf shapes ---------------------
+    stream_res = None
+    if not args.no_stream:
+        stream_res = stream_experiment(pa, torch, args)
+
     # ---- 4. CPU baseline: the oracle on a bounded row panel ----------------------------
     cpu = None
     if not args.no_cpu:
@@ -218,6 +232,8 @@ def main():
         "fp32_simt_tflops": fp32_tflops,
         "speedup_vs_fp32": value / fp32_tflops,
         "selector": selector,
+        "grouped": grouped,
+        "stream": stream_res,
         "roofline": roofline,
         "kernels": kernels,
         "sweep_tflops": {str(s): {k: round(v["tflops"], 2) for k, v in row.items()} for s, row in sweep.items()},
@@ -286,6 +302,110 @@ def selector_experiment(cx, pa, torch, args):
                 mlp_final_loss=loss, mlp_train_s=t2 - t1, mlp_select_500_ms=(t4 - t3) * 1e3,
                 calibration_s=t1 - t0, regret=res, heldout_best_counts=best_counts,
                 regret_pct=res["mlp"]["aggregate_pct"])
+
+
+def grouped_experiment(cx, pa, torch, args):
+    """1024 problems, M, N, K log-uniform in [32, 1024] (seed 4), normal(0,1) FP32 operands."""
+    count = args.grouped_problems
+    shapes = synth.log_uniform_shapes(count, 32, 1024, 4)
+    g = torch.Generator(device="cuda").manual_seed(5)
+    probs = []
+    for (M, N, K) in shapes:
+        A = torch.randn((int(M), int(K)), device="cuda", generator=g)
+        B = torch.randn((int(K), int(N)), device="cuda", generator=g)
+        probs.append((A, B, torch.zeros((int(M), int(N)), device="cuda")))
+    flops = float(sum(2.0 * int(M) * int(N) * int(K) for M, N, K in shapes))
+    reps = 10
+
+    def timed(fn):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for a, b in ev:
+            a.record()
+            fn()
+            b.record()
+        torch.cuda.synchronize()
+        ts = sorted(a.elapsed_time(b) for a, b in ev)
+        return ts[len(ts) // 2]
+
+    def separate():
+        for A, B, C in probs:
+            cx.gemm_variant(0, A, B, C)
+    t_sep = timed(separate)
+    # the same 1024 launches captured once in a graph
+    graph = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        separate()
+    torch.cuda.current_stream().wait_stream(s)
+    with torch.cuda.graph(graph):
+        separate()
+    t_sep_graph = timed(graph.replay)
+    t0 = time.perf_counter()
+    plan = cx.grouped_plan(probs, config=-1, reps=5)
+    t_tune = time.perf_counter() - t0
+    info = plan.info()
+    t_grp = timed(plan.launch)
+    t_grp_graph = timed(plan.graph_launch)
+    plan.destroy()
+    cfgs = pa.grouped_configs()
+    res = dict(problems=count, gflop=flops / 1e9,
+               separate_ms=t_sep, separate_graph_ms=t_sep_graph,
+               grouped_ms=t_grp, grouped_graph_ms=t_grp_graph,
+               grouped_tflops=flops / (t_grp_graph * 1e-3) / 1e12,
+               separate_tflops=flops / (t_sep * 1e-3) / 1e12,
+               speedup_vs_separate=t_sep / t_grp_graph,
+               autotune_s=t_tune, tile=cfgs[info["config"]], tiles=info["tiles"], grid=info["grid"],
+               autotune_ms={f"{c[0]}x{c[1]}x{c[2]}": ms for c, ms in zip(cfgs, info["config_ms"])})
+    log(f"grouped: separate {t_sep:.2f} ms, separate+graph {t_sep_graph:.2f} ms, grouped {t_grp:.2f} ms, "
+        f"grouped+graph {t_grp_graph:.2f} ms, tile {res['tile']}")
+    del probs
+    torch.cuda.empty_cache()
+    return res
+
+
+def stream_experiment(pa, torch, args):
+    """10000 requests over 50 shapes (M, N, K log-uniform in [64, 4096]), Zipf(1.1) ranks,
+    tolerance per request, 20% ill-conditioned operands served in verify mode."""
+    from paper_2311_03543_amd import stream as st
+    req = st.make_stream(nshapes=50, nreq=args.stream_requests, lo=64, hi=4096, s=1.1, ill_frac=0.2, seed=5)
+    pool = st.build_pool(req["shapes"], seed=9, device_gen=True)
+    cx = pa.Compar(0)
+    shapes = [tuple(map(int, s)) for s in req["shapes"]]
+    need = max(max(m * k, k * n, m * n) for m, n, k in shapes)
+    A = torch.randn(need, device="cuda")
+    B = torch.randn(need, device="cuda")
+    C = torch.zeros(need, device="cuda")
+    cx.calibrate(shapes, A, B, C, warmup=2, reps=args.reps)
+    del A, B, C
+    cx.selector_set(pa.CMP_SEL_NN)
+    # warm the workspace and the decision cache on every (shape, tolerance) pair
+    for sh in range(len(shapes)):
+        for t in synth.TOL_CLASSES:
+            a, b = pool[sh]["well"][0]
+            cx.gemm(a, b, pool[sh]["C"], tol=t)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat, chosen, fallbacks = st.run_stream(cx, req, pool, verify_ill=True)
+    wall = time.perf_counter() - t0
+    cx.close()
+    flops = sum(2.0 * shapes[r - 1][0] * shapes[r - 1][1] * shapes[r - 1][2] for r in req["ranks"])
+    mix = {pa.BUILTIN_VARIANTS[v]: int((chosen == v).sum()) for v in range(4)}
+    ill = req["ill"]
+    res = dict(requests=len(lat), wall_s=wall, req_per_s=len(lat) / wall, tflops=flops / wall / 1e12,
+               p50_us=float(np.percentile(lat, 50)), p99_us=float(np.percentile(lat, 99)),
+               p50_us_well=float(np.percentile(lat[~ill], 50)), p99_us_well=float(np.percentile(lat[~ill], 99)),
+               p50_us_ill_verify=float(np.percentile(lat[ill], 50)),
+               p99_us_ill_verify=float(np.percentile(lat[ill], 99)),
+               variant_mix=mix, verify_fallbacks=int(fallbacks))
+    log(f"stream: {res['req_per_s']:.0f} req/s, p50 {res['p50_us']:.0f} us, p99 {res['p99_us']:.0f} us, "
+        f"mix {mix}, fallbacks {fallbacks}")
+    del pool
+    torch.cuda.empty_cache()
+    return res
 
 
 def cpu_baseline(n, seconds):

@@ -290,6 +290,32 @@ int cmp_split_bf16(cmp_ctx *ctx, int64_t rows, int64_t cols, const float *X, int
 int cmp_quant_fp8(cmp_ctx *ctx, int64_t rows, int64_t cols, const float *X, int64_t ldx,
                   uint8_t *q, uint8_t *qscale, uint8_t *rq, uint8_t *rscale, void *stream);
 
+/* ---- grouped launches: many GEMMs of uneven shapes ---------------------- */
+
+/* A plan runs `count` independent gemm problems (FP32 SIMT arithmetic, each
+ * problem's own alpha, beta and leading dimensions; device pointers owned by
+ * the caller and fixed for the plan's lifetime) as ONE persistent kernel whose
+ * workgroups stride over the concatenated tile list, problems ordered by
+ * decreasing work.  The tile shape is one of cmp_grouped_config_count()
+ * configurations; config < 0 runs the autotuner, which times every
+ * configuration `reps` times on this group and keeps the fastest (it runs the
+ * products, so C is overwritten: with beta != 0, re-initialise C afterwards).
+ * The launch is also captured in a hipGraph (cmp_grouped_graph_launch).
+ * Results are bit-identical to cmp_gemm_variant with "f32_simt" per problem.
+ * The plan borrows the context: destroy it before cmp_terminate. */
+typedef struct cmp_grouped_plan cmp_grouped_plan;
+int cmp_grouped_config_count(void);
+int cmp_grouped_config_info(int config, int *bm, int *bn, int *bk);
+int cmp_grouped_plan_create(cmp_ctx *ctx, int count, const cmp_gemm_args *problems, int config,
+                            int reps, void *stream, cmp_grouped_plan **out);
+/* config_ms (may be NULL) receives the autotuner's median ms per configuration
+ * (NaN where not timed). */
+int cmp_grouped_plan_info(const cmp_grouped_plan *plan, int *config, int *problems, int *tiles,
+                          int *grid, float *config_ms);
+int cmp_grouped_launch(cmp_grouped_plan *plan, void *stream);
+int cmp_grouped_graph_launch(cmp_grouped_plan *plan, void *stream);
+int cmp_grouped_plan_destroy(cmp_grouped_plan *plan);
+
 /* ---- per-kernel timing (tracing of the built-in variants) ---------------- */
 
 /* When enabled, every kernel launch of the built-in variants is bracketed by

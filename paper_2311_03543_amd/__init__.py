@@ -339,3 +339,51 @@ class Compar:
         if reset:
             self.L.cmp_kernel_stats(self.ctx, -1, None, 0, None, None)
         return out
+
+    # ---- grouped launches -----------------------------------------------------
+    def grouped_plan(self, problems, config: int = -1, reps: int = 5, stream=None) -> "GroupedPlan":
+        """problems: list of (A, B, C[, alpha, beta]) device-tensor tuples."""
+        args = [gemm_args(*p) for p in problems]
+        arr = (cmp_gemm_args * len(args))(*args)
+        plan = C.c_void_p()
+        self._check(self.L.cmp_grouped_plan_create(self.ctx, len(args), arr, config, reps,
+                                                   _stream_ptr(stream), C.byref(plan)))
+        return GroupedPlan(self, plan)
+
+
+def grouped_configs():
+    L = _lib.load()
+    out = []
+    for i in range(L.cmp_grouped_config_count()):
+        bm, bn, bk = C.c_int(), C.c_int(), C.c_int()
+        L.cmp_grouped_config_info(i, C.byref(bm), C.byref(bn), C.byref(bk))
+        out.append((bm.value, bn.value, bk.value))
+    return out
+
+
+class GroupedPlan:
+    """A grouped launch plan (cmp_grouped_plan_*); destroy before its context."""
+
+    def __init__(self, cx: Compar, handle):
+        self.cx, self.h = cx, handle
+
+    def info(self):
+        import math
+        n = self.cx.L.cmp_grouped_config_count()
+        cfg, probs, tiles, grid = C.c_int(), C.c_int(), C.c_int(), C.c_int()
+        ms = (C.c_float * n)()
+        self.cx._check(self.cx.L.cmp_grouped_plan_info(self.h, C.byref(cfg), C.byref(probs), C.byref(tiles),
+                                                       C.byref(grid), ms))
+        return dict(config=cfg.value, problems=probs.value, tiles=tiles.value, grid=grid.value,
+                    config_ms=[None if math.isnan(v) else v for v in ms])
+
+    def launch(self, stream=None):
+        self.cx._check(self.cx.L.cmp_grouped_launch(self.h, _stream_ptr(stream)))
+
+    def graph_launch(self, stream=None):
+        self.cx._check(self.cx.L.cmp_grouped_graph_launch(self.h, _stream_ptr(stream)))
+
+    def destroy(self):
+        if self.h:
+            self.cx.L.cmp_grouped_plan_destroy(self.h)
+            self.h = C.c_void_p()

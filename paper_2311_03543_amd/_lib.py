@@ -109,6 +109,13 @@ SIGNATURES = {
     "cmp_last_verify": (_I, [_P, _DP, _IP]),
     "cmp_split_bf16": (_I, [_P, _I64, _I64, _P, _I64, _P, _P, _P]),
     "cmp_quant_fp8": (_I, [_P, _I64, _I64, _P, _I64, _P, _P, _P, _P, _P]),
+    "cmp_grouped_config_count": (_I, []),
+    "cmp_grouped_config_info": (_I, [_I, _IP, _IP, _IP]),
+    "cmp_grouped_plan_create": (_I, [_P, _I, C.POINTER(cmp_gemm_args), _I, _I, _P, C.POINTER(_P)]),
+    "cmp_grouped_plan_info": (_I, [_P, _IP, _IP, _IP, _IP, _FP]),
+    "cmp_grouped_launch": (_I, [_P, _P]),
+    "cmp_grouped_graph_launch": (_I, [_P, _P]),
+    "cmp_grouped_plan_destroy": (_I, [_P]),
     "cmp_kernel_timing": (_I, [_P, _I]),
     "cmp_kernel_stats": (_I, [_P, _I, C.c_char_p, C.c_size_t, C.POINTER(C.c_longlong), _DP]),
 }

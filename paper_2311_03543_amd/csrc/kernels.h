@@ -14,6 +14,29 @@ hipError_t launch_gemm_f32_simt(int64_t M, int64_t N, int64_t K, float alpha,
                                 const float* A, int64_t lda, const float* B, int64_t ldb,
                                 float beta, float* C, int64_t ldc, hipStream_t stream);
 
+// Grouped FP32 SIMT launch over many problems of uneven shapes.  The
+// descriptor array (device memory) lists the problems in launch order with
+// the first tile index of each (prefix sum of tiles_m * tiles_n); `grid`
+// persistent workgroups stride over all `total_tiles`.  `vec` marks problems
+// whose A and B allow 16-byte loads (lda, ldb multiples of 4, 16-byte aligned).
+struct GroupedDesc {
+    int64_t M, N, K, lda, ldb, ldc;
+    float alpha, beta;
+    const float* A;
+    const float* B;
+    float* C;
+    int tiles_n, tile_start, vec, pad;
+};
+struct GroupedConfig {
+    int bm, bn, bk;
+};
+constexpr int kNumGroupedConfigs = 8;
+extern const GroupedConfig kGroupedConfigs[kNumGroupedConfigs];
+hipError_t launch_gemm_f32_grouped(int config, const GroupedDesc* desc, int count, int total_tiles,
+                                   int grid, hipStream_t stream);
+// Resident workgroups per CU of the grouped kernel for a configuration.
+int grouped_blocks_per_cu(int config);
+
 // C = beta * C (or 0 when beta == 0) for the alpha == 0 / K == 0 cases.
 hipError_t launch_scale_c(int64_t M, int64_t N, float beta, float* C, int64_t ldc,
                           hipStream_t stream);

@@ -1638,3 +1638,208 @@ CMP_API int cmp_kernel_stats(cmp_ctx* c, int idx, char* name, size_t name_len, l
     if (total_ms) *total_ms = it->second.second;
     return CMP_OK;
 }
+
+// ---------------------------------------------------------------------------
+// Grouped launches: many GEMMs of uneven shapes in one persistent kernel
+
+struct cmp_grouped_plan {
+    cmp_ctx* ctx = nullptr;
+    int count = 0;           // problems with at least one tile
+    int config = -1;
+    int total_tiles = 0;
+    int grid = 0;
+    cmp::GroupedDesc* desc = nullptr;     // device
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<float> config_ms;         // autotuner medians per configuration (NaN: not tried)
+};
+
+namespace {
+
+// Descriptors for one tile configuration, problems in decreasing order of work.
+int build_descs(cmp_ctx* c, const std::vector<cmp_gemm_args>& probs, int config,
+                std::vector<cmp::GroupedDesc>* out, int* total) {
+    const int bm = cmp::kGroupedConfigs[config].bm, bn = cmp::kGroupedConfigs[config].bn;
+    std::vector<int> order;
+    for (int i = 0; i < (int)probs.size(); ++i)
+        if (probs[i].M > 0 && probs[i].N > 0) order.push_back(i);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        return (double)probs[x].M * probs[x].N * std::max<int64_t>(probs[x].K, 1) >
+               (double)probs[y].M * probs[y].N * std::max<int64_t>(probs[y].K, 1);
+    });
+    out->clear();
+    int64_t start = 0;
+    for (int i : order) {
+        const cmp_gemm_args& a = probs[i];
+        cmp::GroupedDesc d{};
+        d.M = a.M; d.N = a.N; d.K = a.K;
+        d.lda = a.lda; d.ldb = a.ldb; d.ldc = a.ldc;
+        d.alpha = a.alpha; d.beta = a.beta;
+        d.A = a.A; d.B = a.B; d.C = a.C;
+        const int64_t tm = (a.M + bm - 1) / bm, tn = (a.N + bn - 1) / bn;
+        d.tiles_n = (int)tn;
+        d.tile_start = (int)start;
+        d.vec = (a.lda % 4 == 0) && (a.ldb % 4 == 0) && ((reinterpret_cast<uintptr_t>(a.A) & 15) == 0) &&
+                ((reinterpret_cast<uintptr_t>(a.B) & 15) == 0);
+        start += tm * tn;
+        if (start > INT32_MAX) return fail(c, CMP_EINVAL, "grouped launch exceeds 2^31 tiles");
+        out->push_back(d);
+    }
+    *total = (int)start;
+    return CMP_OK;
+}
+
+int upload_descs(cmp_ctx* c, cmp_grouped_plan* pl, const std::vector<cmp::GroupedDesc>& d,
+                 hipStream_t s) {
+    if (pl->desc) HIP_TRY(c, hipFree(pl->desc));
+    pl->desc = nullptr;
+    const size_t bytes = std::max<size_t>(d.size(), 1) * sizeof(cmp::GroupedDesc);
+    HIP_TRY(c, hipMalloc(&pl->desc, bytes));
+    if (!d.empty())
+        HIP_TRY(c, hipMemcpyAsync(pl->desc, d.data(), d.size() * sizeof(cmp::GroupedDesc),
+                                  hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    return CMP_OK;
+}
+
+int grouped_grid(cmp_ctx* c, int config, int total_tiles) {
+    const int per_cu = cmp::grouped_blocks_per_cu(config);
+    return std::max(1, std::min(total_tiles, per_cu * c->props.multiProcessorCount));
+}
+
+}  // namespace
+
+CMP_API int cmp_grouped_config_count(void) { return cmp::kNumGroupedConfigs; }
+
+CMP_API int cmp_grouped_config_info(int config, int* bm, int* bn, int* bk) {
+    if (config < 0 || config >= cmp::kNumGroupedConfigs) return CMP_EINVAL;
+    if (bm) *bm = cmp::kGroupedConfigs[config].bm;
+    if (bn) *bn = cmp::kGroupedConfigs[config].bn;
+    if (bk) *bk = cmp::kGroupedConfigs[config].bk;
+    return CMP_OK;
+}
+
+CMP_API int cmp_grouped_plan_create(cmp_ctx* c, int count, const cmp_gemm_args* probs, int config,
+                                    int reps, void* stream, cmp_grouped_plan** out) {
+    if (!c || !out) return CMP_EINVAL;
+    *out = nullptr;
+    if (!c->gpu) return fail(c, CMP_EUNSUPPORTED, "needs a GPU context");
+    if (count < 0 || (count > 0 && !probs)) return fail(c, CMP_EINVAL, "bad problem list");
+    if (config >= cmp::kNumGroupedConfigs) return fail(c, CMP_EINVAL, "unknown tile configuration %d", config);
+    if (reps < 1) return fail(c, CMP_EINVAL, "reps must be >= 1");
+    std::vector<cmp_gemm_args> pv(probs, probs + count);
+    for (int i = 0; i < count; ++i) {
+        int st = check_gemm_args(c, &pv[i]);
+        if (st) return fail(c, st, "problem %d: %s", i, c->last_error.c_str());
+    }
+    auto s = (hipStream_t)stream;
+    auto* pl = new (std::nothrow) cmp_grouped_plan();
+    if (!pl) return fail(c, CMP_ENOMEM, "plan");
+    pl->ctx = c;
+    pl->config_ms.assign(cmp::kNumGroupedConfigs, NAN);
+    auto cleanup = [&](int st) {
+        if (pl->desc) (void)hipFree(pl->desc);
+        delete pl;
+        return st;
+    };
+    std::vector<cmp::GroupedDesc> d;
+    int total = 0, st;
+    if (config < 0) {
+        // autotuner: time every tile configuration on this very group, keep the fastest
+        hipEvent_t e0, e1;
+        HIP_TRY(c, hipEventCreate(&e0));
+        HIP_TRY(c, hipEventCreate(&e1));
+        float best = INFINITY;
+        int best_cfg = 0;
+        for (int cfg = 0; cfg < cmp::kNumGroupedConfigs; ++cfg) {
+            if ((st = build_descs(c, pv, cfg, &d, &total))) return cleanup(st);
+            if ((st = upload_descs(c, pl, d, s))) return cleanup(st);
+            const int grid = grouped_grid(c, cfg, total);
+            std::vector<float> t(reps);
+            hipError_t he = cmp::launch_gemm_f32_grouped(cfg, pl->desc, (int)d.size(), total, grid, s);
+            for (int r = 0; r < reps && he == hipSuccess; ++r) {
+                (void)hipEventRecord(e0, s);
+                he = cmp::launch_gemm_f32_grouped(cfg, pl->desc, (int)d.size(), total, grid, s);
+                (void)hipEventRecord(e1, s);
+                if (he == hipSuccess) he = hipEventSynchronize(e1);
+                if (he == hipSuccess) he = hipEventElapsedTime(&t[r], e0, e1);
+            }
+            if (he != hipSuccess) {
+                (void)hipEventDestroy(e0);
+                (void)hipEventDestroy(e1);
+                return cleanup(hip_fail(c, he, "grouped autotune"));
+            }
+            std::sort(t.begin(), t.end());
+            pl->config_ms[cfg] = t[reps / 2];
+            if (t[reps / 2] < best) {
+                best = t[reps / 2];
+                best_cfg = cfg;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        config = best_cfg;
+    }
+    if ((st = build_descs(c, pv, config, &d, &total))) return cleanup(st);
+    if ((st = upload_descs(c, pl, d, s))) return cleanup(st);
+    pl->config = config;
+    pl->count = (int)d.size();
+    pl->total_tiles = total;
+    pl->grid = grouped_grid(c, config, total);
+    // capture the launch into a graph on a private stream
+    hipStream_t cap = nullptr;
+    hipError_t he = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (he == hipSuccess) he = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (he == hipSuccess) {
+        hipError_t le = cmp::launch_gemm_f32_grouped(pl->config, pl->desc, pl->count, pl->total_tiles,
+                                                     pl->grid, cap);
+        he = hipStreamEndCapture(cap, &pl->graph);
+        if (he == hipSuccess) he = le;
+    }
+    if (he == hipSuccess) he = hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0);
+    if (cap) (void)hipStreamDestroy(cap);
+    if (he != hipSuccess) {
+        if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+        if (pl->graph) (void)hipGraphDestroy(pl->graph);
+        return cleanup(hip_fail(c, he, "grouped graph capture"));
+    }
+    *out = pl;
+    return CMP_OK;
+}
+
+CMP_API int cmp_grouped_plan_info(const cmp_grouped_plan* pl, int* config, int* problems, int* tiles,
+                                  int* grid, float* config_ms) {
+    if (!pl) return CMP_EINVAL;
+    if (config) *config = pl->config;
+    if (problems) *problems = pl->count;
+    if (tiles) *tiles = pl->total_tiles;
+    if (grid) *grid = pl->grid;
+    if (config_ms)
+        for (int i = 0; i < cmp::kNumGroupedConfigs; ++i) config_ms[i] = pl->config_ms[i];
+    return CMP_OK;
+}
+
+CMP_API int cmp_grouped_launch(cmp_grouped_plan* pl, void* stream) {
+    if (!pl) return CMP_EINVAL;
+    cmp_ctx* c = pl->ctx;
+    HIP_TRY(c, cmp::launch_gemm_f32_grouped(pl->config, pl->desc, pl->count, pl->total_tiles, pl->grid,
+                                            (hipStream_t)stream));
+    return CMP_OK;
+}
+
+CMP_API int cmp_grouped_graph_launch(cmp_grouped_plan* pl, void* stream) {
+    if (!pl) return CMP_EINVAL;
+    cmp_ctx* c = pl->ctx;
+    HIP_TRY(c, hipGraphLaunch(pl->exec, (hipStream_t)stream));
+    return CMP_OK;
+}
+
+CMP_API int cmp_grouped_plan_destroy(cmp_grouped_plan* pl) {
+    if (!pl) return CMP_OK;
+    (void)hipDeviceSynchronize();
+    if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+    if (pl->graph) (void)hipGraphDestroy(pl->graph);
+    if (pl->desc) (void)hipFree(pl->desc);
+    delete pl;
+    return CMP_OK;
+}

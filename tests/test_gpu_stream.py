@@ -1,0 +1,43 @@
+"""Request stream through cmp_gemm: every request's output is checked against the full FP64
+oracle within that request's tolerance, ill-conditioned operands included (served in
+verify mode), and the chosen variant is always admissible for the request's tolerance."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import host, say
+
+pytestmark = pytest.mark.gpu
+BOUNDS = [1e-5, 1e-5, 1e-3, 1e-2]
+
+
+def test_request_stream_outputs_within_tolerance():
+    import paper_2311_03543_amd as pa
+    from paper_2311_03543_amd import stream as st
+    req = st.make_stream(nshapes=12, nreq=240, lo=64, hi=1024, seed=21)
+    pool = st.build_pool(req["shapes"], seed=3, host_arrays=True)
+    cx = pa.Compar(0)
+    try:
+        import torch
+        A = torch.randn(1024 * 1024, device="cuda")
+        B = torch.randn(1024 * 1024, device="cuda")
+        C = torch.zeros(1024 * 1024, device="cuda")
+        cx.calibrate([tuple(map(int, s)) for s in req["shapes"]], A, B, C, warmup=1, reps=3)
+        errors = []
+
+        def check(i, Cdev):
+            sh = int(req["ranks"][i]) - 1
+            kind = "ill" if req["ill"][i] else "well"
+            Ah, Bh = pool[sh]["host"][kind][i % 2]
+            errors.append((i, oracle.relfro(host(Cdev), oracle.gemm(Ah, Bh)), float(req["tols"][i])))
+
+        say("  serving 240 requests")
+        lat, chosen, fallbacks = st.run_stream(cx, req, pool, verify_ill=True, on_result=check)
+    finally:
+        cx.close()
+    for i, c in enumerate(chosen):
+        assert BOUNDS[c] <= req["tols"][i]
+    bad = [(i, e, t) for i, e, t in errors if not e <= t]
+    assert not bad, bad[:5]
+    assert np.all(lat > 0)
