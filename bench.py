@@ -92,6 +92,8 @@ def main():
     ap.add_argument("--no-selector", action="store_true")
     ap.add_argument("--no-grouped", action="store_true")
     ap.add_argument("--no-stream", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 256 MiB device copy (reference kernel for HBM byte counters)")
     ap.add_argument("--stream-requests", type=int, default=10000)
     ap.add_argument("--grouped-problems", type=int, default=1024)
     ap.add_argument("--train-shapes", type=int, default=2000)
@@ -191,6 +193,15 @@ def main():
                               tflops=sweep[n][pa.BUILTIN_VARIANTS[v]]["tflops"]) for t, v in chosen.items()}
     del big
     torch.cuda.empty_cache()
+
+    if args.copy_probe:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE calibrate the HBM counters
+        src = torch.empty(64 << 20, dtype=torch.float32, device="cuda").normal_()
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # ---- 3. selector experiment -----------------------------------------------------
     selector = None

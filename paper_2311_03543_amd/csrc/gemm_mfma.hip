@@ -20,6 +20,8 @@
 // MFMAs run without occupying any registers.  Inside a slab row, 16-byte chunk
 // c of row r sits at position c ^ (r % 8): the 32 rows one fragment read
 // touches then spread over all bank groups.
+#include <type_traits>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -63,6 +65,9 @@ __device__ __forceinline__ int swz(int r, int c) { return r * ROWB + ((c ^ (r & 
 // Wait for this wave's outstanding global->LDS loads (vmcnt = 0).
 __device__ __forceinline__ void wait_loads() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
+// Wait for this wave's outstanding LDS reads (lgkmcnt = 0).
+__device__ __forceinline__ void wait_lds_reads() { __builtin_amdgcn_s_waitcnt(0xC07F); }
+
 // Scheduling pattern for one sub-step of 16 MFMAs: the `reads` LDS fragment
 // reads of the next sub-step are interleaved one-for-one with the first MFMAs,
 // so their latency hides behind the matrix pipe instead of stalling it.
@@ -75,6 +80,20 @@ __device__ __forceinline__ void mfma_schedule() {
         __builtin_amdgcn_sched_group_barrier(kDsRead, 1, 0);
     }
     if constexpr (MFMAS > READS) __builtin_amdgcn_sched_group_barrier(kMfma, MFMAS - READS, 0);
+}
+
+// Pattern for the first sub-step of a stage: the next stage's 16 direct
+// global->LDS loads (two per MFMA) and the 8 LDS fragment reads of the next
+// sub-step ride under the first 8 MFMAs.
+__device__ __forceinline__ void mfma_schedule_with_stage() {
+    constexpr int kMfma = 0x008, kVmemRead = 0x020, kDsRead = 0x100;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        __builtin_amdgcn_sched_group_barrier(kMfma, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(kVmemRead, 2, 0);
+        __builtin_amdgcn_sched_group_barrier(kDsRead, 1, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(kMfma, 8, 0);
 }
 
 // 32 x 32 accumulator block layout: lane l holds column l % 32 and rows
@@ -149,46 +168,75 @@ void gemm_bf16_tn_kernel(int64_t M, int64_t N, int64_t Kp, float alpha,
 
     const int frag_row = lane & 31;
     const int frag_c = lane >> 5;               // chunk (8 bf16) within a 16-k sub-step
-    for (int s = 0; s < steps; ++s) {
+    auto load_frags = [&](const uint8_t* sa, const uint8_t* sb, int ks, bf16x8 (&a)[4],
+                          bf16x8 (&b)[4]) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            a[i] = *reinterpret_cast<const bf16x8*>(sa + swz(wm * 128 + i * 32 + frag_row, 2 * ks + frag_c));
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            b[j] = *reinterpret_cast<const bf16x8*>(sb + swz(wn * 128 + j * 32 + frag_row, 2 * ks + frag_c));
+    };
+    auto mfma16 = [&](const bf16x8 (&a)[4], const bf16x8 (&b)[4]) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    };
+
+    // Fragments are double-buffered in registers (sub-step ks + 1 is read
+    // while sub-step ks multiplies).  One stage = 4 sub-steps of 16 MFMAs:
+    //   ks 0: next stage's global->LDS loads + reads of ks 1 under the MFMAs
+    //   ks 1, 2: reads of ks 2, 3
+    //   ks 3: wait for the next stage (own loads landed, own reads of this
+    //         stage done, workgroup barrier), then its ks-0 reads under the
+    //         last 16 MFMAs of this stage.
+    // A buffer is overwritten only by the stage after the barrier that
+    // follows every wave's last read of it.
+    bf16x8 fa[2][4], fb[2][4];
+    load_frags(smem, smem + 2 * SLAB, 0, fa[0], fb[0]);
+    __builtin_amdgcn_sched_barrier(0);
+    auto one_stage = [&](int s, auto more_tag) {
+        constexpr bool MORE = decltype(more_tag)::value;
         const int cur = s & 1;
-        if (s + 1 < steps) {
+        const uint8_t* sa = smem + cur * SLAB;
+        const uint8_t* sb = smem + (2 + cur) * SLAB;
+        // ks 0
+        if constexpr (MORE) {
             const int64_t kb = (int64_t)((s + 1) % nk) * ROWB;
             stage(a_img(s + 1), ldb, m0, kb, smem + (cur ^ 1) * SLAB, wave, lane);
             stage(b_img(s + 1), ldb, n0, kb, smem + (2 + (cur ^ 1)) * SLAB, wave, lane);
         }
-        const uint8_t* sa = smem + cur * SLAB;
-        const uint8_t* sb = smem + (2 + cur) * SLAB;
-        // Fragments are double-buffered in registers: the LDS reads of
-        // sub-step ks + 1 are in flight while the 16 MFMAs of sub-step ks run.
-        bf16x8 fa[2][4], fb[2][4];
-        auto load_frags = [&](int ks, bf16x8 (&a)[4], bf16x8 (&b)[4]) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-                a[i] = *reinterpret_cast<const bf16x8*>(sa + swz(wm * 128 + i * 32 + frag_row, 2 * ks + frag_c));
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                b[j] = *reinterpret_cast<const bf16x8*>(sb + swz(wn * 128 + j * 32 + frag_row, 2 * ks + frag_c));
-        };
-        load_frags(0, fa[0], fb[0]);
+        load_frags(sa, sb, 1, fa[1], fb[1]);
+        mfma16(fa[0], fb[0]);
+        if constexpr (MORE) mfma_schedule_with_stage();
+        else mfma_schedule<8>();
         __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {        // 16 k per MFMA = 2 chunks per row
-            // one scheduling region per sub-step: the next sub-step's reads
-            // interleaved with this sub-step's MFMAs
-            if (ks + 1 < 4) load_frags(ks + 1, fa[(ks + 1) & 1], fb[(ks + 1) & 1]);
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[ks & 1][i], fb[ks & 1][j],
-                                                                        acc[i][j], 0, 0, 0);
-            if (ks + 1 < 4) mfma_schedule<8>();
-            else mfma_schedule<0>();
-            __builtin_amdgcn_sched_barrier(0);
+        // ks 1
+        load_frags(sa, sb, 2, fa[0], fb[0]);
+        mfma16(fa[1], fb[1]);
+        mfma_schedule<8>();
+        __builtin_amdgcn_sched_barrier(0);
+        // ks 2
+        load_frags(sa, sb, 3, fa[1], fb[1]);
+        mfma16(fa[0], fb[0]);
+        mfma_schedule<8>();
+        __builtin_amdgcn_sched_barrier(0);
+        // ks 3
+        if constexpr (MORE) {
+            wait_lds_reads();
+            wait_loads();
+            __syncthreads();
+            load_frags(smem + (cur ^ 1) * SLAB, smem + (2 + (cur ^ 1)) * SLAB, 0, fa[0], fb[0]);
         }
-        wait_loads();
-        __syncthreads();
-    }
+        mfma16(fa[1], fb[1]);
+        if constexpr (MORE) mfma_schedule<8>();
+        else mfma_schedule<0>();
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    for (int s = 0; s + 1 < steps; ++s) one_stage(s, std::true_type{});
+    one_stage(steps - 1, std::false_type{});
     epilogue(acc, M, N, m0, n0, wm, wn, lane, alpha, beta, C, ldc);
 }
 
@@ -242,7 +290,6 @@ void gemm_fp8r_tn_kernel(int64_t M, int64_t N, int64_t Kp, float alpha,
         const int kt = s % nk;
         return byte_at(((s / nk) & 2) ? Bsr : Bsq, b_tile * nk + kt);
     };
-    int sca_next = scale_a(0), scb_next = scale_b(0);
     stage(a_img(0), Kp, m0, 0, smem, wave, lane);
     stage(b_img(0), Kp, n0, 0, smem + 2 * SLAB, wave, lane);
     wait_loads();
@@ -250,53 +297,71 @@ void gemm_fp8r_tn_kernel(int64_t M, int64_t N, int64_t Kp, float alpha,
 
     const int frag_row = lane & 31;
     const int frag_c = (lane >> 5) * 2;         // this lane's 2 chunks (32 bytes) of a 64-k sub-step
-    for (int s = 0; s < steps; ++s) {
+    auto load_frags = [&](const uint8_t* sa, const uint8_t* sb, int ks, intx8 (&a)[4],
+                          intx8 (&b)[4]) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = wm * 128 + i * 32 + frag_row;
+            const intx4 lo = *reinterpret_cast<const intx4*>(sa + swz(r, 4 * ks + frag_c));
+            const intx4 hi = *reinterpret_cast<const intx4*>(sa + swz(r, 4 * ks + frag_c + 1));
+            a[i] = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int r = wn * 128 + j * 32 + frag_row;
+            const intx4 lo = *reinterpret_cast<const intx4*>(sb + swz(r, 4 * ks + frag_c));
+            const intx4 hi = *reinterpret_cast<const intx4*>(sb + swz(r, 4 * ks + frag_c + 1));
+            b[j] = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+        }
+    };
+    auto mfma16 = [&](const intx8 (&a)[4], const intx8 (&b)[4], int sca, int scb) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a[i], b[j], acc[i][j], 0, 0,
+                                                                            0, sca, 0, scb);
+    };
+
+    // Same stage pipeline as the bf16 kernel with two 64-k sub-steps per
+    // stage: ks 0 carries the next stage's loads and the ks-1 reads; ks 1
+    // waits for the next stage and reads its ks-0 fragments under the MFMAs.
+    intx8 fa[2][4], fb[2][4];
+    load_frags(smem, smem + 2 * SLAB, 0, fa[0], fb[0]);
+    int sca_next = scale_a(0), scb_next = scale_b(0);
+    __builtin_amdgcn_sched_barrier(0);
+    auto one_stage = [&](int s, auto more_tag) {
+        constexpr bool MORE = decltype(more_tag)::value;
         const int cur = s & 1;
+        const uint8_t* sa = smem + cur * SLAB;
+        const uint8_t* sb = smem + (2 + cur) * SLAB;
         const int sca = sca_next, scb = scb_next;
-        if (s + 1 < steps) {
+        // ks 0
+        if constexpr (MORE) {
             sca_next = scale_a(s + 1);
             scb_next = scale_b(s + 1);
             const int64_t kb = (int64_t)((s + 1) % nk) * ROWB;
             stage(a_img(s + 1), Kp, m0, kb, smem + (cur ^ 1) * SLAB, wave, lane);
             stage(b_img(s + 1), Kp, n0, kb, smem + (2 + (cur ^ 1)) * SLAB, wave, lane);
         }
-        const uint8_t* sa = smem + cur * SLAB;
-        const uint8_t* sb = smem + (2 + cur) * SLAB;
-        intx8 fa[2][4], fb[2][4];
-        auto load_frags = [&](int ks, intx8 (&a)[4], intx8 (&b)[4]) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int r = wm * 128 + i * 32 + frag_row;
-                const intx4 lo = *reinterpret_cast<const intx4*>(sa + swz(r, 4 * ks + frag_c));
-                const intx4 hi = *reinterpret_cast<const intx4*>(sa + swz(r, 4 * ks + frag_c + 1));
-                a[i] = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
-            }
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int r = wn * 128 + j * 32 + frag_row;
-                const intx4 lo = *reinterpret_cast<const intx4*>(sb + swz(r, 4 * ks + frag_c));
-                const intx4 hi = *reinterpret_cast<const intx4*>(sb + swz(r, 4 * ks + frag_c + 1));
-                b[j] = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
-            }
-        };
-        load_frags(0, fa[0], fb[0]);
+        load_frags(sa, sb, 1, fa[1], fb[1]);
+        mfma16(fa[0], fb[0], sca, scb);
+        mfma_schedule<16>();
         __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int ks = 0; ks < 2; ++ks) {        // 64 k per MFMA = 4 chunks per row
-            if (ks + 1 < 2) load_frags(ks + 1, fa[1], fb[1]);
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-                        fa[ks][i], fb[ks][j], acc[i][j], 0, 0, 0, sca, 0, scb);
-            if (ks + 1 < 2) mfma_schedule<16>();
-            else mfma_schedule<0>();
-            __builtin_amdgcn_sched_barrier(0);
+        // ks 1
+        if constexpr (MORE) {
+            wait_lds_reads();
+            wait_loads();
+            __syncthreads();
+            load_frags(smem + (cur ^ 1) * SLAB, smem + (2 + (cur ^ 1)) * SLAB, 0, fa[0], fb[0]);
         }
-        wait_loads();
-        __syncthreads();
-    }
+        mfma16(fa[1], fb[1], sca, scb);
+        if constexpr (MORE) mfma_schedule<16>();
+        else mfma_schedule<0>();
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    for (int s = 0; s + 1 < steps; ++s) one_stage(s, std::true_type{});
+    one_stage(steps - 1, std::false_type{});
     epilogue(acc, M, N, m0, n0, wm, wn, lane, alpha, beta, C, ldc);
 }
 
