@@ -62,12 +62,14 @@ def nn_select(train_shapes, train_times, bounds, M, N, K, tol):
     return argmin_tiebreak(list(train_times[r]), admissible(bounds, tol), bounds)
 
 
-def static_choice(train_times, train_tols, bounds, tol):
-    """Best single variant for a tolerance class: admissible variant with the lowest
-    total recorded time over the training rows of that class (all rows if none)."""
-    rows = [i for i, t in enumerate(train_tols) if t == tol] or list(range(len(train_tols)))
+def static_choice(train_times, bounds, tol):
+    """Best single variant for a tolerance: the admissible variant with the lowest total
+    recorded time over the recorded shapes (every row holds all variants' times);
+    with no rows, the tightest bound, then the lowest id."""
     cand = admissible(bounds, tol)
-    tot = [sum(train_times[r][v] for r in rows) for v in range(len(bounds))]
+    if len(train_times) == 0:
+        return argmin_tiebreak([0.0] * len(bounds), cand, bounds)
+    tot = [sum(row[v] for row in train_times) for v in range(len(bounds))]
     return argmin_tiebreak(tot, cand, bounds)
 
 

@@ -161,7 +161,7 @@ def test_static_selector_matches_oracle():
             c.history_add(int(m), int(n), int(k), v, 20, float(T[s, v]))
     c.selector_set(pa.CMP_SEL_STATIC)
     for tol in synth.TOL_CLASSES:
-        ref = S.static_choice(T, [tol] * len(T), BOUNDS, tol)
+        ref = S.static_choice(T, BOUNDS, tol)
         assert c.select(100, 200, 300, tol) == ref
 
 

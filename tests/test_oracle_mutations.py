@@ -1,0 +1,87 @@
+"""Planted mistakes: copies of the oracle with one plausible error each (a transposed operand, a
+flipped sign, a dropped term, a wrong tie rule) are compiled on the CPU and must fail the same
+independent pins that the real oracle passes (exact rational arithmetic, torch's E4M3 codes)."""
+import ctypes as C
+import os
+import subprocess
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "oracle.c")
+
+MUTATIONS = {
+    "transposed_B": ("                    s += (double)A[i * lda + k] * (double)B[k * ldb + j];",
+                     "                    s += (double)A[i * lda + k] * (double)B[j * ldb + k];"),
+    "beta_sign": ("r += b * (double)C0[i * ldc + j];", "r -= b * (double)C0[i * ldc + j];"),
+    "dropped_last_k": ("                for (int64_t k = 0; k < K; ++k)\n                    s += (double)A[i * lda + k]",
+                       "                for (int64_t k = 0; k < K - 1; ++k)\n                    s += (double)A[i * lda + k]"),
+    "e4m3_ties_away": ("if (rem > 0.5 * step || (rem == 0.5 * step && fmod(lowm, 2.0) != 0.0)) m = lowm + 1.0;",
+                       "if (rem >= 0.5 * step) m = lowm + 1.0;"),
+}
+
+
+def build_mutant(name, tmp_path):
+    old, new = MUTATIONS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, name
+    path = tmp_path / f"{name}.c"
+    path.write_text(src.replace(old, new))
+    so = tmp_path / f"{name}.so"
+    subprocess.run(["gcc", "-O1", "-fPIC", "-shared", "-std=c11", "-ffp-contract=off", "-o", str(so),
+                    str(path), "-lm"], check=True)
+    return C.CDLL(str(so))
+
+
+def gemm_pin_holds(L):
+    """The exact-rational pin of the plain GEMM on one small non-square case."""
+    g = synth.rng(77)
+    M, N, K = 3, 4, 5
+    A = g.uniform(-1, 1, (M, K)).astype(np.float32)
+    B = g.uniform(-1, 1, (K, N)).astype(np.float32)
+    C0 = g.uniform(-1, 1, (M, N)).astype(np.float32)
+    out = np.empty((M, N), np.float64)
+    fp = C.POINTER(C.c_float)
+    L.oracle_gemm_f64.argtypes = [C.c_int64] * 3 + [C.c_float, fp, C.c_int64, fp, C.c_int64, C.c_float, fp,
+                                                    C.c_int64, C.POINTER(C.c_double), C.c_int64]
+    L.oracle_gemm_f64(M, N, K, 1.0, A.ctypes.data_as(fp), K, B.ctypes.data_as(fp), N, 0.5,
+                      C0.ctypes.data_as(fp), N, out.ctypes.data_as(C.POINTER(C.c_double)), N)
+    for i in range(M):
+        for j in range(N):
+            ex = sum((Fraction(float(A[i, k])) * Fraction(float(B[k, j])) for k in range(K)), Fraction(0)) \
+                + Fraction(1, 2) * Fraction(float(C0[i, j]))
+            if abs(Fraction(out[i, j]) - ex) > Fraction(1, 2 ** 40):
+                return False
+    return True
+
+
+def e4m3_pin_holds(L):
+    pos = np.array([float(v) for v in torch.arange(0, 0x7F, dtype=torch.uint8).view(torch.float8_e4m3fn)
+                    .to(torch.float32)])
+    pos.sort()
+    mids = ((pos[1:] + pos[:-1]) / 2).astype(np.float32)
+    L.oracle_e4m3_rne.argtypes = [C.c_float]
+    L.oracle_e4m3_rne.restype = C.c_uint8
+    ours = np.array([L.oracle_e4m3_rne(float(v)) for v in mids], np.uint8)
+    ref = torch.from_numpy(mids).to(torch.float8_e4m3fn).view(torch.uint8).numpy()
+    return np.array_equal(ours, ref)
+
+
+def test_real_oracle_passes_the_pins(tmp_path):
+    import oracle
+    assert gemm_pin_holds(oracle.lib())
+    assert e4m3_pin_holds(oracle.lib())
+
+
+@pytest.mark.parametrize("name", ["transposed_B", "beta_sign", "dropped_last_k"])
+def test_gemm_mutants_are_caught(name, tmp_path):
+    assert not gemm_pin_holds(build_mutant(name, tmp_path))
+
+
+def test_e4m3_mutant_is_caught(tmp_path):
+    assert not e4m3_pin_holds(build_mutant("e4m3_ties_away", tmp_path))

@@ -67,8 +67,9 @@ def test_regret_known_value():
 
 def test_static_choice():
     T = [[1.0, 5.0, 5.0, 5.0], [9.0, 2.0, 1.0, 0.5]]
-    assert S.static_choice(T, [1e-2, 1e-2], BOUNDS, 1e-2) == 3   # totals 10, 7, 6, 5.5
-    assert S.static_choice(T, [1e-2, 1e-2], BOUNDS, 1e-5) == 1   # all rows, admissible {0,1}: 10 vs 7
+    assert S.static_choice(T, BOUNDS, 1e-2) == 3   # totals 10, 7, 6, 5.5
+    assert S.static_choice(T, BOUNDS, 1e-5) == 1   # admissible {0,1}: 10 vs 7
+    assert S.static_choice([], BOUNDS, 1e-3) == 0
 
 
 def test_log_uniform_shapes_range_and_distinct():
