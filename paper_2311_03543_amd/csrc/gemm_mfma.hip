@@ -17,9 +17,8 @@
 // Each K step stages a 256-row A slab and a 256-row B slab (128 bytes of K per
 // row) in LDS with direct global->LDS loads (global_load_lds_dwordx4), so the
 // next step's tiles stream into the other buffer while the current step's
-// MFMAs run without occupying any registers.  Inside a slab row, 16-byte chunk
-// c of row r sits at position c ^ (r % 8): the 32 rows one fragment read
-// touches then spread over all bank groups.
+// MFMAs run without occupying any registers.  Inside a slab row, 16-byte chunks
+// are XOR-swizzled by row (see swz) so fragment reads are bank-conflict free.
 #include <type_traits>
 
 #include "common.h"
@@ -41,26 +40,36 @@ constexpr int SLAB = TM * ROWB;     // bytes per operand slab (32 KiB)
 typedef const __attribute__((address_space(1))) void* gptr_t;
 typedef __attribute__((address_space(3))) void* lptr_t;
 
+// LDS slab layout: row r holds 128 bytes = 8 chunks of 16 bytes, and chunk c
+// of row r sits at position c ^ f(r), f(r) = (r / 2) % 8.  gfx950's LDS serves
+// a 16-byte-per-lane read 16 lanes per cycle over 64 banks (256 bytes); rows
+// alternate between the two 128-byte bank halves, so the 16 rows one lane
+// group of a fragment read touches ((r % 2), c ^ f(r)) are all distinct: no
+// bank conflicts.  (With f(r) = r % 8, rows r and r + 8 collide: 2-way.)
+__device__ __forceinline__ int swz_f(int r) { return (r >> 1) & 7; }
+
+// Byte address of 16-byte chunk c of slab row r.
+__device__ __forceinline__ int swz(int r, int c) { return r * ROWB + ((c ^ swz_f(r)) << 4); }
+
 // Stage rows [row0, row0 + 256) x bytes [kbyte, kbyte + 128) of an image with
 // row pitch ld_bytes into `slab`.  One wave instruction fills 1 KiB = 8 rows;
 // wave w issues instructions q = 8 w .. 8 w + 7.  Lane l of instruction q
 // lands at slab + 1024 q + 16 l, i.e. row 8 q + l / 8, position l % 8, which
-// holds global chunk (l % 8) ^ (l / 8).
+// must hold global chunk (l % 8) ^ f(8 q + l / 8) = (l % 8) ^ ((4 q + l / 16) % 8).
 __device__ __forceinline__ void stage(const uint8_t* __restrict__ img, int64_t ld_bytes,
                                       int64_t row0, int64_t kbyte, uint8_t* slab, int wave,
                                       int lane) {
-    const int chunk = (lane & 7) ^ (lane >> 3);
-    const uint8_t* src = img + (row0 + wave * 64 + (lane >> 3)) * ld_bytes + kbyte + chunk * 16;
+    const int c_even = (lane & 7) ^ ((lane >> 4) & 7);          // q even: 4 q % 8 = 0
+    const int c_odd = (lane & 7) ^ ((4 + (lane >> 4)) & 7);     // q odd:  4 q % 8 = 4
+    const uint8_t* src = img + (row0 + wave * 64 + (lane >> 3)) * ld_bytes + kbyte;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
         const int q = wave * 8 + i;
-        __builtin_amdgcn_global_load_lds((gptr_t)(src + (int64_t)i * 8 * ld_bytes),
+        const int chunk = (i & 1) ? c_odd : c_even;              // q has the parity of i
+        __builtin_amdgcn_global_load_lds((gptr_t)(src + (int64_t)i * 8 * ld_bytes + chunk * 16),
                                          (lptr_t)(slab + q * 1024), 16, 0, 0);
     }
 }
-
-// Byte address of 16-byte chunk c of slab row r.
-__device__ __forceinline__ int swz(int r, int c) { return r * ROWB + ((c ^ (r & 7)) << 4); }
 
 // Wait for this wave's outstanding global->LDS loads (vmcnt = 0).
 __device__ __forceinline__ void wait_loads() { __builtin_amdgcn_s_waitcnt(0x0F70); }
