@@ -31,4 +31,20 @@ __device__ __forceinline__ void grouped_tile(int id, int tiles_m, int tiles_n, i
     tn = local / gm;
 }
 
+// Panel images: the operand layout the MFMA kernels stream.  An operand with
+// Mp rows (a multiple of 256) and Kb bytes of K per row (a multiple of 64) is
+// cut into blocks of 256 rows x 64 bytes (16 KiB); block (rb, kb) starts at
+// byte (rb * nkb + kb) * 16 KiB, nkb = Kb / 64.  The K extent of one 256-row
+// panel is therefore contiguous, and one block is exactly one LDS slab of one
+// pipeline stage, copied linearly.  Inside a block, row r occupies bytes
+// [64 r, 64 r + 64) and its 16-byte chunk c sits at position c ^ ((r / 4) % 4):
+// the LDS bank swizzle, applied once by the writer of the image.
+constexpr int kPanelRows = 256, kPanelRowBytes = 64, kPanelBlock = 16384;
+
+__host__ __device__ __forceinline__ int64_t panel_offset(int64_t row, int64_t kbyte, int64_t nkb) {
+    const int64_t rb = row >> 8, kb = kbyte >> 6;
+    const int r = (int)(row & 255), c = (int)((kbyte >> 4) & 3);
+    return ((rb * nkb + kb) << 14) + (r << 6) + ((c ^ ((r >> 2) & 3)) << 4) + (kbyte & 15);
+}
+
 }  // namespace cmp

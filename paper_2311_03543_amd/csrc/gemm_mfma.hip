@@ -1,5 +1,6 @@
-// MFMA GEMM kernels for gfx950 over the pre-pass images (both operands
-// K-contiguous: A image Mp x Kp, B image Np x Kp = B transposed).
+// MFMA GEMM kernels for gfx950 over the pre-pass panel images (both operands
+// K-contiguous, A image of Mp rows, B image of Np rows = B transposed, in the
+// panel layout of common.h).
 //
 //   bf16 / bf16x3:  C = alpha * sum_t A_t B_t^T + beta * C with one (bf16) or
 //                   three (hi.hi + hi.lo + lo.hi, the split-precision product)
@@ -8,17 +9,21 @@
 //                   E4M3 images with one E8M0 scale byte per 128 x 128 tile,
 //                   v_mfma_scale_f32_32x32x64_f8f6f4, FP32 accumulation.
 //
-// The extra products are K-concatenated: the main loop walks nterms * Kp / BK
-// steps and each step picks its operand pair, so one accumulator set and one
+// The extra products are K-concatenated: the main loop walks nterms * nkb
+// stages and each stage picks its operand pair, so one accumulator set and one
 // pipeline serve every term.
 //
 // Tiling: 256 x 256 C tile per workgroup of 4 wave64 (2 x 2 waves, 128 x 128
 // per wave = 4 x 4 MFMA blocks of 32 x 32, 256 FP32 accumulators per lane).
-// Each K step stages a 256-row A slab and a 256-row B slab (128 bytes of K per
-// row) in LDS with direct global->LDS loads (global_load_lds_dwordx4), so the
-// next step's tiles stream into the other buffer while the current step's
-// MFMAs run without occupying any registers.  Inside a slab row, 16-byte chunks
-// are XOR-swizzled by row (see swz) so fragment reads are bank-conflict free.
+// A stage is one 64-byte K block of both operands: a 16 KiB A slab and a
+// 16 KiB B slab, each one contiguous panel-image block, so the direct
+// global->LDS loads (global_load_lds_dwordx4) are linear 1 KiB copies whose
+// immediate offset advances the global and the LDS address together.  NBUF
+// stages live in an LDS ring; the loads of stage s + NBUF are issued during
+// stage s, right after the barrier that frees stage s's slot, so a load has
+// about NBUF - 1 stages of MFMA time to land.  Fragments are double-buffered
+// in registers: a stage's slot is read during the previous stage (and its
+// first half, for bf16), never while its own MFMAs run.
 #include <type_traits>
 
 #include "common.h"
@@ -33,100 +38,117 @@ typedef int intx8 __attribute__((ext_vector_type(8)));
 typedef int intx4 __attribute__((ext_vector_type(4)));
 
 constexpr int TM = 256, TN = 256;
-constexpr int ROWB = 128;           // bytes of K per row per step
 constexpr int THREADS = 256;
-constexpr int SLAB = TM * ROWB;     // bytes per operand slab (32 KiB)
+constexpr int SLAB = kPanelBlock;          // 16 KiB: 256 rows x 64 bytes
+constexpr int STAGE = 2 * SLAB;            // A slab + B slab
+constexpr int NBUF = 4;                    // LDS ring depth (stages)
+constexpr size_t kSmem = (size_t)NBUF * STAGE;   // 128 KiB
 
 typedef const __attribute__((address_space(1))) void* gptr_t;
 typedef __attribute__((address_space(3))) void* lptr_t;
 
-// LDS slab layout: row r holds 128 bytes = 8 chunks of 16 bytes, and chunk c
-// of row r sits at position c ^ f(r), f(r) = (r / 2) % 8.  gfx950's LDS serves
-// a 16-byte-per-lane read 16 lanes per cycle over 64 banks (256 bytes); rows
-// alternate between the two 128-byte bank halves, so the 16 rows one lane
-// group of a fragment read touches ((r % 2), c ^ f(r)) are all distinct: no
-// bank conflicts.  (With f(r) = r % 8, rows r and r + 8 collide: 2-way.)
-__device__ __forceinline__ int swz_f(int r) { return (r >> 1) & 7; }
+// Byte offset of 16-byte chunk c of slab row r (the panel swizzle).  gfx950's
+// LDS serves a 16-byte-per-lane read 16 lanes at a time over 64 banks (256
+// bytes = 4 slab rows); the 16 rows one lane group of a fragment read touches
+// then occupy (r % 4, c ^ (r / 4) % 4): 16 distinct bank quads, no conflicts.
+__device__ __forceinline__ int slab_off(int r, int c) { return r * 64 + ((c ^ ((r >> 2) & 3)) << 4); }
 
-// Byte address of 16-byte chunk c of slab row r.
-__device__ __forceinline__ int swz(int r, int c) { return r * ROWB + ((c ^ swz_f(r)) << 4); }
-
-// Stage rows [row0, row0 + 256) x bytes [kbyte, kbyte + 128) of an image with
-// row pitch ld_bytes into `slab`.  One wave instruction fills 1 KiB = 8 rows;
-// wave w issues instructions q = 8 w .. 8 w + 7.  Lane l of instruction q
-// lands at slab + 1024 q + 16 l, i.e. row 8 q + l / 8, position l % 8, which
-// must hold global chunk (l % 8) ^ f(8 q + l / 8) = (l % 8) ^ ((4 q + l / 16) % 8).
-__device__ __forceinline__ void stage(const uint8_t* __restrict__ img, int64_t ld_bytes,
-                                      int64_t row0, int64_t kbyte, uint8_t* slab, int wave,
-                                      int lane) {
-    const int c_even = (lane & 7) ^ ((lane >> 4) & 7);          // q even: 4 q % 8 = 0
-    const int c_odd = (lane & 7) ^ ((4 + (lane >> 4)) & 7);     // q odd:  4 q % 8 = 4
-    const uint8_t* src = img + (row0 + wave * 64 + (lane >> 3)) * ld_bytes + kbyte;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const int q = wave * 8 + i;
-        const int chunk = (i & 1) ? c_odd : c_even;              // q has the parity of i
-        __builtin_amdgcn_global_load_lds((gptr_t)(src + (int64_t)i * 8 * ld_bytes + chunk * 16),
-                                         (lptr_t)(slab + q * 1024), 16, 0, 0);
-    }
+// s_waitcnt immediate: vmcnt <= vm (0..63), lgkmcnt <= lgkm (0..15), expcnt free.
+constexpr int waitcnt_imm(int vm, int lgkm) {
+    return (vm & 15) | ((vm >> 4) << 14) | (7 << 4) | (lgkm << 8);
 }
 
-// Wait for this wave's outstanding global->LDS loads (vmcnt = 0).
-__device__ __forceinline__ void wait_loads() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+// Stage barrier: this wave's LDS reads done, at most `ahead` stages of its
+// slab loads (8 instructions each) still in flight, then the workgroup
+// barrier: afterwards every wave's loads of the awaited stage have landed and
+// every wave's reads of the previous slot are complete.  The empty asm
+// statements keep the compiler from moving memory accesses across.
+template <int AHEAD>
+__device__ __forceinline__ void stage_barrier() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(waitcnt_imm(8 * AHEAD, 0));
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
 
-// Wait for this wave's outstanding LDS reads (lgkmcnt = 0).
-__device__ __forceinline__ void wait_lds_reads() { __builtin_amdgcn_s_waitcnt(0xC07F); }
+// Four 1 KiB linear copies: this wave's quarter (4 KiB) of one slab.
+// `src` already holds the wave's and the lane's offset (wave * 4 KiB + 16 lane),
+// `dst` the wave's slab quarter; lane l lands at dst + offset + 16 l.
+__device__ __forceinline__ void dma_quarter(const uint8_t* src, uint8_t* dst) {
+    __builtin_amdgcn_global_load_lds((gptr_t)src, (lptr_t)dst, 16, 0, 0);
+    __builtin_amdgcn_global_load_lds((gptr_t)src, (lptr_t)dst, 16, 1024, 0);
+    __builtin_amdgcn_global_load_lds((gptr_t)src, (lptr_t)dst, 16, 2048, 0);
+    __builtin_amdgcn_global_load_lds((gptr_t)src, (lptr_t)dst, 16, 3072, 0);
+}
 
-// Scheduling pattern for one sub-step of 16 MFMAs: the `reads` LDS fragment
-// reads of the next sub-step are interleaved one-for-one with the first MFMAs,
-// so their latency hides behind the matrix pipe instead of stalling it.
-template <int READS, int MFMAS = 16>
-__device__ __forceinline__ void mfma_schedule() {
-    constexpr int kMfma = 0x008, kDsRead = 0x100;
+// Scheduling masks of __builtin_amdgcn_sched_group_barrier.
+constexpr int kSchedMfma = 0x008, kSchedVmem = 0x010, kSchedDsRead = 0x100;
+
+// Interleave: READS LDS reads one-for-one under the first MFMAs of a run of
+// MFMAS, the rest of the MFMAs after.
+template <int READS, int MFMAS>
+__device__ __forceinline__ void schedule_reads() {
 #pragma unroll
     for (int r = 0; r < READS; ++r) {
-        __builtin_amdgcn_sched_group_barrier(kMfma, 1, 0);
-        __builtin_amdgcn_sched_group_barrier(kDsRead, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(kSchedMfma, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(kSchedDsRead, 1, 0);
     }
-    if constexpr (MFMAS > READS) __builtin_amdgcn_sched_group_barrier(kMfma, MFMAS - READS, 0);
+    if constexpr (MFMAS > READS) __builtin_amdgcn_sched_group_barrier(kSchedMfma, MFMAS - READS, 0);
 }
 
-// Pattern for the first sub-step of a stage: the next stage's 16 direct
-// global->LDS loads (two per MFMA) and the 8 LDS fragment reads of the next
-// sub-step ride under the first 8 MFMAs.
-__device__ __forceinline__ void mfma_schedule_with_stage() {
-    constexpr int kMfma = 0x008, kVmemRead = 0x020, kDsRead = 0x100;
+// Interleave after a stage barrier: per MFMA one slab load and RPM LDS reads,
+// for the first 8 MFMAs (8 loads, 8 * RPM reads), the rest of the MFMAs after.
+template <int RPM, int MFMAS>
+__device__ __forceinline__ void schedule_loads_reads() {
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
-        __builtin_amdgcn_sched_group_barrier(kMfma, 1, 0);
-        __builtin_amdgcn_sched_group_barrier(kVmemRead, 2, 0);
-        __builtin_amdgcn_sched_group_barrier(kDsRead, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(kSchedMfma, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(kSchedVmem, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(kSchedDsRead, RPM, 0);
     }
-    __builtin_amdgcn_sched_group_barrier(kMfma, 8, 0);
+    if constexpr (MFMAS > 8) __builtin_amdgcn_sched_group_barrier(kSchedMfma, MFMAS - 8, 0);
 }
 
 // 32 x 32 accumulator block layout: lane l holds column l % 32 and rows
 // 8 (r / 4) + 4 (l / 32) + (r % 4), r = 0..15.
+template <bool FULL>
+__device__ __forceinline__ void store_block(const floatx16& acc, int64_t M, int64_t N, int64_t row0,
+                                            int64_t col, float alpha, float beta,
+                                            float* __restrict__ C, int64_t ldc) {
+    if (!FULL && col >= N) return;
+    float old[16];
+    if (beta != 0.f) {
+        // all 16 loads in flight before the first use
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int64_t row = row0 + (r >> 2) * 8 + (r & 3);
+            old[r] = (FULL || row < M) ? C[row * ldc + col] : 0.f;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int64_t row = row0 + (r >> 2) * 8 + (r & 3);
+        if (FULL || row < M) {
+            float v = alpha * acc[r];
+            if (beta != 0.f) v = __builtin_fmaf(beta, old[r], v);
+            C[row * ldc + col] = v;
+        }
+    }
+}
+
 __device__ __forceinline__ void epilogue(const floatx16 (&acc)[4][4], int64_t M, int64_t N,
                                          int64_t m0, int64_t n0, int wm, int wn, int lane,
                                          float alpha, float beta, float* __restrict__ C,
                                          int64_t ldc) {
+    const bool full = m0 + TM <= M && n0 + TN <= N;   // interior tile: no bounds checks
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int64_t col = n0 + wn * 128 + j * 32 + (lane & 31);
-            if (col >= N) continue;
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int64_t row = m0 + wm * 128 + i * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-                if (row < M) {
-                    float* p = C + row * ldc + col;
-                    float v = alpha * acc[i][j][r];
-                    if (beta != 0.f) v = __builtin_fmaf(beta, *p, v);
-                    *p = v;
-                }
-            }
+            const int64_t row0 = m0 + wm * 128 + i * 32 + (lane >> 5) * 4;
+            if (full) store_block<true>(acc[i][j], M, N, row0, col, alpha, beta, C, ldc);
+            else store_block<false>(acc[i][j], M, N, row0, col, alpha, beta, C, ldc);
         }
 }
 
@@ -134,16 +156,35 @@ __device__ __forceinline__ void tile_coords(int tiles_m, int tiles_n, int& tm, i
     grouped_tile(xcd_remap(blockIdx.x, tiles_m * tiles_n), tiles_m, tiles_n, 8, tm, tn);
 }
 
+// Load cursor over the K-concatenated stages: term t, block kb, ring slot.
+// Past the last stage it keeps re-reading the last block into the freed slot
+// (nobody reads it again), so every stage issues the same 8 loads and the
+// in-flight count the barriers wait on stays constant.
+struct LoadCursor {
+    int kb = 0, term = 0, slot = 0, left;
+    __device__ __forceinline__ explicit LoadCursor(int steps) : left(steps) {}
+    // branch-free (selects), so the issuing stage stays one scheduling region
+    __device__ __forceinline__ void advance(int nkb) {
+        const int go = left > 1 ? 1 : 0;
+        left -= go;
+        const int k = kb + go;
+        const int wrap = k == nkb ? 1 : 0;
+        kb = wrap ? 0 : k;
+        term += wrap;
+        slot = slot + 1 == NBUF ? 0 : slot + 1;
+    }
+};
+
 // ---------------------------------------------------------------------------
 template <int NTERMS>
 __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(1, 1)))
-void gemm_bf16_tn_kernel(int64_t M, int64_t N, int64_t Kp, float alpha,
-                         const uint16_t* __restrict__ Ah, const uint16_t* __restrict__ Al,
-                         const uint16_t* __restrict__ Bh, const uint16_t* __restrict__ Bl,
+void gemm_bf16_tn_kernel(int64_t M, int64_t N, int nkb, float alpha,
+                         const uint8_t* __restrict__ Ah, const uint8_t* __restrict__ Al,
+                         const uint8_t* __restrict__ Bh, const uint8_t* __restrict__ Bl,
                          float beta, float* __restrict__ C, int64_t ldc, int tiles_m,
                          int tiles_n) {
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
-    // LDS: [A slab 0 | A slab 1 | B slab 0 | B slab 1]
+    // LDS ring: slot i = [A slab | B slab] at i * STAGE
 
     const int t = threadIdx.x, lane = t & 63;
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);   // wave-uniform (SGPR)
@@ -151,9 +192,13 @@ void gemm_bf16_tn_kernel(int64_t M, int64_t N, int64_t Kp, float alpha,
     int tm, tn;
     tile_coords(tiles_m, tiles_n, tm, tn);
     const int64_t m0 = (int64_t)tm * TM, n0 = (int64_t)tn * TN;
-    const int64_t ldb = Kp * 2;                 // row pitch of both images in bytes
-    const int nk = (int)(Kp / 64);              // 64 bf16 = 128 bytes per step
-    const int steps = NTERMS * nk;
+    const int64_t panel = (int64_t)nkb * SLAB;        // bytes of one 256-row panel
+    const int src_off = wave * 4096 + lane * 16;
+    const uint8_t* a_hi = Ah + tm * panel + src_off;
+    const uint8_t* b_hi = Bh + tn * panel + src_off;
+    const uint8_t* a_lo = NTERMS > 1 ? Al + tm * panel + src_off : a_hi;
+    const uint8_t* b_lo = NTERMS > 1 ? Bl + tn * panel + src_off : b_hi;
+    const int steps = NTERMS * nkb;
 
     floatx16 acc[4][4];
 #pragma unroll
@@ -163,95 +208,81 @@ void gemm_bf16_tn_kernel(int64_t M, int64_t N, int64_t Kp, float alpha,
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-    auto a_img = [&](int s) -> const uint8_t* {
-        return reinterpret_cast<const uint8_t*>((s / nk) == 2 ? Al : Ah);
-    };
-    auto b_img = [&](int s) -> const uint8_t* {
-        return reinterpret_cast<const uint8_t*>((s / nk) == 1 ? Bl : Bh);
+    // term 0 = hi.hi, 1 = hi.lo, 2 = lo.hi
+    LoadCursor ld(steps);
+    auto issue = [&]() {
+        const int64_t kofs = (int64_t)ld.kb * SLAB;
+        uint8_t* dst = smem + ld.slot * STAGE + wave * 4096;
+        dma_quarter((ld.term == 2 ? a_lo : a_hi) + kofs, dst);
+        dma_quarter((ld.term == 1 ? b_lo : b_hi) + kofs, dst + SLAB);
+        ld.advance(nkb);
     };
 
-    stage(a_img(0), ldb, m0, 0, smem, wave, lane);
-    stage(b_img(0), ldb, n0, 0, smem + 2 * SLAB, wave, lane);
-    wait_loads();
-    __syncthreads();
-
+    // lane l feeds row l % 32 of each 32-row block, k-chunk 2 ks + l / 32
     const int frag_row = lane & 31;
-    const int frag_c = lane >> 5;               // chunk (8 bf16) within a 16-k sub-step
-    auto load_frags = [&](const uint8_t* sa, const uint8_t* sb, int ks, bf16x8 (&a)[4],
-                          bf16x8 (&b)[4]) {
+    const int frag_c = lane >> 5;
+    auto load_frags = [&](int slot, int ks, bf16x8 (&a)[4], bf16x8 (&b)[4]) {
+        const uint8_t* sa = smem + slot * STAGE;
+        const uint8_t* sb = sa + SLAB;
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-            a[i] = *reinterpret_cast<const bf16x8*>(sa + swz(wm * 128 + i * 32 + frag_row, 2 * ks + frag_c));
+            a[i] = *reinterpret_cast<const bf16x8*>(sa + slab_off(wm * 128 + i * 32 + frag_row, 2 * ks + frag_c));
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-            b[j] = *reinterpret_cast<const bf16x8*>(sb + swz(wn * 128 + j * 32 + frag_row, 2 * ks + frag_c));
+            b[j] = *reinterpret_cast<const bf16x8*>(sb + slab_off(wn * 128 + j * 32 + frag_row, 2 * ks + frag_c));
     };
-    auto mfma16 = [&](const bf16x8 (&a)[4], const bf16x8 (&b)[4]) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    auto mfma = [&](int idx, const bf16x8 (&a)[4], const bf16x8 (&b)[4]) {
+        const int i = idx >> 2, j = idx & 3;
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     };
 
-    // Fragments are double-buffered in registers (sub-step ks + 1 is read
-    // while sub-step ks multiplies).  One stage = 4 sub-steps of 16 MFMAs:
-    //   ks 0: next stage's global->LDS loads + reads of ks 1 under the MFMAs
-    //   ks 1, 2: reads of ks 2, 3
-    //   ks 3: wait for the next stage (own loads landed, own reads of this
-    //         stage done, workgroup barrier), then its ks-0 reads under the
-    //         last 16 MFMAs of this stage.
-    // A buffer is overwritten only by the stage after the barrier that
-    // follows every wave's last read of it.
+#pragma unroll
+    for (int p = 0; p < NBUF; ++p) issue();
+    stage_barrier<NBUF - 1>();
+
+    // One stage = two 16-MFMA sub-steps over slot `cur`:
+    //   ks 0: MFMAs on fa[0]; reads of ks 1 into fa[1] under them
+    //   ks 1: two MFMAs on fa[1]; stage barrier (stage s + 1 landed, slot
+    //         `cur` free); loads of stage s + NBUF into slot `cur` and reads
+    //         of stage s + 1's ks 0 into fa[0] under the other 14 MFMAs.
+    constexpr int PRE = 2;
     bf16x8 fa[2][4], fb[2][4];
-    load_frags(smem, smem + 2 * SLAB, 0, fa[0], fb[0]);
+    load_frags(0, 0, fa[0], fb[0]);
+    int cur = 0;
     __builtin_amdgcn_sched_barrier(0);
-    auto one_stage = [&](int s, auto more_tag) {
+    auto one_stage = [&](auto more_tag) {
         constexpr bool MORE = decltype(more_tag)::value;
-        const int cur = s & 1;
-        const uint8_t* sa = smem + cur * SLAB;
-        const uint8_t* sb = smem + (2 + cur) * SLAB;
+        const int nxt = cur + 1 == NBUF ? 0 : cur + 1;
         // ks 0
-        if constexpr (MORE) {
-            const int64_t kb = (int64_t)((s + 1) % nk) * ROWB;
-            stage(a_img(s + 1), ldb, m0, kb, smem + (cur ^ 1) * SLAB, wave, lane);
-            stage(b_img(s + 1), ldb, n0, kb, smem + (2 + (cur ^ 1)) * SLAB, wave, lane);
-        }
-        load_frags(sa, sb, 1, fa[1], fb[1]);
-        mfma16(fa[0], fb[0]);
-        if constexpr (MORE) mfma_schedule_with_stage();
-        else mfma_schedule<8>();
+        load_frags(cur, 1, fa[1], fb[1]);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) mfma(q, fa[0], fb[0]);
+        schedule_reads<8, 16>();
         __builtin_amdgcn_sched_barrier(0);
         // ks 1
-        load_frags(sa, sb, 2, fa[0], fb[0]);
-        mfma16(fa[1], fb[1]);
-        mfma_schedule<8>();
+#pragma unroll
+        for (int q = 0; q < PRE; ++q) mfma(q, fa[1], fb[1]);
         __builtin_amdgcn_sched_barrier(0);
-        // ks 2
-        load_frags(sa, sb, 3, fa[1], fb[1]);
-        mfma16(fa[0], fb[0]);
-        mfma_schedule<8>();
-        __builtin_amdgcn_sched_barrier(0);
-        // ks 3
         if constexpr (MORE) {
-            wait_lds_reads();
-            wait_loads();
-            __syncthreads();
-            load_frags(smem + (cur ^ 1) * SLAB, smem + (2 + (cur ^ 1)) * SLAB, 0, fa[0], fb[0]);
+            stage_barrier<NBUF - 2>();
+            issue();
+            load_frags(nxt, 0, fa[0], fb[0]);
         }
-        mfma16(fa[1], fb[1]);
-        if constexpr (MORE) mfma_schedule<8>();
-        else mfma_schedule<0>();
+#pragma unroll
+        for (int q = PRE; q < 16; ++q) mfma(q, fa[1], fb[1]);
+        if constexpr (MORE) schedule_loads_reads<1, 16 - PRE>();
         __builtin_amdgcn_sched_barrier(0);
+        cur = nxt;
     };
-    for (int s = 0; s + 1 < steps; ++s) one_stage(s, std::true_type{});
-    one_stage(steps - 1, std::false_type{});
+    for (int s = 0; s + 1 < steps; ++s) one_stage(std::true_type{});
+    one_stage(std::false_type{});
+    __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 15));   // drain the trailing loads
     epilogue(acc, M, N, m0, n0, wm, wn, lane, alpha, beta, C, ldc);
 }
 
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(1, 1)))
-void gemm_fp8r_tn_kernel(int64_t M, int64_t N, int64_t Kp, float alpha,
+void gemm_fp8r_tn_kernel(int64_t M, int64_t N, int nkb, float alpha,
                          const uint8_t* __restrict__ Aq, const uint8_t* __restrict__ Ar,
                          const uint8_t* __restrict__ Asq, const uint8_t* __restrict__ Asr,
                          const uint8_t* __restrict__ Bq, const uint8_t* __restrict__ Br,
@@ -259,7 +290,6 @@ void gemm_fp8r_tn_kernel(int64_t M, int64_t N, int64_t Kp, float alpha,
                          float beta, float* __restrict__ C, int64_t ldc, int tiles_m,
                          int tiles_n) {
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
-    // LDS: [A slab 0 | A slab 1 | B slab 0 | B slab 1]
 
     const int t = threadIdx.x, lane = t & 63;
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);   // wave-uniform (SGPR)
@@ -267,8 +297,14 @@ void gemm_fp8r_tn_kernel(int64_t M, int64_t N, int64_t Kp, float alpha,
     int tm, tn;
     tile_coords(tiles_m, tiles_n, tm, tn);
     const int64_t m0 = (int64_t)tm * TM, n0 = (int64_t)tn * TN;
-    const int nk = (int)(Kp / 128);             // 128 E4M3 bytes per step
-    const int steps = 4 * nk;
+    const int64_t panel = (int64_t)nkb * SLAB;
+    const int src_off = wave * 4096 + lane * 16;
+    const uint8_t* a_q = Aq + tm * panel + src_off;
+    const uint8_t* a_r = Ar + tm * panel + src_off;
+    const uint8_t* b_q = Bq + tn * panel + src_off;
+    const uint8_t* b_r = Br + tn * panel + src_off;
+    const int steps = 4 * nkb;                  // one 64-k MFMA step per stage
+    const int nkt = nkb / 2;                    // 128-k scale tiles per row
     // this wave's 128 rows of A (and columns of C) lie in one 128-row scale tile
     const int64_t a_tile = m0 / 128 + wm, b_tile = n0 / 128 + wn;
 
@@ -280,101 +316,108 @@ void gemm_fp8r_tn_kernel(int64_t M, int64_t N, int64_t Kp, float alpha,
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-    // term s / nk: 0 = q.q, 1 = r.q, 2 = q.r, 3 = r.r
-    auto a_img = [&](int s) { return ((s / nk) & 1) ? Ar : Aq; };
-    auto b_img = [&](int s) { return ((s / nk) & 2) ? Br : Bq; };
+    // term 0 = q.q, 1 = r.q, 2 = q.r, 3 = r.r
+    LoadCursor ld(steps);
+    auto issue = [&]() {
+        const int64_t kofs = (int64_t)ld.kb * SLAB;
+        uint8_t* dst = smem + ld.slot * STAGE + wave * 4096;
+        dma_quarter(((ld.term & 1) ? a_r : a_q) + kofs, dst);
+        dma_quarter(((ld.term & 2) ? b_r : b_q) + kofs, dst + SLAB);
+        ld.advance(nkb);
+    };
 
-    // E8M0 scale bytes of step s for this wave's A rows and B columns; read
-    // one step ahead (through the scalar cache: every index is wave-uniform)
-    // (a byte is fetched as its aligned 32-bit word so the load is scalar)
+    // E8M0 scale bytes of a stage for this wave's A rows and B columns, read
+    // one stage ahead through the scalar cache (every index is wave-uniform;
+    // a byte is fetched as its aligned 32-bit word so the load is scalar).
     auto byte_at = [](const uint8_t* p, int64_t idx) -> int {
         const uint32_t w = *reinterpret_cast<const uint32_t*>(p + (idx & ~(int64_t)3));
         return (int)((w >> ((idx & 3) * 8)) & 0xffu);
     };
-    auto scale_a = [&](int s) -> int {
-        const int kt = s % nk;
-        return byte_at(((s / nk) & 1) ? Asr : Asq, a_tile * nk + kt);
+    int c_kb = 0, c_term = 0;                   // cursor of the stage whose scales come next
+    auto next_scales = [&](int& sa, int& sb) {
+        const int kt = c_kb >> 1;
+        sa = byte_at((c_term & 1) ? Asr : Asq, a_tile * nkt + kt);
+        sb = byte_at((c_term & 2) ? Bsr : Bsq, b_tile * nkt + kt);
+        const int k = c_kb + 1;
+        const int wrap = k == nkb ? 1 : 0;
+        c_kb = wrap ? 0 : k;
+        c_term += wrap;
     };
-    auto scale_b = [&](int s) -> int {
-        const int kt = s % nk;
-        return byte_at(((s / nk) & 2) ? Bsr : Bsq, b_tile * nk + kt);
-    };
-    stage(a_img(0), Kp, m0, 0, smem, wave, lane);
-    stage(b_img(0), Kp, n0, 0, smem + 2 * SLAB, wave, lane);
-    wait_loads();
-    __syncthreads();
 
+    // lane l feeds row l % 32 of each 32-row block, 32 bytes = chunks 2 (l / 32), +1
     const int frag_row = lane & 31;
-    const int frag_c = (lane >> 5) * 2;         // this lane's 2 chunks (32 bytes) of a 64-k sub-step
-    auto load_frags = [&](const uint8_t* sa, const uint8_t* sb, int ks, intx8 (&a)[4],
-                          intx8 (&b)[4]) {
+    const int frag_c = (lane >> 5) * 2;
+    auto load_frags = [&](int slot, intx8 (&a)[4], intx8 (&b)[4]) {
+        const uint8_t* sa = smem + slot * STAGE;
+        const uint8_t* sb = sa + SLAB;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int r = wm * 128 + i * 32 + frag_row;
-            const intx4 lo = *reinterpret_cast<const intx4*>(sa + swz(r, 4 * ks + frag_c));
-            const intx4 hi = *reinterpret_cast<const intx4*>(sa + swz(r, 4 * ks + frag_c + 1));
+            const intx4 lo = *reinterpret_cast<const intx4*>(sa + slab_off(r, frag_c));
+            const intx4 hi = *reinterpret_cast<const intx4*>(sa + slab_off(r, frag_c + 1));
             a[i] = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int r = wn * 128 + j * 32 + frag_row;
-            const intx4 lo = *reinterpret_cast<const intx4*>(sb + swz(r, 4 * ks + frag_c));
-            const intx4 hi = *reinterpret_cast<const intx4*>(sb + swz(r, 4 * ks + frag_c + 1));
+            const intx4 lo = *reinterpret_cast<const intx4*>(sb + slab_off(r, frag_c));
+            const intx4 hi = *reinterpret_cast<const intx4*>(sb + slab_off(r, frag_c + 1));
             b[j] = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
         }
     };
-    auto mfma16 = [&](const intx8 (&a)[4], const intx8 (&b)[4], int sca, int scb) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a[i], b[j], acc[i][j], 0, 0,
-                                                                            0, sca, 0, scb);
+    auto mfma = [&](int idx, const intx8 (&a)[4], const intx8 (&b)[4], int sca, int scb) {
+        const int i = idx >> 2, j = idx & 3;
+        acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a[i], b[j], acc[i][j], 0, 0, 0,
+                                                                    sca, 0, scb);
     };
 
-    // Same stage pipeline as the bf16 kernel with two 64-k sub-steps per
-    // stage: ks 0 carries the next stage's loads and the ks-1 reads; ks 1
-    // waits for the next stage and reads its ks-0 fragments under the MFMAs.
+#pragma unroll
+    for (int p = 0; p < NBUF; ++p) issue();
+    int sca, scb, sca_n, scb_n;
+    next_scales(sca, scb);
+    next_scales(sca_n, scb_n);
+    stage_barrier<NBUF - 1>();
+
+    // One stage = 16 MFMAs on the fragments of slot `cur` (register set P):
+    // one MFMA, stage barrier (stage s + 1 landed, slot `cur` free), then the
+    // loads of stage s + NBUF into slot `cur` and the 16 reads of stage s + 1
+    // into set P ^ 1 under the other 15 MFMAs.
     intx8 fa[2][4], fb[2][4];
-    load_frags(smem, smem + 2 * SLAB, 0, fa[0], fb[0]);
-    int sca_next = scale_a(0), scb_next = scale_b(0);
+    load_frags(0, fa[0], fb[0]);
+    int cur = 0;
     __builtin_amdgcn_sched_barrier(0);
-    auto one_stage = [&](int s, auto more_tag) {
+    auto one_stage = [&](auto par_tag, auto more_tag) {
+        constexpr int P = decltype(par_tag)::value;
         constexpr bool MORE = decltype(more_tag)::value;
-        const int cur = s & 1;
-        const uint8_t* sa = smem + cur * SLAB;
-        const uint8_t* sb = smem + (2 + cur) * SLAB;
-        const int sca = sca_next, scb = scb_next;
-        // ks 0
-        if constexpr (MORE) {
-            sca_next = scale_a(s + 1);
-            scb_next = scale_b(s + 1);
-            const int64_t kb = (int64_t)((s + 1) % nk) * ROWB;
-            stage(a_img(s + 1), Kp, m0, kb, smem + (cur ^ 1) * SLAB, wave, lane);
-            stage(b_img(s + 1), Kp, n0, kb, smem + (2 + (cur ^ 1)) * SLAB, wave, lane);
-        }
-        load_frags(sa, sb, 1, fa[1], fb[1]);
-        mfma16(fa[0], fb[0], sca, scb);
-        mfma_schedule<16>();
+        const int nxt = cur + 1 == NBUF ? 0 : cur + 1;
+        mfma(0, fa[P], fb[P], sca, scb);
         __builtin_amdgcn_sched_barrier(0);
-        // ks 1
         if constexpr (MORE) {
-            wait_lds_reads();
-            wait_loads();
-            __syncthreads();
-            load_frags(smem + (cur ^ 1) * SLAB, smem + (2 + (cur ^ 1)) * SLAB, 0, fa[0], fb[0]);
+            stage_barrier<NBUF - 2>();
+            issue();
+            load_frags(nxt, fa[P ^ 1], fb[P ^ 1]);
         }
-        mfma16(fa[1], fb[1], sca, scb);
-        if constexpr (MORE) mfma_schedule<16>();
-        else mfma_schedule<0>();
+#pragma unroll
+        for (int q = 1; q < 16; ++q) mfma(q, fa[P], fb[P], sca, scb);
+        if constexpr (MORE) schedule_loads_reads<2, 15>();
         __builtin_amdgcn_sched_barrier(0);
+        if constexpr (MORE) {
+            sca = sca_n;
+            scb = scb_n;
+            next_scales(sca_n, scb_n);
+        }
+        cur = nxt;
     };
-    for (int s = 0; s + 1 < steps; ++s) one_stage(s, std::true_type{});
-    one_stage(steps - 1, std::false_type{});
+    // steps is even (nkb is even)
+    for (int s = 0; s + 2 < steps; s += 2) {
+        one_stage(std::integral_constant<int, 0>{}, std::true_type{});
+        one_stage(std::integral_constant<int, 1>{}, std::true_type{});
+    }
+    one_stage(std::integral_constant<int, 0>{}, std::true_type{});
+    one_stage(std::integral_constant<int, 1>{}, std::false_type{});
+    __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 15));   // drain the trailing loads
     epilogue(acc, M, N, m0, n0, wm, wn, lane, alpha, beta, C, ldc);
 }
-
-constexpr size_t kSmem = 4 * (size_t)SLAB;   // 131072 bytes
 
 template <int NTERMS>
 hipError_t launch_bf16_terms(int64_t M, int64_t N, int64_t Kp, float alpha, const uint16_t* Ah,
@@ -388,8 +431,10 @@ hipError_t launch_bf16_terms(int64_t M, int64_t N, int64_t Kp, float alpha, cons
         attr = true;
     }
     const int tiles_m = (int)((M + TM - 1) / TM), tiles_n = (int)((N + TN - 1) / TN);
+    const int nkb = (int)(Kp * 2 / kPanelRowBytes);
     hipLaunchKernelGGL(gemm_bf16_tn_kernel<NTERMS>, dim3(tiles_m * tiles_n), dim3(THREADS), kSmem,
-                       stream, M, N, Kp, alpha, Ah, Al, Bh, Bl, beta, C, ldc, tiles_m, tiles_n);
+                       stream, M, N, nkb, alpha, (const uint8_t*)Ah, (const uint8_t*)Al,
+                       (const uint8_t*)Bh, (const uint8_t*)Bl, beta, C, ldc, tiles_m, tiles_n);
     return hipGetLastError();
 }
 
@@ -399,7 +444,7 @@ hipError_t launch_gemm_bf16_tn(int64_t M, int64_t N, int64_t Kp, int nterms, flo
                                const uint16_t* Ah, const uint16_t* Al, const uint16_t* Bh,
                                const uint16_t* Bl, float beta, float* C, int64_t ldc,
                                hipStream_t stream) {
-    if (Kp % 64 || Kp <= 0 || (nterms != 1 && nterms != 3) || (nterms == 3 && (!Al || !Bl)))
+    if (Kp % kBf16TileK || Kp <= 0 || (nterms != 1 && nterms != 3) || (nterms == 3 && (!Al || !Bl)))
         return hipErrorInvalidValue;
     if (nterms == 1) return launch_bf16_terms<1>(M, N, Kp, alpha, Ah, Al, Bh, Bl, beta, C, ldc, stream);
     return launch_bf16_terms<3>(M, N, Kp, alpha, Ah, Al, Bh, Bl, beta, C, ldc, stream);
@@ -410,7 +455,7 @@ hipError_t launch_gemm_fp8r_tn(int64_t M, int64_t N, int64_t Kp, float alpha, co
                                const uint8_t* Bq, const uint8_t* Br, const uint8_t* Bsq,
                                const uint8_t* Bsr, float beta, float* C, int64_t ldc,
                                hipStream_t stream) {
-    if (Kp % 128 || Kp <= 0) return hipErrorInvalidValue;
+    if (Kp % kFp8TileK || Kp <= 0) return hipErrorInvalidValue;
     static bool attr = false;
     if (!attr) {
         hipError_t e = hipFuncSetAttribute((const void*)gemm_fp8r_tn_kernel,
@@ -419,8 +464,9 @@ hipError_t launch_gemm_fp8r_tn(int64_t M, int64_t N, int64_t Kp, float alpha, co
         attr = true;
     }
     const int tiles_m = (int)((M + TM - 1) / TM), tiles_n = (int)((N + TN - 1) / TN);
+    const int nkb = (int)(Kp / kPanelRowBytes);
     hipLaunchKernelGGL(gemm_fp8r_tn_kernel, dim3(tiles_m * tiles_n), dim3(THREADS), kSmem, stream,
-                       M, N, Kp, alpha, Aq, Ar, Asq, Asr, Bq, Br, Bsq, Bsr, beta, C, ldc, tiles_m,
+                       M, N, nkb, alpha, Aq, Ar, Asq, Asr, Bq, Br, Bsq, Bsr, beta, C, ldc, tiles_m,
                        tiles_n);
     return hipGetLastError();
 }

@@ -42,9 +42,10 @@ hipError_t launch_scale_c(int64_t M, int64_t N, float beta, float* C, int64_t ld
                           hipStream_t stream);
 
 // ---- operand pre-pass -------------------------------------------------------
-// Padded, K-contiguous operand images used by the MFMA kernels:
-//   A  (M x K, ld lda)  ->  Ah / Al  (Mp x Kp bf16, row-major)
-//   B  (K x N, ld ldb)  ->  Bh / Bl  (Np x Kp bf16, i.e. B transposed)
+// Padded, K-contiguous operand images used by the MFMA kernels, in the panel
+// layout of common.h (Mp, Np multiples of 256, Kp a multiple of 64):
+//   A  (M x K, ld lda)  ->  Ah / Al  (Mp rows x Kp bf16)
+//   B  (K x N, ld ldb)  ->  Bh / Bl  (Np rows x Kp bf16, i.e. B transposed)
 // Padding rows / columns are zero.  lo pointers may be null (bf16 only).
 hipError_t launch_split_a_bf16(int64_t M, int64_t K, const float* A, int64_t lda,
                                int64_t Mp, int64_t Kp, uint16_t* hi, uint16_t* lo,
@@ -58,13 +59,14 @@ hipError_t launch_split_bf16_plain(int64_t rows, int64_t cols, const float* X, i
 
 // E4M3 tile quantisation with one residual pass, 128 x 128 tiles.
 //   transpose = false: X is rows x cols (ld ldx); q/rq are out_rows x out_cols with
-//                      out_rows >= rows, out_cols >= cols (row-major, ld out_cols);
+//                      out_rows >= rows, out_cols >= cols (row-major, ld out_cols,
+//                      or with tiled = true a panel image, out_rows % 256 == 0);
 //                      scales are indexed [row_tile * (out_cols/128) + col_tile].
 //   transpose = true:  q/rq receive X transposed (out_rows >= cols, out_cols >= rows),
 //                      scales indexed [col_tile_of_X * (out_cols/128) + row_tile_of_X].
 // Padding in q/rq is written as zero codes (scale bytes of all-padding tiles 127).
 hipError_t launch_quant_fp8(int64_t rows, int64_t cols, const float* X, int64_t ldx,
-                            bool transpose, int64_t out_rows, int64_t out_cols,
+                            bool transpose, bool tiled, int64_t out_rows, int64_t out_cols,
                             uint8_t* q, uint8_t* qscale, uint8_t* rq, uint8_t* rscale,
                             hipStream_t stream);
 

@@ -1,6 +1,6 @@
 // Operand pre-pass kernels for the MFMA variants.  They read the FP32
-// operands once and write K-contiguous, zero-padded images the GEMM kernels
-// can stream without bounds checks:
+// operands once and write K-contiguous, zero-padded panel images (layout in
+// common.h) the GEMM kernels stream without bounds checks:
 //
 //   bf16 split:   hi = RNE_bf16(x), lo = RNE_bf16(x - hi)   (x - hi is exact in FP32)
 //   E4M3 quant:   per 128 x 128 tile, e = the largest integer with
@@ -32,17 +32,22 @@ __device__ __forceinline__ void split1(float x, uint16_t& hi, uint16_t& lo) {
 }
 
 // ---------------------------------------------------------------------------
-// A (M x K, lda) -> hi/lo (Mp x Kp), 8 consecutive k per lane.
+// A (M x K, lda) -> hi/lo panel images (Mp rows, Kp bf16 per row).  One lane
+// per 16-byte image chunk (8 consecutive k), lanes in image order: the writes
+// are contiguous and each group of 4 lanes reads 32 consecutive floats of a row.
 template <bool VEC>
 __global__ void split_a_kernel(int64_t M, int64_t K, const float* __restrict__ A, int64_t lda,
                                int64_t Mp, int64_t Kp, uint16_t* __restrict__ hi,
                                uint16_t* __restrict__ lo) {
-    const int64_t per_row = Kp / 8;
-    const int64_t total = Mp * per_row;
+    const int64_t nkb = Kp * 2 / kPanelRowBytes;
+    const int64_t total = Mp * (Kp / 8);
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t r = e / per_row;
-        const int64_t k = (e - r * per_row) * 8;
+        const int64_t blk = e >> 10;            // 1024 chunks per 16 KiB block
+        const int w = (int)(e & 1023), rr = w >> 2, pos = w & 3;
+        const int64_t rb = blk / nkb, kb = blk - rb * nkb;
+        const int64_t r = rb * kPanelRows + rr;
+        const int64_t k = kb * 32 + (int64_t)((pos ^ ((rr >> 2) & 3)) * 8);
         float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         if (r < M) {
             const float* p = A + r * lda + k;
@@ -63,16 +68,17 @@ __global__ void split_a_kernel(int64_t M, int64_t K, const float* __restrict__ A
         uint4 hv, lv;
         hv.x = h[0] | ((uint32_t)h[1] << 16); hv.y = h[2] | ((uint32_t)h[3] << 16);
         hv.z = h[4] | ((uint32_t)h[5] << 16); hv.w = h[6] | ((uint32_t)h[7] << 16);
-        *reinterpret_cast<uint4*>(hi + r * Kp + k) = hv;
+        *reinterpret_cast<uint4*>(hi + e * 8) = hv;
         if (lo) {
             lv.x = l[0] | ((uint32_t)l[1] << 16); lv.y = l[2] | ((uint32_t)l[3] << 16);
             lv.z = l[4] | ((uint32_t)l[5] << 16); lv.w = l[6] | ((uint32_t)l[7] << 16);
-            *reinterpret_cast<uint4*>(lo + r * Kp + k) = lv;
+            *reinterpret_cast<uint4*>(lo + e * 8) = lv;
         }
     }
 }
 
-// B (K x N, ldb) -> hi/lo transposed (Np x Kp); one 64 x 64 tile per workgroup.
+// B (K x N, ldb) -> hi/lo transposed panel images (Np rows, Kp bf16 per row);
+// one 64 x 64 tile per workgroup.
 template <bool VEC>
 __global__ __launch_bounds__(256) void split_bt_kernel(int64_t K, int64_t N,
                                                        const float* __restrict__ B, int64_t ldb,
@@ -113,7 +119,11 @@ __global__ __launch_bounds__(256) void split_bt_kernel(int64_t K, int64_t N,
     uint16_t h[16], l[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) split1(T[kb + i][nl], h[i], l[i]);
-    uint16_t* ph = hi + (n0 + nl) * Kp + k0 + kb;
+    const int64_t nkb = Kp * 2 / kPanelRowBytes;
+    // image byte offsets of this lane's two 8-k chunks
+    const int64_t o0 = panel_offset(n0 + nl, (k0 + kb) * 2, nkb);
+    const int64_t o1 = panel_offset(n0 + nl, (k0 + kb + 8) * 2, nkb);
+    uint8_t* ph = reinterpret_cast<uint8_t*>(hi);
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
         uint4 hv;
@@ -121,10 +131,10 @@ __global__ __launch_bounds__(256) void split_bt_kernel(int64_t K, int64_t N,
         hv.y = h[8 * q + 2] | ((uint32_t)h[8 * q + 3] << 16);
         hv.z = h[8 * q + 4] | ((uint32_t)h[8 * q + 5] << 16);
         hv.w = h[8 * q + 6] | ((uint32_t)h[8 * q + 7] << 16);
-        *reinterpret_cast<uint4*>(ph + 8 * q) = hv;
+        *reinterpret_cast<uint4*>(ph + (q ? o1 : o0)) = hv;
     }
     if (lo) {
-        uint16_t* pl = lo + (n0 + nl) * Kp + k0 + kb;
+        uint8_t* pl = reinterpret_cast<uint8_t*>(lo);
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             uint4 lv;
@@ -132,7 +142,7 @@ __global__ __launch_bounds__(256) void split_bt_kernel(int64_t K, int64_t N,
             lv.y = l[8 * q + 2] | ((uint32_t)l[8 * q + 3] << 16);
             lv.z = l[8 * q + 4] | ((uint32_t)l[8 * q + 5] << 16);
             lv.w = l[8 * q + 6] | ((uint32_t)l[8 * q + 7] << 16);
-            *reinterpret_cast<uint4*>(pl + 8 * q) = lv;
+            *reinterpret_cast<uint4*>(pl + (q ? o1 : o0)) = lv;
         }
     }
 }
@@ -210,8 +220,10 @@ __device__ __forceinline__ float block_max(float v, float* red, bool& any_nan_in
 }
 
 // One 128 x 128 output tile per workgroup of 256 lanes.  Lane t holds rows
-// 8 i + t/32 (i = 0..15) and columns 4 (t % 32) .. +3 of the X tile.
-template <bool VEC, bool TRANS>
+// 8 i + t/32 (i = 0..15) and columns 4 (t % 32) .. +3 of the X tile.  The
+// code images are row-major out_rows x out_cols (TILED false) or panel images
+// with out_cols bytes of K per row (TILED true).
+template <bool VEC, bool TRANS, bool TILED>
 __global__ __launch_bounds__(256) void quant_fp8_kernel(
     int64_t rows, int64_t cols, const float* __restrict__ X, int64_t ldx, int64_t out_cols,
     uint8_t* __restrict__ q, uint8_t* __restrict__ qscale, uint8_t* __restrict__ rq,
@@ -221,6 +233,10 @@ __global__ __launch_bounds__(256) void quant_fp8_kernel(
     __shared__ uint32_t tr[128][33];
     const int t = threadIdx.x;
     const int64_t ot_cols = out_cols / 128;
+    const int64_t nkb = out_cols / kPanelRowBytes;
+    auto out_off = [&](int64_t orow, int64_t ocol) -> int64_t {
+        return TILED ? panel_offset(orow, ocol, nkb) : orow * out_cols + ocol;
+    };
     const int64_t ot_r = blockIdx.x / ot_cols, ot_c = blockIdx.x % ot_cols;
     // tile origin in X coordinates
     const int64_t x_r0 = TRANS ? ot_c * 128 : ot_r * 128;
@@ -297,8 +313,9 @@ __global__ __launch_bounds__(256) void quant_fp8_kernel(
         for (int i = 0; i < 16; ++i) {
             const int64_t orow = ot_r * 128 + 8 * i + (t >> 5);
             const int64_t ocol = ot_c * 128 + cl;
-            *reinterpret_cast<uint32_t*>(q + orow * out_cols + ocol) = qw[i];
-            *reinterpret_cast<uint32_t*>(rq + orow * out_cols + ocol) = rw[i];
+            const int64_t o = out_off(orow, ocol);
+            *reinterpret_cast<uint32_t*>(q + o) = qw[i];
+            *reinterpret_cast<uint32_t*>(rq + o) = rw[i];
         }
     } else {
         // out[x_col][x_row]: stage bytes by column, then write rows of 128 bytes
@@ -317,8 +334,6 @@ __global__ __launch_bounds__(256) void quant_fp8_kernel(
         __syncthreads();
         const int oc = t >> 1;            // output row within the tile (= X column)
         const int half = (t & 1) * 64;    // 64 bytes of that row
-        uint8_t* dq = q + (ot_r * 128 + oc) * out_cols + ot_c * 128 + half;
-        uint8_t* dr = rq + (ot_r * 128 + oc) * out_cols + ot_c * 128 + half;
 #pragma unroll
         for (int w = 0; w < 4; ++w) {
             uint4 a, b;
@@ -326,8 +341,9 @@ __global__ __launch_bounds__(256) void quant_fp8_kernel(
             const uint32_t* srcr = &tr[oc][(half + 16 * w) / 4];
             a.x = srcq[0]; a.y = srcq[1]; a.z = srcq[2]; a.w = srcq[3];
             b.x = srcr[0]; b.y = srcr[1]; b.z = srcr[2]; b.w = srcr[3];
-            *reinterpret_cast<uint4*>(dq + 16 * w) = a;
-            *reinterpret_cast<uint4*>(dr + 16 * w) = b;
+            const int64_t o = out_off(ot_r * 128 + oc, ot_c * 128 + half + 16 * w);
+            *reinterpret_cast<uint4*>(q + o) = a;
+            *reinterpret_cast<uint4*>(rq + o) = b;
         }
     }
 }
@@ -375,27 +391,29 @@ hipError_t launch_split_bf16_plain(int64_t rows, int64_t cols, const float* X, i
 }
 
 hipError_t launch_quant_fp8(int64_t rows, int64_t cols, const float* X, int64_t ldx,
-                            bool transpose, int64_t out_rows, int64_t out_cols, uint8_t* q,
-                            uint8_t* qscale, uint8_t* rq, uint8_t* rscale, hipStream_t stream) {
+                            bool transpose, bool tiled, int64_t out_rows, int64_t out_cols,
+                            uint8_t* q, uint8_t* qscale, uint8_t* rq, uint8_t* rscale,
+                            hipStream_t stream) {
     if ((out_rows % 128) || (out_cols % 128)) return hipErrorInvalidValue;
+    if (tiled && (out_rows % kPanelRows)) return hipErrorInvalidValue;
     if (transpose ? (out_rows < cols || out_cols < rows) : (out_rows < rows || out_cols < cols))
         return hipErrorInvalidValue;
     const bool vec = (ldx % 4 == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
     const unsigned g = (unsigned)((out_rows / 128) * (out_cols / 128));
-    if (transpose) {
-        if (vec)
-            hipLaunchKernelGGL((quant_fp8_kernel<true, true>), dim3(g), dim3(256), 0, stream, rows,
-                               cols, X, ldx, out_cols, q, qscale, rq, rscale);
-        else
-            hipLaunchKernelGGL((quant_fp8_kernel<false, true>), dim3(g), dim3(256), 0, stream,
-                               rows, cols, X, ldx, out_cols, q, qscale, rq, rscale);
-    } else {
-        if (vec)
-            hipLaunchKernelGGL((quant_fp8_kernel<true, false>), dim3(g), dim3(256), 0, stream,
-                               rows, cols, X, ldx, out_cols, q, qscale, rq, rscale);
-        else
-            hipLaunchKernelGGL((quant_fp8_kernel<false, false>), dim3(g), dim3(256), 0, stream,
-                               rows, cols, X, ldx, out_cols, q, qscale, rq, rscale);
+    auto go = [&](auto kernel) {
+        hipLaunchKernelGGL(kernel, dim3(g), dim3(256), 0, stream, rows, cols, X, ldx, out_cols, q,
+                           qscale, rq, rscale);
+    };
+    const int sel = (vec ? 4 : 0) | (transpose ? 2 : 0) | (tiled ? 1 : 0);
+    switch (sel) {
+        case 0: go(quant_fp8_kernel<false, false, false>); break;
+        case 1: go(quant_fp8_kernel<false, false, true>); break;
+        case 2: go(quant_fp8_kernel<false, true, false>); break;
+        case 3: go(quant_fp8_kernel<false, true, true>); break;
+        case 4: go(quant_fp8_kernel<true, false, false>); break;
+        case 5: go(quant_fp8_kernel<true, false, true>); break;
+        case 6: go(quant_fp8_kernel<true, true, false>); break;
+        default: go(quant_fp8_kernel<true, true, true>); break;
     }
     return hipGetLastError();
 }

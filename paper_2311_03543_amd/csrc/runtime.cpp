@@ -340,13 +340,13 @@ int v_fp8r(const void* args, void* ws, size_t, void* stream, void* user) {
     uint8_t* Bsr = p;
     {
         KTimer kt(c, s, "quant_fp8_a");
-        if (cmp::launch_quant_fp8(a->M, a->K, a->A, a->lda, false, L.Mp, L.Kp, Aq, Asq, Ar, Asr, s) !=
+        if (cmp::launch_quant_fp8(a->M, a->K, a->A, a->lda, false, true, L.Mp, L.Kp, Aq, Asq, Ar, Asr, s) !=
             hipSuccess)
             return CMP_EHIP;
     }
     {
         KTimer kt(c, s, "quant_fp8_bt");
-        if (cmp::launch_quant_fp8(a->K, a->N, a->B, a->ldb, true, L.Np, L.Kp, Bq, Bsq, Br, Bsr, s) !=
+        if (cmp::launch_quant_fp8(a->K, a->N, a->B, a->ldb, true, true, L.Np, L.Kp, Bq, Bsq, Br, Bsr, s) !=
             hipSuccess)
             return CMP_EHIP;
     }
@@ -1589,14 +1589,14 @@ CMP_API int cmp_quant_fp8(cmp_ctx* c, int64_t rows, int64_t cols, const float* X
         auto* s1 = r2 + (size_t)rp * cp;
         auto* s2 = s1 + (size_t)(rp / 128) * (cp / 128);
         auto s = (hipStream_t)stream;
-        HIP_TRY(c, cmp::launch_quant_fp8(rows, cols, X, ldx, false, rp, cp, q2, s1, r2, s2, s));
+        HIP_TRY(c, cmp::launch_quant_fp8(rows, cols, X, ldx, false, false, rp, cp, q2, s1, r2, s2, s));
         HIP_TRY(c, hipMemcpy2DAsync(q, cols, q2, cp, cols, rows, hipMemcpyDeviceToDevice, s));
         HIP_TRY(c, hipMemcpy2DAsync(rq, cols, r2, cp, cols, rows, hipMemcpyDeviceToDevice, s));
         HIP_TRY(c, hipMemcpyAsync(qs, s1, (size_t)(rp / 128) * (cp / 128), hipMemcpyDeviceToDevice, s));
         HIP_TRY(c, hipMemcpyAsync(rs, s2, (size_t)(rp / 128) * (cp / 128), hipMemcpyDeviceToDevice, s));
         return CMP_OK;
     }
-    HIP_TRY(c, cmp::launch_quant_fp8(rows, cols, X, ldx, false, rows, cols, q, qs, rq, rs,
+    HIP_TRY(c, cmp::launch_quant_fp8(rows, cols, X, ldx, false, false, rows, cols, q, qs, rq, rs,
                                      (hipStream_t)stream));
     return CMP_OK;
 }
