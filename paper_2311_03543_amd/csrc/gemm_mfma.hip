@@ -71,43 +71,18 @@ __device__ __forceinline__ void stage_barrier() {
     asm volatile("" ::: "memory");
 }
 
-// Four 1 KiB linear copies: this wave's quarter (4 KiB) of one slab.
-// `src` already holds the wave's and the lane's offset (wave * 4 KiB + 16 lane),
-// `dst` the wave's slab quarter; lane l lands at dst + offset + 16 l.
-__device__ __forceinline__ void dma_quarter(const uint8_t* src, uint8_t* dst) {
-    __builtin_amdgcn_global_load_lds((gptr_t)src, (lptr_t)dst, 16, 0, 0);
-    __builtin_amdgcn_global_load_lds((gptr_t)src, (lptr_t)dst, 16, 1024, 0);
-    __builtin_amdgcn_global_load_lds((gptr_t)src, (lptr_t)dst, 16, 2048, 0);
-    __builtin_amdgcn_global_load_lds((gptr_t)src, (lptr_t)dst, 16, 3072, 0);
+// One 1 KiB linear copy, part P (0..3) of this wave's quarter (4 KiB) of a
+// slab.  `src` already holds the wave's and the lane's offset (wave * 4 KiB +
+// 16 lane), `dst` the wave's slab quarter; lane l lands at dst + 1024 P + 16 l.
+template <int P>
+__device__ __forceinline__ void dma_part(const uint8_t* src, uint8_t* dst) {
+    __builtin_amdgcn_global_load_lds((gptr_t)src, (lptr_t)dst, 16, P * 1024, 0);
 }
 
-// Scheduling masks of __builtin_amdgcn_sched_group_barrier.
-constexpr int kSchedMfma = 0x008, kSchedVmem = 0x010, kSchedDsRead = 0x100;
-
-// Interleave: READS LDS reads one-for-one under the first MFMAs of a run of
-// MFMAS, the rest of the MFMAs after.
-template <int READS, int MFMAS>
-__device__ __forceinline__ void schedule_reads() {
-#pragma unroll
-    for (int r = 0; r < READS; ++r) {
-        __builtin_amdgcn_sched_group_barrier(kSchedMfma, 1, 0);
-        __builtin_amdgcn_sched_group_barrier(kSchedDsRead, 1, 0);
-    }
-    if constexpr (MFMAS > READS) __builtin_amdgcn_sched_group_barrier(kSchedMfma, MFMAS - READS, 0);
-}
-
-// Interleave after a stage barrier: per MFMA one slab load and RPM LDS reads,
-// for the first 8 MFMAs (8 loads, 8 * RPM reads), the rest of the MFMAs after.
-template <int RPM, int MFMAS>
-__device__ __forceinline__ void schedule_loads_reads() {
-#pragma unroll
-    for (int r = 0; r < 8; ++r) {
-        __builtin_amdgcn_sched_group_barrier(kSchedMfma, 1, 0);
-        __builtin_amdgcn_sched_group_barrier(kSchedVmem, 1, 0);
-        __builtin_amdgcn_sched_group_barrier(kSchedDsRead, RPM, 0);
-    }
-    if constexpr (MFMAS > 8) __builtin_amdgcn_sched_group_barrier(kSchedMfma, MFMAS - 8, 0);
-}
+// The main loops pin their instruction order explicitly: each MFMA is
+// followed by the memory instructions that ride under it, and a
+// sched_barrier after each group keeps the scheduler from clustering them.
+__device__ __forceinline__ void pin() { __builtin_amdgcn_sched_barrier(0); }
 
 // 32 x 32 accumulator block layout: lane l holds column l % 32 and rows
 // 8 (r / 4) + 4 (l / 32) + (r % 4), r = 0..15.
@@ -208,70 +183,110 @@ void gemm_bf16_tn_kernel(int64_t M, int64_t N, int nkb, float alpha,
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-    // term 0 = hi.hi, 1 = hi.lo, 2 = lo.hi
+    // Load cursor: term 0 = hi.hi, 1 = hi.lo, 2 = lo.hi.  The per-stage
+    // source pointers and slot are computed once (after the stage barrier);
+    // the 8 copies are then issued one per MFMA.
     LoadCursor ld(steps);
-    auto issue = [&]() {
+    const uint8_t* dsa = nullptr;
+    const uint8_t* dsb = nullptr;
+    uint8_t* dd = nullptr;
+    auto prepare = [&]() {
         const int64_t kofs = (int64_t)ld.kb * SLAB;
-        uint8_t* dst = smem + ld.slot * STAGE + wave * 4096;
-        dma_quarter((ld.term == 2 ? a_lo : a_hi) + kofs, dst);
-        dma_quarter((ld.term == 1 ? b_lo : b_hi) + kofs, dst + SLAB);
+        dsa = (ld.term == 2 ? a_lo : a_hi) + kofs;
+        dsb = (ld.term == 1 ? b_lo : b_hi) + kofs;
+        dd = smem + ld.slot * STAGE + wave * 4096;
         ld.advance(nkb);
     };
+    auto copy = [&](auto part_tag) {
+        constexpr int P = decltype(part_tag)::value;
+        if constexpr (P < 4) dma_part<P>(dsa, dd);
+        else dma_part<P - 4>(dsb, dd + SLAB);
+    };
 
-    // lane l feeds row l % 32 of each 32-row block, k-chunk 2 ks + l / 32
+    // lane l feeds row l % 32 of each 32-row block, k-chunk 2 ks + l / 32;
+    // fragment f < 4 is A block f, f >= 4 is B block f - 4
     const int frag_row = lane & 31;
     const int frag_c = lane >> 5;
-    auto load_frags = [&](int slot, int ks, bf16x8 (&a)[4], bf16x8 (&b)[4]) {
-        const uint8_t* sa = smem + slot * STAGE;
-        const uint8_t* sb = sa + SLAB;
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-            a[i] = *reinterpret_cast<const bf16x8*>(sa + slab_off(wm * 128 + i * 32 + frag_row, 2 * ks + frag_c));
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-            b[j] = *reinterpret_cast<const bf16x8*>(sb + slab_off(wn * 128 + j * 32 + frag_row, 2 * ks + frag_c));
+    auto read = [&](int slot, int ks, int f, bf16x8 (&a)[4], bf16x8 (&b)[4]) {
+        const uint8_t* base = smem + slot * STAGE;
+        if (f < 4)
+            a[f] = *reinterpret_cast<const bf16x8*>(base + slab_off(wm * 128 + f * 32 + frag_row, 2 * ks + frag_c));
+        else
+            b[f - 4] = *reinterpret_cast<const bf16x8*>(base + SLAB + slab_off(wn * 128 + (f - 4) * 32 + frag_row, 2 * ks + frag_c));
     };
     auto mfma = [&](int idx, const bf16x8 (&a)[4], const bf16x8 (&b)[4]) {
         const int i = idx >> 2, j = idx & 3;
         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     };
 
+    // prologue: the first NBUF stages in flight, wait for stage 0
 #pragma unroll
-    for (int p = 0; p < NBUF; ++p) issue();
+    for (int p = 0; p < NBUF; ++p) {
+        prepare();
+        copy(std::integral_constant<int, 0>{});
+        copy(std::integral_constant<int, 1>{});
+        copy(std::integral_constant<int, 2>{});
+        copy(std::integral_constant<int, 3>{});
+        copy(std::integral_constant<int, 4>{});
+        copy(std::integral_constant<int, 5>{});
+        copy(std::integral_constant<int, 6>{});
+        copy(std::integral_constant<int, 7>{});
+    }
     stage_barrier<NBUF - 1>();
 
     // One stage = two 16-MFMA sub-steps over slot `cur`:
-    //   ks 0: MFMAs on fa[0]; reads of ks 1 into fa[1] under them
-    //   ks 1: two MFMAs on fa[1]; stage barrier (stage s + 1 landed, slot
-    //         `cur` free); loads of stage s + NBUF into slot `cur` and reads
-    //         of stage s + 1's ks 0 into fa[0] under the other 14 MFMAs.
+    //   ks 0: MFMA q on fa[0], then (q < 8) read fragment q of ks 1 into fa[1]
+    //   ks 1: PRE MFMAs on fa[1]; stage barrier (stage s + 1 landed, slot
+    //         `cur` free); then MFMA q, copy q - PRE of stage s + NBUF into
+    //         slot `cur`, read fragment q - PRE of stage s + 1's ks 0 into fa[0].
     constexpr int PRE = 2;
     bf16x8 fa[2][4], fb[2][4];
-    load_frags(0, 0, fa[0], fb[0]);
+#pragma unroll
+    for (int f = 0; f < 8; ++f) read(0, 0, f, fa[0], fb[0]);
     int cur = 0;
-    __builtin_amdgcn_sched_barrier(0);
+    pin();
     auto one_stage = [&](auto more_tag) {
         constexpr bool MORE = decltype(more_tag)::value;
         const int nxt = cur + 1 == NBUF ? 0 : cur + 1;
         // ks 0
-        load_frags(cur, 1, fa[1], fb[1]);
 #pragma unroll
-        for (int q = 0; q < 16; ++q) mfma(q, fa[0], fb[0]);
-        schedule_reads<8, 16>();
-        __builtin_amdgcn_sched_barrier(0);
+        for (int q = 0; q < 16; ++q) {
+            mfma(q, fa[0], fb[0]);
+            if (q < 8) read(cur, 1, q, fa[1], fb[1]);
+            pin();
+        }
         // ks 1
 #pragma unroll
         for (int q = 0; q < PRE; ++q) mfma(q, fa[1], fb[1]);
-        __builtin_amdgcn_sched_barrier(0);
+        pin();
         if constexpr (MORE) {
             stage_barrier<NBUF - 2>();
-            issue();
-            load_frags(nxt, 0, fa[0], fb[0]);
+            prepare();
         }
-#pragma unroll
-        for (int q = PRE; q < 16; ++q) mfma(q, fa[1], fb[1]);
-        if constexpr (MORE) schedule_loads_reads<1, 16 - PRE>();
-        __builtin_amdgcn_sched_barrier(0);
+        pin();
+        auto step = [&](auto q_tag) {
+            constexpr int Q = decltype(q_tag)::value;
+            mfma(Q, fa[1], fb[1]);
+            if constexpr (MORE && Q - PRE < 8) {
+                copy(std::integral_constant<int, Q - PRE>{});
+                read(nxt, 0, Q - PRE, fa[0], fb[0]);
+            }
+            pin();
+        };
+        step(std::integral_constant<int, 2>{});
+        step(std::integral_constant<int, 3>{});
+        step(std::integral_constant<int, 4>{});
+        step(std::integral_constant<int, 5>{});
+        step(std::integral_constant<int, 6>{});
+        step(std::integral_constant<int, 7>{});
+        step(std::integral_constant<int, 8>{});
+        step(std::integral_constant<int, 9>{});
+        step(std::integral_constant<int, 10>{});
+        step(std::integral_constant<int, 11>{});
+        step(std::integral_constant<int, 12>{});
+        step(std::integral_constant<int, 13>{});
+        step(std::integral_constant<int, 14>{});
+        step(std::integral_constant<int, 15>{});
         cur = nxt;
     };
     for (int s = 0; s + 1 < steps; ++s) one_stage(std::true_type{});
@@ -316,96 +331,134 @@ void gemm_fp8r_tn_kernel(int64_t M, int64_t N, int nkb, float alpha,
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-    // term 0 = q.q, 1 = r.q, 2 = q.r, 3 = r.r
+    // Load cursor: term 0 = q.q, 1 = r.q, 2 = q.r, 3 = r.r.
     LoadCursor ld(steps);
-    auto issue = [&]() {
+    const uint8_t* dsa = nullptr;
+    const uint8_t* dsb = nullptr;
+    uint8_t* dd = nullptr;
+    auto prepare = [&]() {
         const int64_t kofs = (int64_t)ld.kb * SLAB;
-        uint8_t* dst = smem + ld.slot * STAGE + wave * 4096;
-        dma_quarter(((ld.term & 1) ? a_r : a_q) + kofs, dst);
-        dma_quarter(((ld.term & 2) ? b_r : b_q) + kofs, dst + SLAB);
+        dsa = ((ld.term & 1) ? a_r : a_q) + kofs;
+        dsb = ((ld.term & 2) ? b_r : b_q) + kofs;
+        dd = smem + ld.slot * STAGE + wave * 4096;
         ld.advance(nkb);
     };
-
-    // E8M0 scale bytes of a stage for this wave's A rows and B columns, read
-    // one stage ahead through the scalar cache (every index is wave-uniform;
-    // a byte is fetched as its aligned 32-bit word so the load is scalar).
-    auto byte_at = [](const uint8_t* p, int64_t idx) -> int {
-        const uint32_t w = *reinterpret_cast<const uint32_t*>(p + (idx & ~(int64_t)3));
-        return (int)((w >> ((idx & 3) * 8)) & 0xffu);
+    auto copy = [&](auto part_tag) {
+        constexpr int P = decltype(part_tag)::value;
+        if constexpr (P < 4) dma_part<P>(dsa, dd);
+        else dma_part<P - 4>(dsb, dd + SLAB);
     };
-    int c_kb = 0, c_term = 0;                   // cursor of the stage whose scales come next
-    auto next_scales = [&](int& sa, int& sb) {
-        const int kt = c_kb >> 1;
-        sa = byte_at((c_term & 1) ? Asr : Asq, a_tile * nkt + kt);
-        sb = byte_at((c_term & 2) ? Bsr : Bsq, b_tile * nkt + kt);
-        const int k = c_kb + 1;
+
+    // E8M0 scale bytes of a stage for this wave's A rows and B columns.  A
+    // byte is fetched as its aligned 32-bit word so the load is scalar (every
+    // index is wave-uniform); a stage's words are loaded right after the
+    // previous stage's barrier and unpacked at that stage's end.
+    int sc_kb = 0, sc_term = 0;                 // stage whose scale words load next
+    uint32_t wa = 0, wb = 0;
+    int sha = 0, shb = 0;
+    auto load_scale_words = [&]() {
+        const int64_t ia = a_tile * nkt + (sc_kb >> 1), ib = b_tile * nkt + (sc_kb >> 1);
+        wa = *reinterpret_cast<const uint32_t*>(((sc_term & 1) ? Asr : Asq) + (ia & ~(int64_t)3));
+        wb = *reinterpret_cast<const uint32_t*>(((sc_term & 2) ? Bsr : Bsq) + (ib & ~(int64_t)3));
+        sha = (int)(ia & 3) * 8;
+        shb = (int)(ib & 3) * 8;
+        const int k = sc_kb + 1;
         const int wrap = k == nkb ? 1 : 0;
-        c_kb = wrap ? 0 : k;
-        c_term += wrap;
+        sc_kb = __builtin_amdgcn_readfirstlane(wrap ? 0 : k);
+        sc_term = __builtin_amdgcn_readfirstlane(sc_term + wrap);
+    };
+    auto unpack = [&](int& sa, int& sb) {
+        sa = (int)((wa >> sha) & 0xffu);
+        sb = (int)((wb >> shb) & 0xffu);
     };
 
-    // lane l feeds row l % 32 of each 32-row block, 32 bytes = chunks 2 (l / 32), +1
+    // lane l feeds row l % 32 of each 32-row block, 32 bytes = chunks 2 (l / 32)
+    // and 2 (l / 32) + 1; half h < 8 is A block h / 2, h >= 8 is B block h / 2 - 4
     const int frag_row = lane & 31;
     const int frag_c = (lane >> 5) * 2;
-    auto load_frags = [&](int slot, intx8 (&a)[4], intx8 (&b)[4]) {
-        const uint8_t* sa = smem + slot * STAGE;
-        const uint8_t* sb = sa + SLAB;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int r = wm * 128 + i * 32 + frag_row;
-            const intx4 lo = *reinterpret_cast<const intx4*>(sa + slab_off(r, frag_c));
-            const intx4 hi = *reinterpret_cast<const intx4*>(sa + slab_off(r, frag_c + 1));
-            a[i] = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int r = wn * 128 + j * 32 + frag_row;
-            const intx4 lo = *reinterpret_cast<const intx4*>(sb + slab_off(r, frag_c));
-            const intx4 hi = *reinterpret_cast<const intx4*>(sb + slab_off(r, frag_c + 1));
-            b[j] = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
-        }
+    intx4 ha[2][8], hb[2][8];                   // fragment halves, two register sets
+    auto read = [&](int slot, int h, intx4 (&a)[8], intx4 (&b)[8]) {
+        const uint8_t* base = smem + slot * STAGE;
+        const int blk = h >> 1, c = frag_c + (h & 1);
+        if (blk < 4)
+            a[h] = *reinterpret_cast<const intx4*>(base + slab_off(wm * 128 + blk * 32 + frag_row, c));
+        else
+            b[h - 8] = *reinterpret_cast<const intx4*>(base + SLAB + slab_off(wn * 128 + (blk - 4) * 32 + frag_row, c));
     };
-    auto mfma = [&](int idx, const intx8 (&a)[4], const intx8 (&b)[4], int sca, int scb) {
+    auto mfma = [&](int idx, const intx4 (&a)[8], const intx4 (&b)[8], int sca, int scb) {
         const int i = idx >> 2, j = idx & 3;
-        acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a[i], b[j], acc[i][j], 0, 0, 0,
+        const intx8 av = __builtin_shufflevector(a[2 * i], a[2 * i + 1], 0, 1, 2, 3, 4, 5, 6, 7);
+        const intx8 bv = __builtin_shufflevector(b[2 * j], b[2 * j + 1], 0, 1, 2, 3, 4, 5, 6, 7);
+        acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, acc[i][j], 0, 0, 0,
                                                                     sca, 0, scb);
     };
 
+    // prologue: the first NBUF stages in flight, stage 0's scales, wait for stage 0
 #pragma unroll
-    for (int p = 0; p < NBUF; ++p) issue();
-    int sca, scb, sca_n, scb_n;
-    next_scales(sca, scb);
-    next_scales(sca_n, scb_n);
+    for (int p = 0; p < NBUF; ++p) {
+        prepare();
+        copy(std::integral_constant<int, 0>{});
+        copy(std::integral_constant<int, 1>{});
+        copy(std::integral_constant<int, 2>{});
+        copy(std::integral_constant<int, 3>{});
+        copy(std::integral_constant<int, 4>{});
+        copy(std::integral_constant<int, 5>{});
+        copy(std::integral_constant<int, 6>{});
+        copy(std::integral_constant<int, 7>{});
+    }
+    int sca, scb;
+    load_scale_words();
+    unpack(sca, scb);
     stage_barrier<NBUF - 1>();
+#pragma unroll
+    for (int h = 0; h < 16; ++h) read(0, h, ha[0], hb[0]);
+    int cur = 0;
+    pin();
 
     // One stage = 16 MFMAs on the fragments of slot `cur` (register set P):
-    // one MFMA, stage barrier (stage s + 1 landed, slot `cur` free), then the
-    // loads of stage s + NBUF into slot `cur` and the 16 reads of stage s + 1
-    // into set P ^ 1 under the other 15 MFMAs.
-    intx8 fa[2][4], fb[2][4];
-    load_frags(0, fa[0], fb[0]);
-    int cur = 0;
-    __builtin_amdgcn_sched_barrier(0);
+    // one MFMA, stage barrier (stage s + 1 landed, slot `cur` free), the
+    // scale words of stage s + 1, then MFMA q followed by copy q - 1 of stage
+    // s + NBUF into slot `cur` and reads 2 (q - 1), +1 of stage s + 1 into set
+    // P ^ 1 (q = 1..8), then the remaining MFMAs.
     auto one_stage = [&](auto par_tag, auto more_tag) {
         constexpr int P = decltype(par_tag)::value;
         constexpr bool MORE = decltype(more_tag)::value;
         const int nxt = cur + 1 == NBUF ? 0 : cur + 1;
-        mfma(0, fa[P], fb[P], sca, scb);
-        __builtin_amdgcn_sched_barrier(0);
+        mfma(0, ha[P], hb[P], sca, scb);
+        pin();
         if constexpr (MORE) {
             stage_barrier<NBUF - 2>();
-            issue();
-            load_frags(nxt, fa[P ^ 1], fb[P ^ 1]);
+            prepare();
+            load_scale_words();
         }
-#pragma unroll
-        for (int q = 1; q < 16; ++q) mfma(q, fa[P], fb[P], sca, scb);
-        if constexpr (MORE) schedule_loads_reads<2, 15>();
-        __builtin_amdgcn_sched_barrier(0);
-        if constexpr (MORE) {
-            sca = sca_n;
-            scb = scb_n;
-            next_scales(sca_n, scb_n);
-        }
+        pin();
+        auto step = [&](auto q_tag) {
+            constexpr int Q = decltype(q_tag)::value;
+            mfma(Q, ha[P], hb[P], sca, scb);
+            if constexpr (MORE && Q <= 8) {
+                copy(std::integral_constant<int, Q - 1>{});
+                read(nxt, 2 * (Q - 1), ha[P ^ 1], hb[P ^ 1]);
+                read(nxt, 2 * (Q - 1) + 1, ha[P ^ 1], hb[P ^ 1]);
+            }
+            pin();
+        };
+        step(std::integral_constant<int, 1>{});
+        step(std::integral_constant<int, 2>{});
+        step(std::integral_constant<int, 3>{});
+        step(std::integral_constant<int, 4>{});
+        step(std::integral_constant<int, 5>{});
+        step(std::integral_constant<int, 6>{});
+        step(std::integral_constant<int, 7>{});
+        step(std::integral_constant<int, 8>{});
+        step(std::integral_constant<int, 9>{});
+        step(std::integral_constant<int, 10>{});
+        step(std::integral_constant<int, 11>{});
+        step(std::integral_constant<int, 12>{});
+        step(std::integral_constant<int, 13>{});
+        step(std::integral_constant<int, 14>{});
+        step(std::integral_constant<int, 15>{});
+        if constexpr (MORE) unpack(sca, scb);
+        pin();
         cur = nxt;
     };
     // steps is even (nkb is even)
