@@ -76,6 +76,7 @@ __device__ __forceinline__ void stage_barrier() {
 // 16 lane), `dst` the wave's slab quarter; lane l lands at dst + 1024 P + 16 l.
 template <int P>
 __device__ __forceinline__ void dma_part(const uint8_t* src, uint8_t* dst) {
+    static_assert(P >= 0 && P < 4, "part of a 4 KiB quarter");
     __builtin_amdgcn_global_load_lds((gptr_t)src, (lptr_t)dst, 16, P * 1024, 0);
 }
 
@@ -83,6 +84,15 @@ __device__ __forceinline__ void dma_part(const uint8_t* src, uint8_t* dst) {
 // followed by the memory instructions that ride under it, and a
 // sched_barrier after each group keeps the scheduler from clustering them.
 __device__ __forceinline__ void pin() { __builtin_amdgcn_sched_barrier(0); }
+
+// f(integral_constant<int, I>) for I = B .. E - 1, unrolled at compile time.
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
 
 // 32 x 32 accumulator block layout: lane l holds column l % 32 and rows
 // 8 (r / 4) + 4 (l / 32) + (r % 4), r = 0..15.
@@ -199,6 +209,7 @@ void gemm_bf16_tn_kernel(int64_t M, int64_t N, int nkb, float alpha,
     };
     auto copy = [&](auto part_tag) {
         constexpr int P = decltype(part_tag)::value;
+        static_assert(P >= 0 && P < 8, "a stage is 8 copies");
         if constexpr (P < 4) dma_part<P>(dsa, dd);
         else dma_part<P - 4>(dsb, dd + SLAB);
     };
@@ -223,14 +234,7 @@ void gemm_bf16_tn_kernel(int64_t M, int64_t N, int nkb, float alpha,
 #pragma unroll
     for (int p = 0; p < NBUF; ++p) {
         prepare();
-        copy(std::integral_constant<int, 0>{});
-        copy(std::integral_constant<int, 1>{});
-        copy(std::integral_constant<int, 2>{});
-        copy(std::integral_constant<int, 3>{});
-        copy(std::integral_constant<int, 4>{});
-        copy(std::integral_constant<int, 5>{});
-        copy(std::integral_constant<int, 6>{});
-        copy(std::integral_constant<int, 7>{});
+        static_for<0, 8>(copy);
     }
     stage_barrier<NBUF - 1>();
 
@@ -240,6 +244,7 @@ void gemm_bf16_tn_kernel(int64_t M, int64_t N, int nkb, float alpha,
     //         `cur` free); then MFMA q, copy q - PRE of stage s + NBUF into
     //         slot `cur`, read fragment q - PRE of stage s + 1's ks 0 into fa[0].
     constexpr int PRE = 2;
+    static_assert(PRE >= 1 && PRE + 8 <= 16, "the 8 copies and reads ride under MFMAs PRE .. PRE + 7");
     bf16x8 fa[2][4], fb[2][4];
 #pragma unroll
     for (int f = 0; f < 8; ++f) read(0, 0, f, fa[0], fb[0]);
@@ -273,20 +278,7 @@ void gemm_bf16_tn_kernel(int64_t M, int64_t N, int nkb, float alpha,
             }
             pin();
         };
-        step(std::integral_constant<int, 2>{});
-        step(std::integral_constant<int, 3>{});
-        step(std::integral_constant<int, 4>{});
-        step(std::integral_constant<int, 5>{});
-        step(std::integral_constant<int, 6>{});
-        step(std::integral_constant<int, 7>{});
-        step(std::integral_constant<int, 8>{});
-        step(std::integral_constant<int, 9>{});
-        step(std::integral_constant<int, 10>{});
-        step(std::integral_constant<int, 11>{});
-        step(std::integral_constant<int, 12>{});
-        step(std::integral_constant<int, 13>{});
-        step(std::integral_constant<int, 14>{});
-        step(std::integral_constant<int, 15>{});
+        static_for<PRE, 16>(step);
         cur = nxt;
     };
     for (int s = 0; s + 1 < steps; ++s) one_stage(std::true_type{});
@@ -345,6 +337,7 @@ void gemm_fp8r_tn_kernel(int64_t M, int64_t N, int nkb, float alpha,
     };
     auto copy = [&](auto part_tag) {
         constexpr int P = decltype(part_tag)::value;
+        static_assert(P >= 0 && P < 8, "a stage is 8 copies");
         if constexpr (P < 4) dma_part<P>(dsa, dd);
         else dma_part<P - 4>(dsb, dd + SLAB);
     };
@@ -397,14 +390,7 @@ void gemm_fp8r_tn_kernel(int64_t M, int64_t N, int nkb, float alpha,
 #pragma unroll
     for (int p = 0; p < NBUF; ++p) {
         prepare();
-        copy(std::integral_constant<int, 0>{});
-        copy(std::integral_constant<int, 1>{});
-        copy(std::integral_constant<int, 2>{});
-        copy(std::integral_constant<int, 3>{});
-        copy(std::integral_constant<int, 4>{});
-        copy(std::integral_constant<int, 5>{});
-        copy(std::integral_constant<int, 6>{});
-        copy(std::integral_constant<int, 7>{});
+        static_for<0, 8>(copy);
     }
     int sca, scb;
     load_scale_words();
@@ -442,21 +428,7 @@ void gemm_fp8r_tn_kernel(int64_t M, int64_t N, int nkb, float alpha,
             }
             pin();
         };
-        step(std::integral_constant<int, 1>{});
-        step(std::integral_constant<int, 2>{});
-        step(std::integral_constant<int, 3>{});
-        step(std::integral_constant<int, 4>{});
-        step(std::integral_constant<int, 5>{});
-        step(std::integral_constant<int, 6>{});
-        step(std::integral_constant<int, 7>{});
-        step(std::integral_constant<int, 8>{});
-        step(std::integral_constant<int, 9>{});
-        step(std::integral_constant<int, 10>{});
-        step(std::integral_constant<int, 11>{});
-        step(std::integral_constant<int, 12>{});
-        step(std::integral_constant<int, 13>{});
-        step(std::integral_constant<int, 14>{});
-        step(std::integral_constant<int, 15>{});
+        static_for<1, 16>(step);
         if constexpr (MORE) unpack(sca, scb);
         pin();
         cur = nxt;
