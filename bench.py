@@ -128,6 +128,8 @@ def main():
     ap.add_argument("--heldout-shapes", type=int, default=500)
     ap.add_argument("--mlp-steps", type=int, default=5000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--clock-seconds", type=float, default=8.0,
+                    help="sustained bf16 run while sampling board power and GFX clocks (0 = skip)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--sweep", type=str, default="",
                     help="comma-separated square sizes to time and record (default: 128..--size)")
@@ -231,6 +233,11 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    # ---- 2b. sustained load: board power and GFX clocks --------------------------------
+    clock = None
+    if args.clock_seconds > 0:
+        clock = sustained_clock(cx, pa, torch, n, args.clock_seconds)
+
     # ---- 3. selector experiment -----------------------------------------------------
     selector = None
     if not args.no_selector:
@@ -274,6 +281,7 @@ def main():
         "grouped": grouped,
         "stream": stream_res,
         "roofline": roofline,
+        "sustained_clock": clock,
         "kernels": kernels,
         "sweep_tflops": {str(s): {k: round(v["tflops"], 2) for k, v in row.items()} for s, row in sweep.items()},
         "cpu_baseline": cpu,
@@ -281,6 +289,71 @@ def main():
     }
     cx.close()
     print(json.dumps(out), flush=True)
+
+
+def sustained_clock(cx, pa, torch, n, seconds):
+    """Run the bf16 variant back to back at n^3 for `seconds` while a thread samples the board's
+    socket power and per-XCD GFX clocks with amd-smi (a child process, about once a second).
+    Samples from the first 1.5 s (clock ramp) are dropped.  The published MFMA peaks assume
+    2.4 GHz; `clock_adjusted_bf16_peak` rescales the bf16 peak to the measured mean clock."""
+    import re
+    import shutil
+    import subprocess
+    import threading
+    smi = shutil.which("amd-smi") or "/opt/rocm/bin/amd-smi"
+    if not os.path.exists(smi):
+        return None
+    vid = pa.BUILTIN_VARIANTS.index("bf16")
+    g = torch.Generator(device="cuda").manual_seed(11)
+    A = torch.randn((n, n), device="cuda", generator=g)
+    B = torch.randn((n, n), device="cuda", generator=g)
+    C = torch.zeros((n, n), device="cuda")
+    samples = []
+    stop = threading.Event()
+
+    def sampler():
+        while not stop.is_set():
+            try:
+                out = subprocess.run([smi, "metric", "-g", "0", "--clock", "--power"], capture_output=True,
+                                     text=True, timeout=10).stdout
+            except Exception:
+                return
+            clks = [int(x) for x in re.findall(r"GFX_\d+:\s*\n\s*CLK:\s*(\d+) MHz", out)]
+            pw = re.search(r"SOCKET_POWER:\s*([\d.]+) W", out)
+            if clks:
+                samples.append((time.perf_counter(), clks, float(pw.group(1)) if pw else None))
+            stop.wait(0.5)
+
+    cx.gemm_variant(vid, A, B, C)
+    torch.cuda.synchronize()
+    th = threading.Thread(target=sampler, daemon=True)
+    t0 = time.perf_counter()
+    th.start()
+    launches = 0
+    while time.perf_counter() - t0 < seconds:
+        for _ in range(10):
+            cx.gemm_variant(vid, A, B, C)
+        torch.cuda.synchronize()
+        launches += 10
+    dt = time.perf_counter() - t0
+    stop.set()
+    th.join(timeout=15)
+    steady = [s for s in samples if s[0] - t0 > 1.5]
+    tflops = launches * 2.0 * n ** 3 / dt / 1e12
+    if not steady:
+        return dict(variant="bf16", seconds=dt, launches=launches, tflops=tflops, samples=0)
+    clk = np.array([c for _, cs, _ in steady for c in cs], dtype=np.float64)
+    pw = [p for _, _, p in steady if p is not None]
+    mean_mhz = float(clk.mean())
+    adj = PEAK["bf16"] * mean_mhz / 2400.0
+    log(f"sustained bf16: {tflops:.0f} TFLOP/s over {dt:.1f} s, GFX clock {mean_mhz:.0f} MHz "
+        f"[{clk.min():.0f}, {clk.max():.0f}], socket power {np.mean(pw) if pw else float('nan'):.0f} W")
+    return dict(variant="bf16", seconds=dt, launches=launches, tflops=tflops, samples=len(steady),
+                gfx_mhz_mean=mean_mhz, gfx_mhz_min=float(clk.min()), gfx_mhz_max=float(clk.max()),
+                socket_power_w_mean=float(np.mean(pw)) if pw else None,
+                socket_power_w_max=float(np.max(pw)) if pw else None,
+                clock_adjusted_bf16_peak=adj, frac_of_published_peak=tflops / PEAK["bf16"],
+                frac_of_clock_adjusted_peak=tflops / adj)
 
 
 def selector_experiment(cx, pa, torch, args):
