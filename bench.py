@@ -128,6 +128,8 @@ def main():
     ap.add_argument("--heldout-shapes", type=int, default=500)
     ap.add_argument("--mlp-steps", type=int, default=5000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-vendor", action="store_true",
+                    help="skip the vendor-library reference (torch.mm, i.e. hipBLASLt, at the same size)")
     ap.add_argument("--clock-seconds", type=float, default=8.0,
                     help="sustained bf16 run while sampling board power and GFX clocks (0 = skip)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -233,6 +235,11 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    # ---- 2a. context: the vendor GEMM library at the same size -----------------------
+    vendor = None
+    if not args.no_vendor:
+        vendor = vendor_reference(torch, n)
+
     # ---- 2b. sustained load: board power and GFX clocks --------------------------------
     clock = None
     if args.clock_seconds > 0:
@@ -282,6 +289,7 @@ def main():
         "stream": stream_res,
         "roofline": roofline,
         "sustained_clock": clock,
+        "vendor_reference": vendor,
         "kernels": kernels,
         "sweep_tflops": {str(s): {k: round(v["tflops"], 2) for k, v in row.items()} for s, row in sweep.items()},
         "cpu_baseline": cpu,
@@ -289,6 +297,33 @@ def main():
     }
     cx.close()
     print(json.dumps(out), flush=True)
+
+
+def vendor_reference(torch, n):
+    """Context only: torch.mm (hipBLASLt) on contiguous n x n operands in bf16 (bf16 output) and
+    in fp32, median of 20 timed calls after 3 warm-ups."""
+    res = {}
+    g = torch.Generator(device="cuda").manual_seed(12)
+    for name, dt in (("bf16", torch.bfloat16), ("f32", torch.float32)):
+        A = torch.randn((n, n), device="cuda", generator=g).to(dt).contiguous()
+        B = torch.randn((n, n), device="cuda", generator=g).to(dt).contiguous()
+        for _ in range(3):
+            torch.mm(A, B)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(20):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            torch.mm(A, B)
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        med = float(np.median(ts))
+        res[f"torch_mm_{name}"] = dict(median_ms=med, tflops=2.0 * n ** 3 / (med * 1e-3) / 1e12)
+        del A, B
+    torch.cuda.empty_cache()
+    log("vendor reference: " + ", ".join(f"{k} {v['median_ms']:.3f} ms {v['tflops']:.0f} TF" for k, v in res.items()))
+    return res
 
 
 def sustained_clock(cx, pa, torch, n, seconds):
