@@ -9,9 +9,11 @@
 //                   E4M3 images with one E8M0 scale byte per 128 x 128 tile,
 //                   v_mfma_scale_f32_32x32x64_f8f6f4, FP32 accumulation.
 //
-// The extra products are K-concatenated: the main loop walks nterms * nkb
-// stages and each stage picks its operand pair, so one accumulator set and one
-// pipeline serve every term.
+// The fp8 kernel K-concatenates its four products: the main loop walks
+// 4 * nkb stages and each stage picks its operand pair, so one accumulator set
+// and one pipeline serve every term.  bf16x3 instead fuses its three products
+// per K block (gemm_bf16x3_fused_kernel): each operand block is copied once
+// and feeds all the products that use it.
 //
 // Tiling: 256 x 256 C tile per workgroup of 4 wave64 (2 x 2 waves, 128 x 128
 // per wave = 4 x 4 MFMA blocks of 32 x 32, 256 FP32 accumulators per lane).
@@ -288,6 +290,140 @@ void gemm_bf16_tn_kernel(int64_t M, int64_t N, int nkb, float alpha,
 }
 
 // ---------------------------------------------------------------------------
+// bf16x3 with the three products fused per K block.  A stage holds the four
+// slabs [Ah | Bh | Al | Bl] of one 64-byte K block (64 KiB), two stages in the
+// ring.  Per 32-k sub-step the 16 fragments of the four slabs feed 3 x 16
+// MFMAs: hi.hi, then hi.lo, then lo.hi, so an accumulator is reused every 16
+// MFMAs.  Against the K-concatenated form this reads every operand block from
+// global memory once (2/3 of the copies), reads 2/3 of the LDS fragments per
+// MFMA and takes one stage barrier per 96 MFMAs instead of one per 32.  The
+// copies of stage s + 2 are issued right after the barrier of stage s that
+// frees its slot and must land by the next barrier, 96 MFMAs later.
+constexpr int NBUF3 = 2;
+constexpr int STAGE3 = 4 * SLAB;
+static_assert((size_t)NBUF3 * STAGE3 <= kSmem, "fused bf16x3 ring fits the LDS allocation");
+
+__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void gemm_bf16x3_fused_kernel(int64_t M, int64_t N, int nkb, float alpha,
+                              const uint8_t* __restrict__ Ah, const uint8_t* __restrict__ Al,
+                              const uint8_t* __restrict__ Bh, const uint8_t* __restrict__ Bl,
+                              float beta, float* __restrict__ C, int64_t ldc, int tiles_m,
+                              int tiles_n) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    // LDS ring: slot i = [Ah slab | Bh slab | Al slab | Bl slab] at i * STAGE3
+
+    const int t = threadIdx.x, lane = t & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);   // wave-uniform (SGPR)
+    const int wm = wave >> 1, wn = wave & 1;
+    int tm, tn;
+    tile_coords(tiles_m, tiles_n, tm, tn);
+    const int64_t m0 = (int64_t)tm * TM, n0 = (int64_t)tn * TN;
+    const int64_t panel = (int64_t)nkb * SLAB;
+    const int src_off = wave * 4096 + lane * 16;
+    const uint8_t* a_hi = Ah + tm * panel + src_off;
+    const uint8_t* b_hi = Bh + tn * panel + src_off;
+    const uint8_t* a_lo = Al + tm * panel + src_off;
+    const uint8_t* b_lo = Bl + tn * panel + src_off;
+    const int steps = nkb;
+
+    floatx16 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+    // Load cursor: K block, slot; past the last block it re-reads the last
+    // one into the freed slot, so every stage issues the same 16 copies.
+    int ld_kb = 0, ld_left = steps, ld_slot = 0;
+    int64_t kofs = 0;
+    uint8_t* dd = nullptr;
+    auto prepare = [&]() {
+        kofs = (int64_t)ld_kb * SLAB;
+        dd = smem + ld_slot * STAGE3 + wave * 4096;
+        const int go = ld_left > 1 ? 1 : 0;
+        ld_left -= go;
+        ld_kb += go;
+        ld_slot ^= 1;
+    };
+    auto copy = [&](auto part_tag) {            // copy P: slab P / 4, part P % 4
+        constexpr int P = decltype(part_tag)::value;
+        static_assert(P >= 0 && P < 16, "a fused stage is 16 copies");
+        constexpr int S = P / 4;
+        const uint8_t* src = S == 0 ? a_hi : (S == 1 ? b_hi : (S == 2 ? a_lo : b_lo));
+        dma_part<P % 4>(src + kofs, dd + S * SLAB);
+    };
+
+    // fragment f of a sub-step: slab f / 4 (Ah, Bh, Al, Bl), 32-row block f % 4
+    const int frag_row = lane & 31;
+    const int frag_c = lane >> 5;
+    auto read = [&](int slot, int ks, auto f_tag, bf16x8 (&F)[16]) {
+        constexpr int f = decltype(f_tag)::value;
+        constexpr int S = f / 4, blk = f % 4;
+        const int r = ((S & 1) ? wn : wm) * 128 + blk * 32 + frag_row;
+        F[f] = *reinterpret_cast<const bf16x8*>(smem + slot * STAGE3 + S * SLAB + slab_off(r, 2 * ks + frag_c));
+    };
+    // MFMA q of a sub-step: product q / 16 (hi.hi, hi.lo, lo.hi), block q % 16
+    auto mfma = [&](auto q_tag, const bf16x8 (&F)[16]) {
+        constexpr int q = decltype(q_tag)::value;
+        constexpr int p = q / 16, i = (q % 16) / 4, j = q % 4;
+        constexpr int fa = (p == 2 ? 8 : 0) + i, fb = (p == 1 ? 12 : 4) + j;
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(F[fa], F[fb], acc[i][j], 0, 0, 0);
+    };
+
+    // prologue: stages 0 and 1 in flight, wait for stage 0
+#pragma unroll
+    for (int p = 0; p < NBUF3; ++p) {
+        prepare();
+        static_for<0, 16>(copy);
+    }
+    stage_barrier<2>();                         // 16 copies (stage 1) may stay in flight
+
+    constexpr int PRE = 2;
+    static_assert(PRE >= 1 && PRE + 16 <= 48, "the 16 copies and reads ride under MFMAs PRE .. PRE + 15");
+    bf16x8 F0[16], F1[16];
+    static_for<0, 16>([&](auto f) { read(0, 0, f, F0); });
+    int cur = 0;
+    pin();
+    // One stage = two sub-steps of 48 MFMAs over slot `cur`:
+    //   ks 0: MFMA q on F0, then (q < 16) read fragment q of ks 1 into F1
+    //   ks 1: PRE MFMAs on F1; stage barrier (stage s + 1 landed, slot `cur`
+    //         free); then MFMA q, copy q - PRE of stage s + 2 into slot `cur`,
+    //         read fragment q - PRE of stage s + 1's ks 0 into F0.
+    auto one_stage = [&](auto more_tag) {
+        constexpr bool MORE = decltype(more_tag)::value;
+        const int nxt = cur ^ 1;
+        static_for<0, 48>([&](auto q) {
+            mfma(q, F0);
+            if constexpr (decltype(q)::value < 16) read(cur, 1, q, F1);
+            pin();
+        });
+        static_for<0, PRE>([&](auto q) { mfma(q, F1); });
+        pin();
+        if constexpr (MORE) {
+            stage_barrier<0>();
+            prepare();
+        }
+        pin();
+        static_for<PRE, 48>([&](auto q) {
+            mfma(q, F1);
+            constexpr int k = decltype(q)::value - PRE;
+            if constexpr (MORE && k < 16) {
+                copy(std::integral_constant<int, k>{});
+                read(nxt, 0, std::integral_constant<int, k>{}, F0);
+            }
+            pin();
+        });
+        cur = nxt;
+    };
+    for (int s = 0; s + 1 < steps; ++s) one_stage(std::true_type{});
+    one_stage(std::false_type{});
+    __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 15));   // drain the trailing copies
+    epilogue(acc, M, N, m0, n0, wm, wn, lane, alpha, beta, C, ldc);
+}
+
+// ---------------------------------------------------------------------------
 __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void gemm_fp8r_tn_kernel(int64_t M, int64_t N, int nkb, float alpha,
                          const uint8_t* __restrict__ Aq, const uint8_t* __restrict__ Ar,
@@ -472,7 +608,19 @@ hipError_t launch_gemm_bf16_tn(int64_t M, int64_t N, int64_t Kp, int nterms, flo
     if (Kp % kBf16TileK || Kp <= 0 || (nterms != 1 && nterms != 3) || (nterms == 3 && (!Al || !Bl)))
         return hipErrorInvalidValue;
     if (nterms == 1) return launch_bf16_terms<1>(M, N, Kp, alpha, Ah, Al, Bh, Bl, beta, C, ldc, stream);
-    return launch_bf16_terms<3>(M, N, Kp, alpha, Ah, Al, Bh, Bl, beta, C, ldc, stream);
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)gemm_bf16x3_fused_kernel,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmem);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const int tiles_m = (int)((M + TM - 1) / TM), tiles_n = (int)((N + TN - 1) / TN);
+    const int nkb = (int)(Kp * 2 / kPanelRowBytes);
+    hipLaunchKernelGGL(gemm_bf16x3_fused_kernel, dim3(tiles_m * tiles_n), dim3(THREADS), kSmem,
+                       stream, M, N, nkb, alpha, (const uint8_t*)Ah, (const uint8_t*)Al,
+                       (const uint8_t*)Bh, (const uint8_t*)Bl, beta, C, ldc, tiles_m, tiles_n);
+    return hipGetLastError();
 }
 
 hipError_t launch_gemm_fp8r_tn(int64_t M, int64_t N, int64_t Kp, float alpha, const uint8_t* Aq,
