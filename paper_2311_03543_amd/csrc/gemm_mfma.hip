@@ -9,11 +9,10 @@
 //                   E4M3 images with one E8M0 scale byte per 128 x 128 tile,
 //                   v_mfma_scale_f32_32x32x64_f8f6f4, FP32 accumulation.
 //
-// The fp8 kernel K-concatenates its four products: the main loop walks
-// 4 * nkb stages and each stage picks its operand pair, so one accumulator set
-// and one pipeline serve every term.  bf16x3 instead fuses its three products
-// per K block (gemm_bf16x3_fused_kernel): each operand block is copied once
-// and feeds all the products that use it.
+// The multi-product variants fuse their products per K block
+// (gemm_bf16x3_fused_kernel, gemm_fp8r_fused_kernel): a stage holds the four
+// operand slabs of one K block, each copied once, and feeds every product
+// that uses them into one accumulator set.
 //
 // Tiling: 256 x 256 C tile per workgroup of 4 wave64 (2 x 2 waves, 128 x 128
 // per wave = 4 x 4 MFMA blocks of 32 x 32, 256 FP32 accumulators per lane).
@@ -424,15 +423,28 @@ void gemm_bf16x3_fused_kernel(int64_t M, int64_t N, int nkb, float alpha,
 }
 
 // ---------------------------------------------------------------------------
+// fp8 refined with the four products fused per K block.  A stage holds the
+// four slabs [Aq | Bq | Ar | Br] of one 64-byte K block (one 64-k MFMA step),
+// two stages in the ring.  The products run in the order q.q, q.r, r.q, r.r
+// (16 MFMAs each), and the operand registers are reused as soon as their last
+// product has issued, so one register set suffices:
+//   q.q  (Aq, Bq)  under it: read Br, then Ar of this stage
+//   --- stage barrier: stage s + 1 landed, every read of slot s done ---
+//   q.r  (Aq, Br)  under it: the 16 copies of stage s + 2 into slot s
+//   r.q  (Ar, Bq)  under it: read Aq of stage s + 1
+//   r.r  (Ar, Br)  under it: read Bq of stage s + 1
+// Copies get 64 MFMAs (one stage) to land; one barrier per 64 MFMAs.  Each
+// product has its own pair of E8M0 tile scales (q or r of A, q or r of B).
 __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(1, 1)))
-void gemm_fp8r_tn_kernel(int64_t M, int64_t N, int nkb, float alpha,
-                         const uint8_t* __restrict__ Aq, const uint8_t* __restrict__ Ar,
-                         const uint8_t* __restrict__ Asq, const uint8_t* __restrict__ Asr,
-                         const uint8_t* __restrict__ Bq, const uint8_t* __restrict__ Br,
-                         const uint8_t* __restrict__ Bsq, const uint8_t* __restrict__ Bsr,
-                         float beta, float* __restrict__ C, int64_t ldc, int tiles_m,
-                         int tiles_n) {
+void gemm_fp8r_fused_kernel(int64_t M, int64_t N, int nkb, float alpha,
+                            const uint8_t* __restrict__ Aq, const uint8_t* __restrict__ Ar,
+                            const uint8_t* __restrict__ Asq, const uint8_t* __restrict__ Asr,
+                            const uint8_t* __restrict__ Bq, const uint8_t* __restrict__ Br,
+                            const uint8_t* __restrict__ Bsq, const uint8_t* __restrict__ Bsr,
+                            float beta, float* __restrict__ C, int64_t ldc, int tiles_m,
+                            int tiles_n) {
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    // LDS ring: slot i = [Aq slab | Bq slab | Ar slab | Br slab] at i * STAGE3
 
     const int t = threadIdx.x, lane = t & 63;
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);   // wave-uniform (SGPR)
@@ -443,10 +455,10 @@ void gemm_fp8r_tn_kernel(int64_t M, int64_t N, int nkb, float alpha,
     const int64_t panel = (int64_t)nkb * SLAB;
     const int src_off = wave * 4096 + lane * 16;
     const uint8_t* a_q = Aq + tm * panel + src_off;
-    const uint8_t* a_r = Ar + tm * panel + src_off;
     const uint8_t* b_q = Bq + tn * panel + src_off;
+    const uint8_t* a_r = Ar + tm * panel + src_off;
     const uint8_t* b_r = Br + tn * panel + src_off;
-    const int steps = 4 * nkb;                  // one 64-k MFMA step per stage
+    const int steps = nkb;                      // one 64-k MFMA step per stage
     const int nkt = nkb / 2;                    // 128-k scale tiles per row
     // this wave's 128 rows of A (and columns of C) lie in one 128-row scale tile
     const int64_t a_tile = m0 / 128 + wm, b_tile = n0 / 128 + wn;
@@ -459,124 +471,150 @@ void gemm_fp8r_tn_kernel(int64_t M, int64_t N, int nkb, float alpha,
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-    // Load cursor: term 0 = q.q, 1 = r.q, 2 = q.r, 3 = r.r.
-    LoadCursor ld(steps);
-    const uint8_t* dsa = nullptr;
-    const uint8_t* dsb = nullptr;
+    // Load cursor (K block, slot); past the last block it re-reads the last
+    // one into the freed slot, so every stage issues the same 16 copies.
+    int ld_kb = 0, ld_left = steps, ld_slot = 0;
+    int64_t kofs = 0;
     uint8_t* dd = nullptr;
     auto prepare = [&]() {
-        const int64_t kofs = (int64_t)ld.kb * SLAB;
-        dsa = ((ld.term & 1) ? a_r : a_q) + kofs;
-        dsb = ((ld.term & 2) ? b_r : b_q) + kofs;
-        dd = smem + ld.slot * STAGE + wave * 4096;
-        ld.advance(nkb);
+        kofs = (int64_t)ld_kb * SLAB;
+        dd = smem + ld_slot * STAGE3 + wave * 4096;
+        const int go = ld_left > 1 ? 1 : 0;
+        ld_left -= go;
+        ld_kb += go;
+        ld_slot ^= 1;
     };
-    auto copy = [&](auto part_tag) {
+    auto copy = [&](auto part_tag) {            // copy P: slab P / 4, part P % 4
         constexpr int P = decltype(part_tag)::value;
-        static_assert(P >= 0 && P < 8, "a stage is 8 copies");
-        if constexpr (P < 4) dma_part<P>(dsa, dd);
-        else dma_part<P - 4>(dsb, dd + SLAB);
+        static_assert(P >= 0 && P < 16, "a fused stage is 16 copies");
+        constexpr int S = P / 4;
+        const uint8_t* src = S == 0 ? a_q : (S == 1 ? b_q : (S == 2 ? a_r : b_r));
+        dma_part<P % 4>(src + kofs, dd + S * SLAB);
     };
 
-    // E8M0 scale bytes of a stage for this wave's A rows and B columns.  A
-    // byte is fetched as its aligned 32-bit word so the load is scalar (every
-    // index is wave-uniform); a stage's words are loaded right after the
-    // previous stage's barrier and unpacked at that stage's end.
-    int sc_kb = 0, sc_term = 0;                 // stage whose scale words load next
-    uint32_t wa = 0, wb = 0;
-    int sha = 0, shb = 0;
+    // Scale bytes of a K block: E8M0 of this wave's A tile (q, r) and B tile
+    // (q, r); scalar loads of the aligned words, issued one stage ahead.
+    int sc_kb = 0;
+    uint32_t w_aq = 0, w_ar = 0, w_bq = 0, w_br = 0;
+    int sh_a = 0, sh_b = 0;
     auto load_scale_words = [&]() {
         const int64_t ia = a_tile * nkt + (sc_kb >> 1), ib = b_tile * nkt + (sc_kb >> 1);
-        wa = *reinterpret_cast<const uint32_t*>(((sc_term & 1) ? Asr : Asq) + (ia & ~(int64_t)3));
-        wb = *reinterpret_cast<const uint32_t*>(((sc_term & 2) ? Bsr : Bsq) + (ib & ~(int64_t)3));
-        sha = (int)(ia & 3) * 8;
-        shb = (int)(ib & 3) * 8;
-        const int k = sc_kb + 1;
-        const int wrap = k == nkb ? 1 : 0;
-        sc_kb = __builtin_amdgcn_readfirstlane(wrap ? 0 : k);
-        sc_term = __builtin_amdgcn_readfirstlane(sc_term + wrap);
+        const int64_t oa = ia & ~(int64_t)3, ob = ib & ~(int64_t)3;
+        w_aq = *reinterpret_cast<const uint32_t*>(Asq + oa);
+        w_ar = *reinterpret_cast<const uint32_t*>(Asr + oa);
+        w_bq = *reinterpret_cast<const uint32_t*>(Bsq + ob);
+        w_br = *reinterpret_cast<const uint32_t*>(Bsr + ob);
+        sh_a = (int)(ia & 3) * 8;
+        sh_b = (int)(ib & 3) * 8;
+        sc_kb = __builtin_amdgcn_readfirstlane(sc_kb + 1 < steps ? sc_kb + 1 : sc_kb);
     };
-    auto unpack = [&](int& sa, int& sb) {
-        sa = (int)((wa >> sha) & 0xffu);
-        sb = (int)((wb >> shb) & 0xffu);
+    int s_aq, s_ar, s_bq, s_br;                 // scales of the stage being multiplied
+    int n_aq = 0, n_ar = 0, n_bq = 0, n_br = 0; // scales of the next stage
+    auto unpack_next = [&]() {
+        n_aq = (int)((w_aq >> sh_a) & 0xffu);
+        n_ar = (int)((w_ar >> sh_a) & 0xffu);
+        n_bq = (int)((w_bq >> sh_b) & 0xffu);
+        n_br = (int)((w_br >> sh_b) & 0xffu);
+    };
+    auto advance_scales = [&]() {
+        s_aq = n_aq;
+        s_ar = n_ar;
+        s_bq = n_bq;
+        s_br = n_br;
     };
 
-    // lane l feeds row l % 32 of each 32-row block, 32 bytes = chunks 2 (l / 32)
-    // and 2 (l / 32) + 1; half h < 8 is A block h / 2, h >= 8 is B block h / 2 - 4
+    // Operand registers: image X in {Aq, Bq, Ar, Br} (X = 0..3), 32-row block
+    // b, half h (16 of the 32 bytes a lane feeds): R[X][2 b + h].  Lane l
+    // feeds row l % 32 of a block, bytes 32 (l / 32) .. +31 of the K block.
+    intx4 R[4][8];
     const int frag_row = lane & 31;
     const int frag_c = (lane >> 5) * 2;
-    intx4 ha[2][8], hb[2][8];                   // fragment halves, two register sets
-    auto read = [&](int slot, int h, intx4 (&a)[8], intx4 (&b)[8]) {
-        const uint8_t* base = smem + slot * STAGE;
-        const int blk = h >> 1, c = frag_c + (h & 1);
-        if (blk < 4)
-            a[h] = *reinterpret_cast<const intx4*>(base + slab_off(wm * 128 + blk * 32 + frag_row, c));
-        else
-            b[h - 8] = *reinterpret_cast<const intx4*>(base + SLAB + slab_off(wn * 128 + (blk - 4) * 32 + frag_row, c));
+    auto read = [&](int slot, auto x_tag, auto h_tag) {
+        constexpr int X = decltype(x_tag)::value, H = decltype(h_tag)::value;
+        constexpr int blk = H / 2, half = H % 2;
+        const int r = ((X & 1) ? wn : wm) * 128 + blk * 32 + frag_row;
+        R[X][H] = *reinterpret_cast<const intx4*>(smem + slot * STAGE3 + X * SLAB + slab_off(r, frag_c + half));
     };
-    auto mfma = [&](int idx, const intx4 (&a)[8], const intx4 (&b)[8], int sca, int scb) {
-        const int i = idx >> 2, j = idx & 3;
-        const intx8 av = __builtin_shufflevector(a[2 * i], a[2 * i + 1], 0, 1, 2, 3, 4, 5, 6, 7);
-        const intx8 bv = __builtin_shufflevector(b[2 * j], b[2 * j + 1], 0, 1, 2, 3, 4, 5, 6, 7);
-        acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, acc[i][j], 0, 0, 0,
-                                                                    sca, 0, scb);
+    // MFMA q (0..15) of product P (0 q.q, 1 q.r, 2 r.q, 3 r.r)
+    auto mfma = [&](auto p_tag, auto q_tag) {
+        constexpr int P = decltype(p_tag)::value, q = decltype(q_tag)::value;
+        constexpr int i = q / 4, j = q % 4;
+        constexpr int XA = (P == 2 || P == 3) ? 2 : 0, XB = (P == 1 || P == 3) ? 3 : 1;
+        const intx8 av = __builtin_shufflevector(R[XA][2 * i], R[XA][2 * i + 1], 0, 1, 2, 3, 4, 5, 6, 7);
+        const intx8 bv = __builtin_shufflevector(R[XB][2 * j], R[XB][2 * j + 1], 0, 1, 2, 3, 4, 5, 6, 7);
+        const int sa = XA == 0 ? s_aq : s_ar, sb = XB == 1 ? s_bq : s_br;
+        acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, acc[i][j], 0, 0, 0, sa, 0, sb);
     };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using I3 = std::integral_constant<int, 3>;
 
-    // prologue: the first NBUF stages in flight, stage 0's scales, wait for stage 0
+    // prologue: stages 0 and 1 in flight, stage 0's scales, wait for stage 0,
+    // read Aq and Bq of stage 0
 #pragma unroll
-    for (int p = 0; p < NBUF; ++p) {
+    for (int p = 0; p < 2; ++p) {
         prepare();
-        static_for<0, 8>(copy);
+        static_for<0, 16>(copy);
     }
-    int sca, scb;
     load_scale_words();
-    unpack(sca, scb);
-    stage_barrier<NBUF - 1>();
-#pragma unroll
-    for (int h = 0; h < 16; ++h) read(0, h, ha[0], hb[0]);
+    unpack_next();
+    advance_scales();                            // stage 0's scales
+    load_scale_words();                          // stage 1's words
+    stage_barrier<2>();                          // stage 1 (16 copies) may stay in flight
+    static_for<0, 8>([&](auto h) { read(0, I0{}, h); });
+    static_for<0, 8>([&](auto h) { read(0, I1{}, h); });
     int cur = 0;
     pin();
 
-    // One stage = 16 MFMAs on the fragments of slot `cur` (register set P):
-    // one MFMA, stage barrier (stage s + 1 landed, slot `cur` free), the
-    // scale words of stage s + 1, then MFMA q followed by copy q - 1 of stage
-    // s + NBUF into slot `cur` and reads 2 (q - 1), +1 of stage s + 1 into set
-    // P ^ 1 (q = 1..8), then the remaining MFMAs.
-    auto one_stage = [&](auto par_tag, auto more_tag) {
-        constexpr int P = decltype(par_tag)::value;
+    auto one_stage = [&](auto more_tag) {
         constexpr bool MORE = decltype(more_tag)::value;
-        const int nxt = cur + 1 == NBUF ? 0 : cur + 1;
-        mfma(0, ha[P], hb[P], sca, scb);
-        pin();
+        const int nxt = cur ^ 1;
+        // q.q; read Br then Ar of this stage under it
+        static_for<0, 16>([&](auto q) {
+            mfma(I0{}, q);
+            constexpr int k = decltype(q)::value;
+            if constexpr (k < 8) read(cur, I3{}, std::integral_constant<int, k>{});
+            else read(cur, I2{}, std::integral_constant<int, k - 8>{});
+            pin();
+        });
         if constexpr (MORE) {
-            stage_barrier<NBUF - 2>();
+            stage_barrier<0>();                 // stage s + 1 landed, slot `cur` free
             prepare();
-            load_scale_words();
         }
         pin();
-        auto step = [&](auto q_tag) {
-            constexpr int Q = decltype(q_tag)::value;
-            mfma(Q, ha[P], hb[P], sca, scb);
-            if constexpr (MORE && Q <= 8) {
-                copy(std::integral_constant<int, Q - 1>{});
-                read(nxt, 2 * (Q - 1), ha[P ^ 1], hb[P ^ 1]);
-                read(nxt, 2 * (Q - 1) + 1, ha[P ^ 1], hb[P ^ 1]);
-            }
+        // q.r; the copies of stage s + 2 under it
+        static_for<0, 16>([&](auto q) {
+            mfma(I1{}, q);
+            if constexpr (MORE) copy(q);
             pin();
-        };
-        static_for<1, 16>(step);
-        if constexpr (MORE) unpack(sca, scb);
+        });
+        if constexpr (MORE) {
+            unpack_next();                      // stage s + 1's scales (words loaded a stage ago)
+            load_scale_words();                 // stage s + 2's words
+        }
+        pin();
+        // r.q; read Aq of stage s + 1 under it
+        static_for<0, 16>([&](auto q) {
+            mfma(I2{}, q);
+            constexpr int k = decltype(q)::value;
+            if constexpr (MORE && k < 8) read(nxt, I0{}, std::integral_constant<int, k>{});
+            pin();
+        });
+        // r.r; read Bq of stage s + 1 under it
+        static_for<0, 16>([&](auto q) {
+            mfma(I3{}, q);
+            constexpr int k = decltype(q)::value;
+            if constexpr (MORE && k < 8) read(nxt, I1{}, std::integral_constant<int, k>{});
+            pin();
+        });
+        if constexpr (MORE) advance_scales();
         pin();
         cur = nxt;
     };
-    // steps is even (nkb is even)
-    for (int s = 0; s + 2 < steps; s += 2) {
-        one_stage(std::integral_constant<int, 0>{}, std::true_type{});
-        one_stage(std::integral_constant<int, 1>{}, std::true_type{});
-    }
-    one_stage(std::integral_constant<int, 0>{}, std::true_type{});
-    one_stage(std::integral_constant<int, 1>{}, std::false_type{});
-    __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 15));   // drain the trailing loads
+    for (int s = 0; s + 1 < steps; ++s) one_stage(std::true_type{});
+    one_stage(std::false_type{});
+    __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 15));   // drain the trailing copies
     epilogue(acc, M, N, m0, n0, wm, wn, lane, alpha, beta, C, ldc);
 }
 
@@ -631,14 +669,14 @@ hipError_t launch_gemm_fp8r_tn(int64_t M, int64_t N, int64_t Kp, float alpha, co
     if (Kp % kFp8TileK || Kp <= 0) return hipErrorInvalidValue;
     static bool attr = false;
     if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)gemm_fp8r_tn_kernel,
+        hipError_t e = hipFuncSetAttribute((const void*)gemm_fp8r_fused_kernel,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmem);
         if (e != hipSuccess) return e;
         attr = true;
     }
     const int tiles_m = (int)((M + TM - 1) / TM), tiles_n = (int)((N + TN - 1) / TN);
     const int nkb = (int)(Kp / kPanelRowBytes);
-    hipLaunchKernelGGL(gemm_fp8r_tn_kernel, dim3(tiles_m * tiles_n), dim3(THREADS), kSmem, stream,
+    hipLaunchKernelGGL(gemm_fp8r_fused_kernel, dim3(tiles_m * tiles_n), dim3(THREADS), kSmem, stream,
                        M, N, nkb, alpha, Aq, Ar, Asq, Asr, Bq, Br, Bsq, Bsr, beta, C, ldc, tiles_m,
                        tiles_n);
     return hipGetLastError();
