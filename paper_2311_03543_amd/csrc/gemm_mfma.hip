@@ -299,6 +299,9 @@ void gemm_bf16_tn_kernel(int64_t M, int64_t N, int nkb, float alpha,
 // copies of stage s + 2 are issued right after the barrier of stage s that
 // frees its slot and must land by the next barrier, 96 MFMAs later.
 constexpr int NBUF3 = 2;
+// Fragment read order of a fused bf16x3 sub-step (fragment f: slab f / 4 of
+// Ah, Bh, Al, Bl, block f % 4): the order the next sub-step's MFMAs use them.
+constexpr int kX3Order[16] = {0, 4, 5, 6, 7, 1, 2, 3, 12, 13, 14, 15, 8, 9, 10, 11};
 constexpr int STAGE3 = 4 * SLAB;
 static_assert((size_t)NBUF3 * STAGE3 <= kSmem, "fused bf16x3 ring fits the LDS allocation");
 
@@ -379,39 +382,42 @@ void gemm_bf16x3_fused_kernel(int64_t M, int64_t N, int nkb, float alpha,
     }
     stage_barrier<2>();                         // 16 copies (stage 1) may stay in flight
 
-    constexpr int PRE = 2;
-    static_assert(PRE >= 1 && PRE + 16 <= 48, "the 16 copies and reads ride under MFMAs PRE .. PRE + 15");
+    // Fragment reads go in the order the next sub-step uses them (Ah0, Bh0-3,
+    // Ah1-3 for hi.hi, then Bl for hi.lo, then Al for lo.hi), one every two
+    // MFMAs with the copies between them, over the first two thirds of the
+    // sub-step: LDS reads and copy writes are spread instead of bursting, and
+    // the last third leaves the reads time to land before the next wait.
     bf16x8 F0[16], F1[16];
-    static_for<0, 16>([&](auto f) { read(0, 0, f, F0); });
+    static_for<0, 16>([&](auto k) { read(0, 0, std::integral_constant<int, kX3Order[decltype(k)::value]>{}, F0); });
     int cur = 0;
     pin();
     // One stage = two sub-steps of 48 MFMAs over slot `cur`:
-    //   ks 0: MFMA q on F0, then (q < 16) read fragment q of ks 1 into F1
-    //   ks 1: PRE MFMAs on F1; stage barrier (stage s + 1 landed, slot `cur`
-    //         free); then MFMA q, copy q - PRE of stage s + 2 into slot `cur`,
-    //         read fragment q - PRE of stage s + 1's ks 0 into F0.
+    //   ks 0: MFMA q on F0; after MFMA 2k, read fragment kX3Order[k] of ks 1 into F1
+    //   ks 1: one MFMA on F1; stage barrier (stage s + 1 landed, slot `cur`
+    //         free); then MFMA q = 1 + m on F1 with, for m = 2k, the read of
+    //         fragment kX3Order[k] of stage s + 1's ks 0 into F0 and, for
+    //         m = 2k + 1, copy k of stage s + 2 into slot `cur`.
     auto one_stage = [&](auto more_tag) {
         constexpr bool MORE = decltype(more_tag)::value;
         const int nxt = cur ^ 1;
         static_for<0, 48>([&](auto q) {
+            constexpr int Q = decltype(q)::value;
             mfma(q, F0);
-            if constexpr (decltype(q)::value < 16) read(cur, 1, q, F1);
+            if constexpr (Q % 2 == 0 && Q < 32) read(cur, 1, std::integral_constant<int, kX3Order[Q / 2]>{}, F1);
             pin();
         });
-        static_for<0, PRE>([&](auto q) { mfma(q, F1); });
+        mfma(std::integral_constant<int, 0>{}, F1);
         pin();
         if constexpr (MORE) {
             stage_barrier<0>();
             prepare();
         }
         pin();
-        static_for<PRE, 48>([&](auto q) {
+        static_for<1, 48>([&](auto q) {
+            constexpr int m = decltype(q)::value - 1;
             mfma(q, F1);
-            constexpr int k = decltype(q)::value - PRE;
-            if constexpr (MORE && k < 16) {
-                copy(std::integral_constant<int, k>{});
-                read(nxt, 0, std::integral_constant<int, k>{}, F0);
-            }
+            if constexpr (MORE && m % 2 == 0 && m < 32) read(nxt, 0, std::integral_constant<int, kX3Order[m / 2]>{}, F0);
+            if constexpr (MORE && m % 2 == 1 && m < 32) copy(std::integral_constant<int, m / 2>{});
             pin();
         });
         cur = nxt;
