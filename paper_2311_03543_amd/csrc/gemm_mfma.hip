@@ -9,22 +9,18 @@
 //                   E4M3 images with one E8M0 scale byte per 128 x 128 tile,
 //                   v_mfma_scale_f32_32x32x64_f8f6f4, FP32 accumulation.
 //
-// The multi-product variants fuse their products per K block
-// (gemm_bf16x3_fused_kernel, gemm_fp8r_fused_kernel): a stage holds the four
-// operand slabs of one K block, each copied once, and feeds every product
-// that uses them into one accumulator set.
-//
 // Tiling: 256 x 256 C tile per workgroup of 4 wave64 (2 x 2 waves, 128 x 128
 // per wave = 4 x 4 MFMA blocks of 32 x 32, 256 FP32 accumulators per lane).
-// A stage is one 64-byte K block of both operands: a 16 KiB A slab and a
-// 16 KiB B slab, each one contiguous panel-image block, so the direct
-// global->LDS loads (global_load_lds_dwordx4) are linear 1 KiB copies whose
-// immediate offset advances the global and the LDS address together.  NBUF
-// stages live in an LDS ring; the loads of stage s + NBUF are issued during
-// stage s, right after the barrier that frees stage s's slot, so a load has
-// about NBUF - 1 stages of MFMA time to land.  Fragments are double-buffered
-// in registers: a stage's slot is read during the previous stage (and its
-// first half, for bf16), never while its own MFMAs run.
+// A pipeline stage holds four 16 KiB slabs (256 rows x 64 bytes of K, each one
+// contiguous panel-image block) in a 2-slot LDS ring: the operand blocks of
+// one K block that feed all the products using them (bf16x3: Ah Bh Al Bl;
+// fp8: Aq Bq Ar Br), or two consecutive K blocks of A and B (bf16).  Direct
+// global->LDS loads (global_load_lds_dwordx4) copy the slabs as linear 1 KiB
+// pieces whose immediate offset advances the global and the LDS address
+// together; the copies of stage s + 2 go out right after the barrier of stage
+// s that frees their slot and have one whole stage of MFMAs to land.  The
+// instruction order of every main loop is pinned: each MFMA is followed by the
+// copy and fragment reads that ride under it.
 #include <type_traits>
 
 #include "common.h"
@@ -41,9 +37,9 @@ typedef int intx4 __attribute__((ext_vector_type(4)));
 constexpr int TM = 256, TN = 256;
 constexpr int THREADS = 256;
 constexpr int SLAB = kPanelBlock;          // 16 KiB: 256 rows x 64 bytes
-constexpr int STAGE = 2 * SLAB;            // A slab + B slab
-constexpr int NBUF = 4;                    // LDS ring depth (stages)
-constexpr size_t kSmem = (size_t)NBUF * STAGE;   // 128 KiB
+constexpr int STAGE4 = 4 * SLAB;           // four slabs per pipeline stage
+constexpr int NBUF4 = 2;                   // LDS ring depth (stages)
+constexpr size_t kSmem = (size_t)NBUF4 * STAGE4;   // 128 KiB
 
 typedef const __attribute__((address_space(1))) void* gptr_t;
 typedef __attribute__((address_space(3))) void* lptr_t;
@@ -59,15 +55,16 @@ constexpr int waitcnt_imm(int vm, int lgkm) {
     return (vm & 15) | ((vm >> 4) << 14) | (7 << 4) | (lgkm << 8);
 }
 
-// Stage barrier: this wave's LDS reads done, at most `ahead` stages of its
-// slab loads (8 instructions each) still in flight, then the workgroup
-// barrier: afterwards every wave's loads of the awaited stage have landed and
-// every wave's reads of the previous slot are complete.  The empty asm
+// Stage barrier: this wave's LDS reads done, at most VM of its copies still
+// in flight (copies complete in issue order), then the workgroup barrier:
+// afterwards every wave's copies of the awaited stage have landed and every
+// wave's reads of the slot about to be refilled are complete.  The empty asm
 // statements keep the compiler from moving memory accesses across.
-template <int AHEAD>
+template <int VM>
 __device__ __forceinline__ void stage_barrier() {
+    static_assert(VM >= 0 && VM <= 63, "vmcnt range");
     asm volatile("" ::: "memory");
-    __builtin_amdgcn_s_waitcnt(waitcnt_imm(8 * AHEAD, 0));
+    __builtin_amdgcn_s_waitcnt(waitcnt_imm(VM, 0));
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
 }
@@ -142,177 +139,54 @@ __device__ __forceinline__ void tile_coords(int tiles_m, int tiles_n, int& tm, i
     grouped_tile(xcd_remap(blockIdx.x, tiles_m * tiles_n), tiles_m, tiles_n, 8, tm, tn);
 }
 
-// Load cursor over the K-concatenated stages: term t, block kb, ring slot.
-// Past the last stage it keeps re-reading the last block into the freed slot
-// (nobody reads it again), so every stage issues the same 8 loads and the
-// in-flight count the barriers wait on stays constant.
-struct LoadCursor {
-    int kb = 0, term = 0, slot = 0, left;
-    __device__ __forceinline__ explicit LoadCursor(int steps) : left(steps) {}
-    // branch-free (selects), so the issuing stage stays one scheduling region
-    __device__ __forceinline__ void advance(int nkb) {
-        const int go = left > 1 ? 1 : 0;
-        left -= go;
-        const int k = kb + go;
-        const int wrap = k == nkb ? 1 : 0;
-        kb = wrap ? 0 : k;
-        term += wrap;
-        slot = slot + 1 == NBUF ? 0 : slot + 1;
-    }
-};
-
 // ---------------------------------------------------------------------------
-template <int NTERMS>
-__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(1, 1)))
-void gemm_bf16_tn_kernel(int64_t M, int64_t N, int nkb, float alpha,
-                         const uint8_t* __restrict__ Ah, const uint8_t* __restrict__ Al,
-                         const uint8_t* __restrict__ Bh, const uint8_t* __restrict__ Bl,
-                         float beta, float* __restrict__ C, int64_t ldc, int tiles_m,
-                         int tiles_n) {
-    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
-    // LDS ring: slot i = [A slab | B slab] at i * STAGE
+// bf16 kernels over four-slab stages.  A stage holds four 16 KiB slabs (64
+// KiB), two stages in the LDS ring; per 16-k sub-step (two per stage) the 16
+// fragments of the four slabs (4 blocks of 32 rows each) feed NPROD x 16
+// MFMAs, one product after the other so an accumulator is reused every 16
+// MFMAs.
+//   NPROD = 3 (bf16x3): slabs [Ah | Bh | Al | Bl] of one 64-byte K block;
+//            products hi.hi, hi.lo, lo.hi.  Every operand block is copied once
+//            and feeds all the products that use it.
+//   NPROD = 2 (bf16):   slabs [A | B | A' | B'] of two consecutive K blocks;
+//            products A.B and A'.B'.
+// The copies of stage s + 2 are issued right after the barrier of stage s
+// that frees its slot and must land by the next barrier, one stage later;
+// one barrier per 32 NPROD MFMAs.
 
-    const int t = threadIdx.x, lane = t & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);   // wave-uniform (SGPR)
-    const int wm = wave >> 1, wn = wave & 1;
-    int tm, tn;
-    tile_coords(tiles_m, tiles_n, tm, tn);
-    const int64_t m0 = (int64_t)tm * TM, n0 = (int64_t)tn * TN;
-    const int64_t panel = (int64_t)nkb * SLAB;        // bytes of one 256-row panel
-    const int src_off = wave * 4096 + lane * 16;
-    const uint8_t* a_hi = Ah + tm * panel + src_off;
-    const uint8_t* b_hi = Bh + tn * panel + src_off;
-    const uint8_t* a_lo = NTERMS > 1 ? Al + tm * panel + src_off : a_hi;
-    const uint8_t* b_lo = NTERMS > 1 ? Bl + tn * panel + src_off : b_hi;
-    const int steps = NTERMS * nkb;
+// Slabs (A side, B side) of product p.
+template <int NPROD>
+constexpr int prod_a(int p) { return NPROD == 3 ? (p == 2 ? 2 : 0) : 2 * p; }
+template <int NPROD>
+constexpr int prod_b(int p) { return NPROD == 3 ? (p == 1 ? 3 : 1) : 2 * p + 1; }
 
-    floatx16 acc[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
-
-    // Load cursor: term 0 = hi.hi, 1 = hi.lo, 2 = lo.hi.  The per-stage
-    // source pointers and slot are computed once (after the stage barrier);
-    // the 8 copies are then issued one per MFMA.
-    LoadCursor ld(steps);
-    const uint8_t* dsa = nullptr;
-    const uint8_t* dsb = nullptr;
-    uint8_t* dd = nullptr;
-    auto prepare = [&]() {
-        const int64_t kofs = (int64_t)ld.kb * SLAB;
-        dsa = (ld.term == 2 ? a_lo : a_hi) + kofs;
-        dsb = (ld.term == 1 ? b_lo : b_hi) + kofs;
-        dd = smem + ld.slot * STAGE + wave * 4096;
-        ld.advance(nkb);
-    };
-    auto copy = [&](auto part_tag) {
-        constexpr int P = decltype(part_tag)::value;
-        static_assert(P >= 0 && P < 8, "a stage is 8 copies");
-        if constexpr (P < 4) dma_part<P>(dsa, dd);
-        else dma_part<P - 4>(dsb, dd + SLAB);
-    };
-
-    // lane l feeds row l % 32 of each 32-row block, k-chunk 2 ks + l / 32;
-    // fragment f < 4 is A block f, f >= 4 is B block f - 4
-    const int frag_row = lane & 31;
-    const int frag_c = lane >> 5;
-    auto read = [&](int slot, int ks, int f, bf16x8 (&a)[4], bf16x8 (&b)[4]) {
-        const uint8_t* base = smem + slot * STAGE;
-        if (f < 4)
-            a[f] = *reinterpret_cast<const bf16x8*>(base + slab_off(wm * 128 + f * 32 + frag_row, 2 * ks + frag_c));
-        else
-            b[f - 4] = *reinterpret_cast<const bf16x8*>(base + SLAB + slab_off(wn * 128 + (f - 4) * 32 + frag_row, 2 * ks + frag_c));
-    };
-    auto mfma = [&](int idx, const bf16x8 (&a)[4], const bf16x8 (&b)[4]) {
-        const int i = idx >> 2, j = idx & 3;
-        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-    };
-
-    // prologue: the first NBUF stages in flight, wait for stage 0
-#pragma unroll
-    for (int p = 0; p < NBUF; ++p) {
-        prepare();
-        static_for<0, 8>(copy);
-    }
-    stage_barrier<NBUF - 1>();
-
-    // One stage = two 16-MFMA sub-steps over slot `cur`:
-    //   ks 0: MFMA q on fa[0], then (q < 8) read fragment q of ks 1 into fa[1]
-    //   ks 1: PRE MFMAs on fa[1]; stage barrier (stage s + 1 landed, slot
-    //         `cur` free); then MFMA q, copy q - PRE of stage s + NBUF into
-    //         slot `cur`, read fragment q - PRE of stage s + 1's ks 0 into fa[0].
-    constexpr int PRE = 2;
-    static_assert(PRE >= 1 && PRE + 8 <= 16, "the 8 copies and reads ride under MFMAs PRE .. PRE + 7");
-    bf16x8 fa[2][4], fb[2][4];
-#pragma unroll
-    for (int f = 0; f < 8; ++f) read(0, 0, f, fa[0], fb[0]);
-    int cur = 0;
-    pin();
-    auto one_stage = [&](auto more_tag) {
-        constexpr bool MORE = decltype(more_tag)::value;
-        const int nxt = cur + 1 == NBUF ? 0 : cur + 1;
-        // ks 0
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            mfma(q, fa[0], fb[0]);
-            if (q < 8) read(cur, 1, q, fa[1], fb[1]);
-            pin();
-        }
-        // ks 1
-#pragma unroll
-        for (int q = 0; q < PRE; ++q) mfma(q, fa[1], fb[1]);
-        pin();
-        if constexpr (MORE) {
-            stage_barrier<NBUF - 2>();
-            prepare();
-        }
-        pin();
-        auto step = [&](auto q_tag) {
-            constexpr int Q = decltype(q_tag)::value;
-            mfma(Q, fa[1], fb[1]);
-            if constexpr (MORE && Q - PRE < 8) {
-                copy(std::integral_constant<int, Q - PRE>{});
-                read(nxt, 0, Q - PRE, fa[0], fb[0]);
-            }
-            pin();
-        };
-        static_for<PRE, 16>(step);
-        cur = nxt;
-    };
-    for (int s = 0; s + 1 < steps; ++s) one_stage(std::true_type{});
-    one_stage(std::false_type{});
-    __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 15));   // drain the trailing loads
-    epilogue(acc, M, N, m0, n0, wm, wn, lane, alpha, beta, C, ldc);
+// Fragment read order of a sub-step (fragment f: slab f / 4, block f % 4):
+// the order the next sub-step's MFMAs use them.
+template <int NPROD>
+constexpr int read_order(int k) {
+    constexpr int x3[16] = {0, 4, 5, 6, 7, 1, 2, 3, 12, 13, 14, 15, 8, 9, 10, 11};
+    constexpr int x2[16] = {0, 4, 5, 6, 7, 1, 2, 3, 8, 12, 13, 14, 15, 9, 10, 11};
+    return NPROD == 3 ? x3[k] : x2[k];
 }
 
-// ---------------------------------------------------------------------------
-// bf16x3 with the three products fused per K block.  A stage holds the four
-// slabs [Ah | Bh | Al | Bl] of one 64-byte K block (64 KiB), two stages in the
-// ring.  Per 32-k sub-step the 16 fragments of the four slabs feed 3 x 16
-// MFMAs: hi.hi, then hi.lo, then lo.hi, so an accumulator is reused every 16
-// MFMAs.  Against the K-concatenated form this reads every operand block from
-// global memory once (2/3 of the copies), reads 2/3 of the LDS fragments per
-// MFMA and takes one stage barrier per 96 MFMAs instead of one per 32.  The
-// copies of stage s + 2 are issued right after the barrier of stage s that
-// frees its slot and must land by the next barrier, 96 MFMAs later.
-constexpr int NBUF3 = 2;
-// Fragment read order of a fused bf16x3 sub-step (fragment f: slab f / 4 of
-// Ah, Bh, Al, Bl, block f % 4): the order the next sub-step's MFMAs use them.
-constexpr int kX3Order[16] = {0, 4, 5, 6, 7, 1, 2, 3, 12, 13, 14, 15, 8, 9, 10, 11};
-constexpr int STAGE3 = 4 * SLAB;
-static_assert((size_t)NBUF3 * STAGE3 <= kSmem, "fused bf16x3 ring fits the LDS allocation");
+// Read / copy schedule of a sub-step, by MFMA index: the 16 fragment reads
+// and (after the barrier) the 16 copies are spread over the first 32 MFMAs
+// (NPROD = 3, one of each every two MFMAs) or the first 16 (NPROD = 2, one of
+// each per MFMA), leaving the rest of the sub-step for the reads to land
+// before the next sub-step's first MFMA waits for them.
+template <int NPROD>
+constexpr int sched_stride() { return NPROD == 3 ? 2 : 1; }
 
+template <int NPROD>
 __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(1, 1)))
-void gemm_bf16x3_fused_kernel(int64_t M, int64_t N, int nkb, float alpha,
-                              const uint8_t* __restrict__ Ah, const uint8_t* __restrict__ Al,
-                              const uint8_t* __restrict__ Bh, const uint8_t* __restrict__ Bl,
-                              float beta, float* __restrict__ C, int64_t ldc, int tiles_m,
-                              int tiles_n) {
+void gemm_bf16_slab4_kernel(int64_t M, int64_t N, int nkb, float alpha,
+                            const uint8_t* __restrict__ Ah, const uint8_t* __restrict__ Al,
+                            const uint8_t* __restrict__ Bh, const uint8_t* __restrict__ Bl,
+                            float beta, float* __restrict__ C, int64_t ldc, int tiles_m,
+                            int tiles_n) {
+    static_assert(NPROD == 2 || NPROD == 3, "bf16 (2 K blocks per stage) or bf16x3");
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
-    // LDS ring: slot i = [Ah slab | Bh slab | Al slab | Bl slab] at i * STAGE3
+    // LDS ring: slot i = four slabs at i * STAGE4
 
     const int t = threadIdx.x, lane = t & 63;
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);   // wave-uniform (SGPR)
@@ -324,9 +198,11 @@ void gemm_bf16x3_fused_kernel(int64_t M, int64_t N, int nkb, float alpha,
     const int src_off = wave * 4096 + lane * 16;
     const uint8_t* a_hi = Ah + tm * panel + src_off;
     const uint8_t* b_hi = Bh + tn * panel + src_off;
-    const uint8_t* a_lo = Al + tm * panel + src_off;
-    const uint8_t* b_lo = Bl + tn * panel + src_off;
-    const int steps = nkb;
+    const uint8_t* a_lo = NPROD == 3 ? Al + tm * panel + src_off : a_hi;
+    const uint8_t* b_lo = NPROD == 3 ? Bl + tn * panel + src_off : b_hi;
+    // K blocks per stage: 1 (bf16x3) or 2 (bf16; nkb is even)
+    constexpr int KB = NPROD == 3 ? 1 : 2;
+    const int steps = nkb / KB;
 
     floatx16 acc[4][4];
 #pragma unroll
@@ -336,74 +212,78 @@ void gemm_bf16x3_fused_kernel(int64_t M, int64_t N, int nkb, float alpha,
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-    // Load cursor: K block, slot; past the last block it re-reads the last
-    // one into the freed slot, so every stage issues the same 16 copies.
-    int ld_kb = 0, ld_left = steps, ld_slot = 0;
+    // Load cursor (stage, slot); past the last stage it re-reads the last one
+    // into the freed slot, so every stage issues the same 16 copies.
+    int ld_st = 0, ld_left = steps, ld_slot = 0;
     int64_t kofs = 0;
     uint8_t* dd = nullptr;
     auto prepare = [&]() {
-        kofs = (int64_t)ld_kb * SLAB;
-        dd = smem + ld_slot * STAGE3 + wave * 4096;
+        kofs = (int64_t)ld_st * KB * SLAB;
+        dd = smem + ld_slot * STAGE4 + wave * 4096;
         const int go = ld_left > 1 ? 1 : 0;
         ld_left -= go;
-        ld_kb += go;
+        ld_st += go;
         ld_slot ^= 1;
     };
     auto copy = [&](auto part_tag) {            // copy P: slab P / 4, part P % 4
         constexpr int P = decltype(part_tag)::value;
-        static_assert(P >= 0 && P < 16, "a fused stage is 16 copies");
+        static_assert(P >= 0 && P < 16, "a stage is 16 copies");
         constexpr int S = P / 4;
-        const uint8_t* src = S == 0 ? a_hi : (S == 1 ? b_hi : (S == 2 ? a_lo : b_lo));
-        dma_part<P % 4>(src + kofs, dd + S * SLAB);
+        const uint8_t* src;
+        if constexpr (NPROD == 3) src = (S == 0 ? a_hi : (S == 1 ? b_hi : (S == 2 ? a_lo : b_lo))) + kofs;
+        else src = ((S & 1) ? b_hi : a_hi) + kofs + (S / 2) * SLAB;
+        dma_part<P % 4>(src, dd + S * SLAB);
     };
 
-    // fragment f of a sub-step: slab f / 4 (Ah, Bh, Al, Bl), 32-row block f % 4
+    // fragment f of a sub-step: slab f / 4 (even slabs are A sides, odd B
+    // sides), 32-row block f % 4; lane l feeds row l % 32, k-chunk 2 ks + l / 32
     const int frag_row = lane & 31;
     const int frag_c = lane >> 5;
     auto read = [&](int slot, int ks, auto f_tag, bf16x8 (&F)[16]) {
         constexpr int f = decltype(f_tag)::value;
         constexpr int S = f / 4, blk = f % 4;
         const int r = ((S & 1) ? wn : wm) * 128 + blk * 32 + frag_row;
-        F[f] = *reinterpret_cast<const bf16x8*>(smem + slot * STAGE3 + S * SLAB + slab_off(r, 2 * ks + frag_c));
+        F[f] = *reinterpret_cast<const bf16x8*>(smem + slot * STAGE4 + S * SLAB + slab_off(r, 2 * ks + frag_c));
     };
-    // MFMA q of a sub-step: product q / 16 (hi.hi, hi.lo, lo.hi), block q % 16
+    // MFMA q of a sub-step: product q / 16, block q % 16
     auto mfma = [&](auto q_tag, const bf16x8 (&F)[16]) {
         constexpr int q = decltype(q_tag)::value;
         constexpr int p = q / 16, i = (q % 16) / 4, j = q % 4;
-        constexpr int fa = (p == 2 ? 8 : 0) + i, fb = (p == 1 ? 12 : 4) + j;
+        constexpr int fa = 4 * prod_a<NPROD>(p) + i, fb = 4 * prod_b<NPROD>(p) + j;
         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(F[fa], F[fb], acc[i][j], 0, 0, 0);
     };
 
     // prologue: stages 0 and 1 in flight, wait for stage 0
 #pragma unroll
-    for (int p = 0; p < NBUF3; ++p) {
+    for (int p = 0; p < NBUF4; ++p) {
         prepare();
         static_for<0, 16>(copy);
     }
-    stage_barrier<2>();                         // 16 copies (stage 1) may stay in flight
+    stage_barrier<16>();                        // stage 1 (16 copies) may stay in flight
 
-    // Fragment reads go in the order the next sub-step uses them (Ah0, Bh0-3,
-    // Ah1-3 for hi.hi, then Bl for hi.lo, then Al for lo.hi), one every two
-    // MFMAs with the copies between them, over the first two thirds of the
-    // sub-step: LDS reads and copy writes are spread instead of bursting, and
-    // the last third leaves the reads time to land before the next wait.
+    constexpr int NM = 16 * NPROD;              // MFMAs per sub-step
+    constexpr int ST = sched_stride<NPROD>();
+    static_assert(1 + 16 * ST <= NM, "reads and copies fit the sub-step");
     bf16x8 F0[16], F1[16];
-    static_for<0, 16>([&](auto k) { read(0, 0, std::integral_constant<int, kX3Order[decltype(k)::value]>{}, F0); });
+    static_for<0, 16>([&](auto k) {
+        read(0, 0, std::integral_constant<int, read_order<NPROD>(decltype(k)::value)>{}, F0);
+    });
     int cur = 0;
     pin();
-    // One stage = two sub-steps of 48 MFMAs over slot `cur`:
-    //   ks 0: MFMA q on F0; after MFMA 2k, read fragment kX3Order[k] of ks 1 into F1
+    // One stage = two sub-steps of NM MFMAs over slot `cur`:
+    //   ks 0: MFMA q on F0; after MFMA ST k, read fragment read_order(k) of ks 1 into F1
     //   ks 1: one MFMA on F1; stage barrier (stage s + 1 landed, slot `cur`
-    //         free); then MFMA q = 1 + m on F1 with, for m = 2k, the read of
-    //         fragment kX3Order[k] of stage s + 1's ks 0 into F0 and, for
-    //         m = 2k + 1, copy k of stage s + 2 into slot `cur`.
+    //         free); then MFMA q = 1 + m on F1 with, for m = ST k, the read
+    //         of fragment read_order(k) of stage s + 1's ks 0 into F0 and
+    //         copy k of stage s + 2 into slot `cur`.
     auto one_stage = [&](auto more_tag) {
         constexpr bool MORE = decltype(more_tag)::value;
         const int nxt = cur ^ 1;
-        static_for<0, 48>([&](auto q) {
+        static_for<0, NM>([&](auto q) {
             constexpr int Q = decltype(q)::value;
             mfma(q, F0);
-            if constexpr (Q % 2 == 0 && Q < 32) read(cur, 1, std::integral_constant<int, kX3Order[Q / 2]>{}, F1);
+            if constexpr (Q % ST == 0 && Q / ST < 16)
+                read(cur, 1, std::integral_constant<int, read_order<NPROD>(Q / ST)>{}, F1);
             pin();
         });
         mfma(std::integral_constant<int, 0>{}, F1);
@@ -413,11 +293,13 @@ void gemm_bf16x3_fused_kernel(int64_t M, int64_t N, int nkb, float alpha,
             prepare();
         }
         pin();
-        static_for<1, 48>([&](auto q) {
+        static_for<1, NM>([&](auto q) {
             constexpr int m = decltype(q)::value - 1;
             mfma(q, F1);
-            if constexpr (MORE && m % 2 == 0 && m < 32) read(nxt, 0, std::integral_constant<int, kX3Order[m / 2]>{}, F0);
-            if constexpr (MORE && m % 2 == 1 && m < 32) copy(std::integral_constant<int, m / 2>{});
+            if constexpr (MORE && m % ST == 0 && m / ST < 16) {
+                read(nxt, 0, std::integral_constant<int, read_order<NPROD>(m / ST)>{}, F0);
+                copy(std::integral_constant<int, m / ST>{});
+            }
             pin();
         });
         cur = nxt;
@@ -450,7 +332,7 @@ void gemm_fp8r_fused_kernel(int64_t M, int64_t N, int nkb, float alpha,
                             float beta, float* __restrict__ C, int64_t ldc, int tiles_m,
                             int tiles_n) {
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
-    // LDS ring: slot i = [Aq slab | Bq slab | Ar slab | Br slab] at i * STAGE3
+    // LDS ring: slot i = [Aq slab | Bq slab | Ar slab | Br slab] at i * STAGE4
 
     const int t = threadIdx.x, lane = t & 63;
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);   // wave-uniform (SGPR)
@@ -484,7 +366,7 @@ void gemm_fp8r_fused_kernel(int64_t M, int64_t N, int nkb, float alpha,
     uint8_t* dd = nullptr;
     auto prepare = [&]() {
         kofs = (int64_t)ld_kb * SLAB;
-        dd = smem + ld_slot * STAGE3 + wave * 4096;
+        dd = smem + ld_slot * STAGE4 + wave * 4096;
         const int go = ld_left > 1 ? 1 : 0;
         ld_left -= go;
         ld_kb += go;
@@ -539,7 +421,7 @@ void gemm_fp8r_fused_kernel(int64_t M, int64_t N, int nkb, float alpha,
         constexpr int X = decltype(x_tag)::value, H = decltype(h_tag)::value;
         constexpr int blk = H / 2, half = H % 2;
         const int r = ((X & 1) ? wn : wm) * 128 + blk * 32 + frag_row;
-        R[X][H] = *reinterpret_cast<const intx4*>(smem + slot * STAGE3 + X * SLAB + slab_off(r, frag_c + half));
+        R[X][H] = *reinterpret_cast<const intx4*>(smem + slot * STAGE4 + X * SLAB + slab_off(r, frag_c + half));
     };
     // MFMA q (0..15) of product P (0 q.q, 1 q.r, 2 r.q, 3 r.r)
     auto mfma = [&](auto p_tag, auto q_tag) {
@@ -567,7 +449,7 @@ void gemm_fp8r_fused_kernel(int64_t M, int64_t N, int nkb, float alpha,
     unpack_next();
     advance_scales();                            // stage 0's scales
     load_scale_words();                          // stage 1's words
-    stage_barrier<2>();                          // stage 1 (16 copies) may stay in flight
+    stage_barrier<16>();                         // stage 1 (16 copies) may stay in flight
     static_for<0, 8>([&](auto h) { read(0, I0{}, h); });
     static_for<0, 8>([&](auto h) { read(0, I1{}, h); });
     int cur = 0;
@@ -624,20 +506,20 @@ void gemm_fp8r_fused_kernel(int64_t M, int64_t N, int nkb, float alpha,
     epilogue(acc, M, N, m0, n0, wm, wn, lane, alpha, beta, C, ldc);
 }
 
-template <int NTERMS>
-hipError_t launch_bf16_terms(int64_t M, int64_t N, int64_t Kp, float alpha, const uint16_t* Ah,
+template <int NPROD>
+hipError_t launch_bf16_slab4(int64_t M, int64_t N, int64_t Kp, float alpha, const uint16_t* Ah,
                              const uint16_t* Al, const uint16_t* Bh, const uint16_t* Bl, float beta,
                              float* C, int64_t ldc, hipStream_t stream) {
     static bool attr = false;
     if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)gemm_bf16_tn_kernel<NTERMS>,
+        hipError_t e = hipFuncSetAttribute((const void*)gemm_bf16_slab4_kernel<NPROD>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmem);
         if (e != hipSuccess) return e;
         attr = true;
     }
     const int tiles_m = (int)((M + TM - 1) / TM), tiles_n = (int)((N + TN - 1) / TN);
     const int nkb = (int)(Kp * 2 / kPanelRowBytes);
-    hipLaunchKernelGGL(gemm_bf16_tn_kernel<NTERMS>, dim3(tiles_m * tiles_n), dim3(THREADS), kSmem,
+    hipLaunchKernelGGL(gemm_bf16_slab4_kernel<NPROD>, dim3(tiles_m * tiles_n), dim3(THREADS), kSmem,
                        stream, M, N, nkb, alpha, (const uint8_t*)Ah, (const uint8_t*)Al,
                        (const uint8_t*)Bh, (const uint8_t*)Bl, beta, C, ldc, tiles_m, tiles_n);
     return hipGetLastError();
@@ -649,22 +531,11 @@ hipError_t launch_gemm_bf16_tn(int64_t M, int64_t N, int64_t Kp, int nterms, flo
                                const uint16_t* Ah, const uint16_t* Al, const uint16_t* Bh,
                                const uint16_t* Bl, float beta, float* C, int64_t ldc,
                                hipStream_t stream) {
+    // Kp % 64 == 0: a whole number of 2-block stages for the one-term kernel
     if (Kp % kBf16TileK || Kp <= 0 || (nterms != 1 && nterms != 3) || (nterms == 3 && (!Al || !Bl)))
         return hipErrorInvalidValue;
-    if (nterms == 1) return launch_bf16_terms<1>(M, N, Kp, alpha, Ah, Al, Bh, Bl, beta, C, ldc, stream);
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)gemm_bf16x3_fused_kernel,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmem);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
-    const int tiles_m = (int)((M + TM - 1) / TM), tiles_n = (int)((N + TN - 1) / TN);
-    const int nkb = (int)(Kp * 2 / kPanelRowBytes);
-    hipLaunchKernelGGL(gemm_bf16x3_fused_kernel, dim3(tiles_m * tiles_n), dim3(THREADS), kSmem,
-                       stream, M, N, nkb, alpha, (const uint8_t*)Ah, (const uint8_t*)Al,
-                       (const uint8_t*)Bh, (const uint8_t*)Bl, beta, C, ldc, tiles_m, tiles_n);
-    return hipGetLastError();
+    if (nterms == 1) return launch_bf16_slab4<2>(M, N, Kp, alpha, Ah, Al, Bh, Bl, beta, C, ldc, stream);
+    return launch_bf16_slab4<3>(M, N, Kp, alpha, Ah, Al, Bh, Bl, beta, C, ldc, stream);
 }
 
 hipError_t launch_gemm_fp8r_tn(int64_t M, int64_t N, int64_t Kp, float alpha, const uint8_t* Aq,
