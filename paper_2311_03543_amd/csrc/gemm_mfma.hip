@@ -11,16 +11,16 @@
 //
 // Tiling: 256 x 256 C tile per workgroup of 4 wave64 (2 x 2 waves, 128 x 128
 // per wave = 4 x 4 MFMA blocks of 32 x 32, 256 FP32 accumulators per lane).
-// A pipeline stage holds four 16 KiB slabs (256 rows x 64 bytes of K, each one
-// contiguous panel-image block) in a 2-slot LDS ring: the operand blocks of
-// one K block that feed all the products using them (bf16x3: Ah Bh Al Bl;
-// fp8: Aq Bq Ar Br), or two consecutive K blocks of A and B (bf16).  Direct
+// Operands move in 16 KiB slabs (256 rows x 64 bytes of K, each one
+// contiguous panel-image block) through an LDS ring.  The multi-product
+// variants stage the four slabs of one K block that feed all their products
+// (bf16x3: Ah Bh Al Bl; fp8: Aq Bq Ar Br) in a 2-slot ring; one-term bf16
+// stages the A and B slabs of one K block in a 4-slot ring.  Direct
 // global->LDS loads (global_load_lds_dwordx4) copy the slabs as linear 1 KiB
 // pieces whose immediate offset advances the global and the LDS address
-// together; the copies of stage s + 2 go out right after the barrier of stage
-// s that frees their slot and have one whole stage of MFMAs to land.  The
-// instruction order of every main loop is pinned: each MFMA is followed by the
-// copy and fragment reads that ride under it.
+// together; a stage's copies go out right after the barrier that frees their
+// slot.  The instruction order of every main loop is pinned: each MFMA is
+// followed by the copy and fragment reads that ride under it.
 #include <type_traits>
 
 #include "common.h"
@@ -140,51 +140,165 @@ __device__ __forceinline__ void tile_coords(int tiles_m, int tiles_n, int& tm, i
 }
 
 // ---------------------------------------------------------------------------
-// bf16 kernels over four-slab stages.  A stage holds four 16 KiB slabs (64
-// KiB), two stages in the LDS ring; per 16-k sub-step (two per stage) the 16
-// fragments of the four slabs (4 blocks of 32 rows each) feed NPROD x 16
-// MFMAs, one product after the other so an accumulator is reused every 16
-// MFMAs.
-//   NPROD = 3 (bf16x3): slabs [Ah | Bh | Al | Bl] of one 64-byte K block;
-//            products hi.hi, hi.lo, lo.hi.  Every operand block is copied once
-//            and feeds all the products that use it.
-//   NPROD = 2 (bf16):   slabs [A | B | A' | B'] of two consecutive K blocks;
-//            products A.B and A'.B'.
-// The copies of stage s + 2 are issued right after the barrier of stage s
-// that frees its slot and must land by the next barrier, one stage later;
-// one barrier per 32 NPROD MFMAs.
+// One-term bf16: a stage is one 64-byte K block of A and B (16 KiB slabs),
+// NRING = 4 stages in the LDS ring.  The copies of stage s + 4 go out right
+// after the barrier of stage s that frees its slot, so a copy has three stages
+// (96 MFMAs) to land; the barrier waits only for stage s + 1
+// (vmcnt(16): the two younger stages stay in flight).  With a single product
+// the deeper ring beats the four-slab stage: its copies get one and a half
+// times the cover for the price of one barrier per 32 MFMAs.
+constexpr int NRING = 4;
+constexpr int RSTAGE = 2 * SLAB;
+static_assert((size_t)NRING * RSTAGE <= kSmem, "ring fits the LDS allocation");
 
-// Slabs (A side, B side) of product p.
-template <int NPROD>
-constexpr int prod_a(int p) { return NPROD == 3 ? (p == 2 ? 2 : 0) : 2 * p; }
-template <int NPROD>
-constexpr int prod_b(int p) { return NPROD == 3 ? (p == 1 ? 3 : 1) : 2 * p + 1; }
+__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void gemm_bf16_ring_kernel(int64_t M, int64_t N, int nkb, float alpha, const uint8_t* __restrict__ Ah,
+                           const uint8_t* __restrict__ Bh, float beta, float* __restrict__ C,
+                           int64_t ldc, int tiles_m, int tiles_n) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    // LDS ring: slot i = [A slab | B slab] at i * RSTAGE
 
-// Fragment read order of a sub-step (fragment f: slab f / 4, block f % 4):
-// the order the next sub-step's MFMAs use them.
-template <int NPROD>
-constexpr int read_order(int k) {
-    constexpr int x3[16] = {0, 4, 5, 6, 7, 1, 2, 3, 12, 13, 14, 15, 8, 9, 10, 11};
-    constexpr int x2[16] = {0, 4, 5, 6, 7, 1, 2, 3, 8, 12, 13, 14, 15, 9, 10, 11};
-    return NPROD == 3 ? x3[k] : x2[k];
+    const int t = threadIdx.x, lane = t & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);   // wave-uniform (SGPR)
+    const int wm = wave >> 1, wn = wave & 1;
+    int tm, tn;
+    tile_coords(tiles_m, tiles_n, tm, tn);
+    const int64_t m0 = (int64_t)tm * TM, n0 = (int64_t)tn * TN;
+    const int64_t panel = (int64_t)nkb * SLAB;        // bytes of one 256-row panel
+    const int src_off = wave * 4096 + lane * 16;
+    const uint8_t* a_src = Ah + tm * panel + src_off;
+    const uint8_t* b_src = Bh + tn * panel + src_off;
+    const int steps = nkb;
+
+    floatx16 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+    // Load cursor (K block, slot); past the last block it re-reads the last
+    // one into the freed slot, so every stage issues the same 8 copies and the
+    // in-flight count the barriers wait on stays constant.
+    int ld_kb = 0, ld_left = steps, ld_slot = 0;
+    int64_t kofs = 0;
+    uint8_t* dd = nullptr;
+    auto prepare = [&]() {
+        kofs = (int64_t)ld_kb * SLAB;
+        dd = smem + ld_slot * RSTAGE + wave * 4096;
+        const int go = ld_left > 1 ? 1 : 0;
+        ld_left -= go;
+        ld_kb += go;
+        ld_slot = ld_slot + 1 == NRING ? 0 : ld_slot + 1;
+    };
+    auto copy = [&](auto part_tag) {            // copy P: A (P < 4) or B slab, part P % 4
+        constexpr int P = decltype(part_tag)::value;
+        static_assert(P >= 0 && P < 8, "a stage is 8 copies");
+        if constexpr (P < 4) dma_part<P>(a_src + kofs, dd);
+        else dma_part<P - 4>(b_src + kofs, dd + SLAB);
+    };
+
+    // lane l feeds row l % 32 of each 32-row block, k-chunk 2 ks + l / 32;
+    // fragment f < 4 is A block f, f >= 4 is B block f - 4
+    const int frag_row = lane & 31;
+    const int frag_c = lane >> 5;
+    auto read = [&](int slot, int ks, int f, bf16x8 (&a)[4], bf16x8 (&b)[4]) {
+        const uint8_t* base = smem + slot * RSTAGE;
+        if (f < 4)
+            a[f] = *reinterpret_cast<const bf16x8*>(base + slab_off(wm * 128 + f * 32 + frag_row, 2 * ks + frag_c));
+        else
+            b[f - 4] = *reinterpret_cast<const bf16x8*>(base + SLAB + slab_off(wn * 128 + (f - 4) * 32 + frag_row, 2 * ks + frag_c));
+    };
+    auto mfma = [&](int idx, const bf16x8 (&a)[4], const bf16x8 (&b)[4]) {
+        const int i = idx >> 2, j = idx & 3;
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    };
+
+    // prologue: the first NRING stages in flight, wait for stage 0
+#pragma unroll
+    for (int p = 0; p < NRING; ++p) {
+        prepare();
+        static_for<0, 8>(copy);
+    }
+    stage_barrier<8 * (NRING - 1)>();
+
+    // One stage = two 16-MFMA sub-steps over slot `cur`:
+    //   ks 0: MFMA q on fa[0], then (q < 8) read fragment q of ks 1 into fa[1]
+    //   ks 1: PRE MFMAs on fa[1]; stage barrier (stage s + 1 landed, slot
+    //         `cur` free); then MFMA q, copy q - PRE of stage s + NRING into
+    //         slot `cur`, read fragment q - PRE of stage s + 1's ks 0 into fa[0].
+    constexpr int PRE = 2;
+    static_assert(PRE >= 1 && PRE + 8 <= 16, "the 8 copies and reads ride under MFMAs PRE .. PRE + 7");
+    bf16x8 fa[2][4], fb[2][4];
+#pragma unroll
+    for (int f = 0; f < 8; ++f) read(0, 0, f, fa[0], fb[0]);
+    int cur = 0;
+    pin();
+    auto one_stage = [&](auto more_tag) {
+        constexpr bool MORE = decltype(more_tag)::value;
+        const int nxt = cur + 1 == NRING ? 0 : cur + 1;
+        // ks 0
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            mfma(q, fa[0], fb[0]);
+            if (q < 8) read(cur, 1, q, fa[1], fb[1]);
+            pin();
+        }
+        // ks 1
+#pragma unroll
+        for (int q = 0; q < PRE; ++q) mfma(q, fa[1], fb[1]);
+        pin();
+        if constexpr (MORE) {
+            stage_barrier<8 * (NRING - 2)>();
+            prepare();
+        }
+        pin();
+        static_for<PRE, 16>([&](auto q_tag) {
+            constexpr int Q = decltype(q_tag)::value;
+            mfma(Q, fa[1], fb[1]);
+            if constexpr (MORE && Q - PRE < 8) {
+                copy(std::integral_constant<int, Q - PRE>{});
+                read(nxt, 0, Q - PRE, fa[0], fb[0]);
+            }
+            pin();
+        });
+        cur = nxt;
+    };
+    for (int s = 0; s + 1 < steps; ++s) one_stage(std::true_type{});
+    one_stage(std::false_type{});
+    __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 15));   // drain the trailing copies
+    epilogue(acc, M, N, m0, n0, wm, wn, lane, alpha, beta, C, ldc);
 }
 
-// Read / copy schedule of a sub-step, by MFMA index: the 16 fragment reads
-// and (after the barrier) the 16 copies are spread over the first 32 MFMAs
-// (NPROD = 3, one of each every two MFMAs) or the first 16 (NPROD = 2, one of
-// each per MFMA), leaving the rest of the sub-step for the reads to land
-// before the next sub-step's first MFMA waits for them.
-template <int NPROD>
-constexpr int sched_stride() { return NPROD == 3 ? 2 : 1; }
+// ---------------------------------------------------------------------------
+// bf16x3 over four-slab stages: a stage holds the slabs [Ah | Bh | Al | Bl]
+// of one 64-byte K block (64 KiB), two stages in the LDS ring.  Per 16-k
+// sub-step (two per stage) the 16 fragments of the four slabs (4 blocks of 32
+// rows each) feed 3 x 16 MFMAs, hi.hi, then hi.lo, then lo.hi, so an
+// accumulator is reused every 16 MFMAs.  Every operand block is copied once
+// and feeds all the products that use it.  The copies of stage s + 2 are
+// issued right after the barrier of stage s that frees its slot and must land
+// by the next barrier, one stage (96 MFMAs) later.
 
-template <int NPROD>
+// Slabs (A side, B side) of product p: hi.hi, hi.lo, lo.hi.
+constexpr int prod_a(int p) { return p == 2 ? 2 : 0; }
+constexpr int prod_b(int p) { return p == 1 ? 3 : 1; }
+
+// Fragment read order of a sub-step (fragment f: slab f / 4, block f % 4):
+// the order the next sub-step's MFMAs use them (Ah0, Bh0-3, Ah1-3 for
+// hi.hi, then Bl for hi.lo, then Al for lo.hi).
+constexpr int read_order(int k) {
+    constexpr int order[16] = {0, 4, 5, 6, 7, 1, 2, 3, 12, 13, 14, 15, 8, 9, 10, 11};
+    return order[k];
+}
+
 __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(1, 1)))
-void gemm_bf16_slab4_kernel(int64_t M, int64_t N, int nkb, float alpha,
-                            const uint8_t* __restrict__ Ah, const uint8_t* __restrict__ Al,
-                            const uint8_t* __restrict__ Bh, const uint8_t* __restrict__ Bl,
-                            float beta, float* __restrict__ C, int64_t ldc, int tiles_m,
-                            int tiles_n) {
-    static_assert(NPROD == 2 || NPROD == 3, "bf16 (2 K blocks per stage) or bf16x3");
+void gemm_bf16x3_slab4_kernel(int64_t M, int64_t N, int nkb, float alpha,
+                              const uint8_t* __restrict__ Ah, const uint8_t* __restrict__ Al,
+                              const uint8_t* __restrict__ Bh, const uint8_t* __restrict__ Bl,
+                              float beta, float* __restrict__ C, int64_t ldc, int tiles_m,
+                              int tiles_n) {
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
     // LDS ring: slot i = four slabs at i * STAGE4
 
@@ -198,11 +312,9 @@ void gemm_bf16_slab4_kernel(int64_t M, int64_t N, int nkb, float alpha,
     const int src_off = wave * 4096 + lane * 16;
     const uint8_t* a_hi = Ah + tm * panel + src_off;
     const uint8_t* b_hi = Bh + tn * panel + src_off;
-    const uint8_t* a_lo = NPROD == 3 ? Al + tm * panel + src_off : a_hi;
-    const uint8_t* b_lo = NPROD == 3 ? Bl + tn * panel + src_off : b_hi;
-    // K blocks per stage: 1 (bf16x3) or 2 (bf16; nkb is even)
-    constexpr int KB = NPROD == 3 ? 1 : 2;
-    const int steps = nkb / KB;
+    const uint8_t* a_lo = Al + tm * panel + src_off;
+    const uint8_t* b_lo = Bl + tn * panel + src_off;
+    const int steps = nkb;
 
     floatx16 acc[4][4];
 #pragma unroll
@@ -218,7 +330,7 @@ void gemm_bf16_slab4_kernel(int64_t M, int64_t N, int nkb, float alpha,
     int64_t kofs = 0;
     uint8_t* dd = nullptr;
     auto prepare = [&]() {
-        kofs = (int64_t)ld_st * KB * SLAB;
+        kofs = (int64_t)ld_st * SLAB;
         dd = smem + ld_slot * STAGE4 + wave * 4096;
         const int go = ld_left > 1 ? 1 : 0;
         ld_left -= go;
@@ -229,10 +341,8 @@ void gemm_bf16_slab4_kernel(int64_t M, int64_t N, int nkb, float alpha,
         constexpr int P = decltype(part_tag)::value;
         static_assert(P >= 0 && P < 16, "a stage is 16 copies");
         constexpr int S = P / 4;
-        const uint8_t* src;
-        if constexpr (NPROD == 3) src = (S == 0 ? a_hi : (S == 1 ? b_hi : (S == 2 ? a_lo : b_lo))) + kofs;
-        else src = ((S & 1) ? b_hi : a_hi) + kofs + (S / 2) * SLAB;
-        dma_part<P % 4>(src, dd + S * SLAB);
+        const uint8_t* src = S == 0 ? a_hi : (S == 1 ? b_hi : (S == 2 ? a_lo : b_lo));
+        dma_part<P % 4>(src + kofs, dd + S * SLAB);
     };
 
     // fragment f of a sub-step: slab f / 4 (even slabs are A sides, odd B
@@ -249,7 +359,7 @@ void gemm_bf16_slab4_kernel(int64_t M, int64_t N, int nkb, float alpha,
     auto mfma = [&](auto q_tag, const bf16x8 (&F)[16]) {
         constexpr int q = decltype(q_tag)::value;
         constexpr int p = q / 16, i = (q % 16) / 4, j = q % 4;
-        constexpr int fa = 4 * prod_a<NPROD>(p) + i, fb = 4 * prod_b<NPROD>(p) + j;
+        constexpr int fa = 4 * prod_a(p) + i, fb = 4 * prod_b(p) + j;
         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(F[fa], F[fb], acc[i][j], 0, 0, 0);
     };
 
@@ -261,12 +371,15 @@ void gemm_bf16_slab4_kernel(int64_t M, int64_t N, int nkb, float alpha,
     }
     stage_barrier<16>();                        // stage 1 (16 copies) may stay in flight
 
-    constexpr int NM = 16 * NPROD;              // MFMAs per sub-step
-    constexpr int ST = sched_stride<NPROD>();
+    constexpr int NM = 48;                      // MFMAs per sub-step
+    // the 16 fragment reads and (after the barrier) the 16 copies go one
+    // every ST = 2 MFMAs over the first 32 MFMAs of a sub-step, leaving the
+    // last 16 for the reads to land before the next sub-step's first MFMA
+    constexpr int ST = 2;
     static_assert(1 + 16 * ST <= NM, "reads and copies fit the sub-step");
     bf16x8 F0[16], F1[16];
     static_for<0, 16>([&](auto k) {
-        read(0, 0, std::integral_constant<int, read_order<NPROD>(decltype(k)::value)>{}, F0);
+        read(0, 0, std::integral_constant<int, read_order(decltype(k)::value)>{}, F0);
     });
     int cur = 0;
     pin();
@@ -283,7 +396,7 @@ void gemm_bf16_slab4_kernel(int64_t M, int64_t N, int nkb, float alpha,
             constexpr int Q = decltype(q)::value;
             mfma(q, F0);
             if constexpr (Q % ST == 0 && Q / ST < 16)
-                read(cur, 1, std::integral_constant<int, read_order<NPROD>(Q / ST)>{}, F1);
+                read(cur, 1, std::integral_constant<int, read_order(Q / ST)>{}, F1);
             pin();
         });
         mfma(std::integral_constant<int, 0>{}, F1);
@@ -297,7 +410,7 @@ void gemm_bf16_slab4_kernel(int64_t M, int64_t N, int nkb, float alpha,
             constexpr int m = decltype(q)::value - 1;
             mfma(q, F1);
             if constexpr (MORE && m % ST == 0 && m / ST < 16) {
-                read(nxt, 0, std::integral_constant<int, read_order<NPROD>(m / ST)>{}, F0);
+                read(nxt, 0, std::integral_constant<int, read_order(m / ST)>{}, F0);
                 copy(std::integral_constant<int, m / ST>{});
             }
             pin();
@@ -506,36 +619,40 @@ void gemm_fp8r_fused_kernel(int64_t M, int64_t N, int nkb, float alpha,
     epilogue(acc, M, N, m0, n0, wm, wn, lane, alpha, beta, C, ldc);
 }
 
-template <int NPROD>
-hipError_t launch_bf16_slab4(int64_t M, int64_t N, int64_t Kp, float alpha, const uint16_t* Ah,
-                             const uint16_t* Al, const uint16_t* Bh, const uint16_t* Bl, float beta,
-                             float* C, int64_t ldc, hipStream_t stream) {
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)gemm_bf16_slab4_kernel<NPROD>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmem);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
-    const int tiles_m = (int)((M + TM - 1) / TM), tiles_n = (int)((N + TN - 1) / TN);
-    const int nkb = (int)(Kp * 2 / kPanelRowBytes);
-    hipLaunchKernelGGL(gemm_bf16_slab4_kernel<NPROD>, dim3(tiles_m * tiles_n), dim3(THREADS), kSmem,
-                       stream, M, N, nkb, alpha, (const uint8_t*)Ah, (const uint8_t*)Al,
-                       (const uint8_t*)Bh, (const uint8_t*)Bl, beta, C, ldc, tiles_m, tiles_n);
-    return hipGetLastError();
-}
-
 }  // namespace
 
 hipError_t launch_gemm_bf16_tn(int64_t M, int64_t N, int64_t Kp, int nterms, float alpha,
                                const uint16_t* Ah, const uint16_t* Al, const uint16_t* Bh,
                                const uint16_t* Bl, float beta, float* C, int64_t ldc,
                                hipStream_t stream) {
-    // Kp % 64 == 0: a whole number of 2-block stages for the one-term kernel
     if (Kp % kBf16TileK || Kp <= 0 || (nterms != 1 && nterms != 3) || (nterms == 3 && (!Al || !Bl)))
         return hipErrorInvalidValue;
-    if (nterms == 1) return launch_bf16_slab4<2>(M, N, Kp, alpha, Ah, Al, Bh, Bl, beta, C, ldc, stream);
-    return launch_bf16_slab4<3>(M, N, Kp, alpha, Ah, Al, Bh, Bl, beta, C, ldc, stream);
+    const int tiles_m = (int)((M + TM - 1) / TM), tiles_n = (int)((N + TN - 1) / TN);
+    const int nkb = (int)(Kp * 2 / kPanelRowBytes);
+    if (nterms == 3) {
+        static bool attr3 = false;
+        if (!attr3) {
+            hipError_t e = hipFuncSetAttribute((const void*)gemm_bf16x3_slab4_kernel,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmem);
+            if (e != hipSuccess) return e;
+            attr3 = true;
+        }
+        hipLaunchKernelGGL(gemm_bf16x3_slab4_kernel, dim3(tiles_m * tiles_n), dim3(THREADS), kSmem,
+                           stream, M, N, nkb, alpha, (const uint8_t*)Ah, (const uint8_t*)Al,
+                           (const uint8_t*)Bh, (const uint8_t*)Bl, beta, C, ldc, tiles_m, tiles_n);
+        return hipGetLastError();
+    }
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)gemm_bf16_ring_kernel,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmem);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    hipLaunchKernelGGL(gemm_bf16_ring_kernel, dim3(tiles_m * tiles_n), dim3(THREADS), kSmem, stream,
+                       M, N, nkb, alpha, (const uint8_t*)Ah, (const uint8_t*)Bh, beta, C, ldc, tiles_m,
+                       tiles_n);
+    return hipGetLastError();
 }
 
 hipError_t launch_gemm_fp8r_tn(int64_t M, int64_t N, int64_t Kp, float alpha, const uint8_t* Aq,
