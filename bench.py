@@ -437,6 +437,20 @@ def selector_experiment(cx, pa, torch, args):
     t4 = time.perf_counter()
     res["mlp"] = regret(Tho, mlp_choice, tol_ho)
     res["always_fp32"] = regret(Tho, [0] * len(q), tol_ho)
+    # per-call decision cost: the 500 held-out contexts through cmp_select_batch, first
+    # uncached (network inference or nearest-neighbour search), then from the decision cache
+    # (the path every repeated call takes), averaged over 200 passes
+    decision_us = {}
+    for kind, label in [(pa.CMP_SEL_MLP, "mlp"), (pa.CMP_SEL_NN, "nn")]:
+        sel.selector_set(kind)                  # switching the selector clears the cache
+        ta = time.perf_counter()
+        sel.select_batch(q)
+        tb = time.perf_counter()
+        for _ in range(200):
+            sel.select_batch(q)
+        tc = time.perf_counter()
+        decision_us[f"{label}_uncached"] = (tb - ta) * 1e6 / len(q)
+        decision_us[f"{label}_cached"] = (tc - tb) * 1e6 / (200 * len(q))
     # the best variant differs across shapes: how often each is the held-out optimum
     best_counts = {}
     for s in range(len(held)):
@@ -448,6 +462,7 @@ def selector_experiment(cx, pa, torch, args):
     return dict(train_shapes=ntr, heldout_shapes=nho, reps=args.reps, mlp_steps=args.mlp_steps,
                 mlp_final_loss=loss, mlp_train_s=t2 - t1, mlp_select_500_ms=(t4 - t3) * 1e3,
                 calibration_s=t1 - t0, regret=res, heldout_best_counts=best_counts,
+                decision_us_per_call=decision_us,
                 regret_pct=res["mlp"]["aggregate_pct"])
 
 

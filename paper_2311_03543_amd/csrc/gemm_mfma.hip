@@ -21,6 +21,7 @@
 // together; a stage's copies go out right after the barrier that frees their
 // slot.  The instruction order of every main loop is pinned: each MFMA is
 // followed by the copy and fragment reads that ride under it.
+#include <atomic>
 #include <type_traits>
 
 #include "common.h"
@@ -619,6 +620,20 @@ void gemm_fp8r_fused_kernel(int64_t M, int64_t N, int nkb, float alpha,
     epilogue(acc, M, N, m0, n0, wm, wn, lane, alpha, beta, C, ldc);
 }
 
+// The kernels use more than the default 64 KiB of dynamic LDS; the limit is a
+// per-device function attribute, set once on each device the library runs on.
+template <class Kernel>
+hipError_t allow_lds(Kernel kernel, std::atomic<uint64_t>& done) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    const uint64_t bit = dev < 64 ? (uint64_t)1 << dev : 0;
+    if (bit && (done.load(std::memory_order_relaxed) & bit)) return hipSuccess;
+    e = hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmem);
+    if (e == hipSuccess) done.fetch_or(bit, std::memory_order_relaxed);
+    return e;
+}
+
 }  // namespace
 
 hipError_t launch_gemm_bf16_tn(int64_t M, int64_t N, int64_t Kp, int nterms, float alpha,
@@ -630,25 +645,15 @@ hipError_t launch_gemm_bf16_tn(int64_t M, int64_t N, int64_t Kp, int nterms, flo
     const int tiles_m = (int)((M + TM - 1) / TM), tiles_n = (int)((N + TN - 1) / TN);
     const int nkb = (int)(Kp * 2 / kPanelRowBytes);
     if (nterms == 3) {
-        static bool attr3 = false;
-        if (!attr3) {
-            hipError_t e = hipFuncSetAttribute((const void*)gemm_bf16x3_slab4_kernel,
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmem);
-            if (e != hipSuccess) return e;
-            attr3 = true;
-        }
+        static std::atomic<uint64_t> lds_x3{0};
+        if (hipError_t e = allow_lds(gemm_bf16x3_slab4_kernel, lds_x3)) return e;
         hipLaunchKernelGGL(gemm_bf16x3_slab4_kernel, dim3(tiles_m * tiles_n), dim3(THREADS), kSmem,
                            stream, M, N, nkb, alpha, (const uint8_t*)Ah, (const uint8_t*)Al,
                            (const uint8_t*)Bh, (const uint8_t*)Bl, beta, C, ldc, tiles_m, tiles_n);
         return hipGetLastError();
     }
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)gemm_bf16_ring_kernel,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmem);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
+    static std::atomic<uint64_t> lds_x1{0};
+    if (hipError_t e = allow_lds(gemm_bf16_ring_kernel, lds_x1)) return e;
     hipLaunchKernelGGL(gemm_bf16_ring_kernel, dim3(tiles_m * tiles_n), dim3(THREADS), kSmem, stream,
                        M, N, nkb, alpha, (const uint8_t*)Ah, (const uint8_t*)Bh, beta, C, ldc, tiles_m,
                        tiles_n);
@@ -661,13 +666,8 @@ hipError_t launch_gemm_fp8r_tn(int64_t M, int64_t N, int64_t Kp, float alpha, co
                                const uint8_t* Bsr, float beta, float* C, int64_t ldc,
                                hipStream_t stream) {
     if (Kp % kFp8TileK || Kp <= 0) return hipErrorInvalidValue;
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)gemm_fp8r_fused_kernel,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmem);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
+    static std::atomic<uint64_t> lds_f8{0};
+    if (hipError_t e = allow_lds(gemm_fp8r_fused_kernel, lds_f8)) return e;
     const int tiles_m = (int)((M + TM - 1) / TM), tiles_n = (int)((N + TN - 1) / TN);
     const int nkb = (int)(Kp / kPanelRowBytes);
     hipLaunchKernelGGL(gemm_fp8r_fused_kernel, dim3(tiles_m * tiles_n), dim3(THREADS), kSmem, stream,
