@@ -1,7 +1,8 @@
 """Per-shape error table: every variant's relative Frobenius error against the full FP64 oracle
 on the square sweep N in {128, ..., 8192} (normal(0,1), seed 1000 + log2 N) and on
 ill-conditioned operands (normal(0,1) * 2^u, u per entry in [-20, 20]).  Each entry must be
-within the variant's stated bound; the table is written to gpurun_out/error_table.md."""
+within the variant's stated bound; the table is printed and, when CMP_RESULTS_DIR names a
+directory, also written there as error_table.md."""
 import os
 
 import numpy as np
@@ -14,7 +15,6 @@ from gpu_util import dev, host, say
 pytestmark = pytest.mark.gpu
 VARIANTS = ["f32_simt", "bf16x3", "fp8r", "bf16"]
 BOUND = {"f32_simt": 1e-5, "bf16x3": 1e-5, "fp8r": 1e-3, "bf16": 1e-2}
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _errors(cx, A, B):
@@ -50,9 +50,11 @@ def test_error_table():
         lines.append(f"| {dist} | {n} | " + " | ".join(f"{e[v]:.2e}" for v in VARIANTS) + " |")
     lines.append("| stated bound | | " + " | ".join(f"{BOUND[v]:.0e}" for v in VARIANTS) + " |")
     text = "\n".join(lines) + "\n"
-    os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
-    with open(os.path.join(ROOT, "gpurun_out", "error_table.md"), "w") as f:
-        f.write(text)
+    out_dir = os.environ.get("CMP_RESULTS_DIR")
+    if out_dir:
+        os.makedirs(out_dir, exist_ok=True)
+        with open(os.path.join(out_dir, "error_table.md"), "w") as f:
+            f.write(text)
     print(text, flush=True)
     for dist, n, e in rows:
         for v in VARIANTS:
