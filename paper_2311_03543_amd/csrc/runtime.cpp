@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -70,6 +71,15 @@ struct HistRow {
     float med, mn, mean;
 };
 
+// The history grouped by shape (first-appearance order): per shape the
+// recorded median of each variant (NaN when missing) and the nearest-
+// neighbour features (log2 M, log2 N, log2 K).
+struct ShapeTable {
+    std::vector<std::tuple<int64_t, int64_t, int64_t>> shapes;
+    std::vector<std::vector<double>> med;
+    std::vector<std::array<double, 3>> lg;
+};
+
 struct CacheKey {
     int64_t M, N, K;
     double tol;
@@ -112,6 +122,11 @@ struct cmp_ctx {
     int selector = CMP_SEL_NN;
     uint32_t flags = 0;
     std::vector<HistRow> history;
+    uint64_t hist_gen = 0;            // bumped on every change of `history`
+    // shape table of the history, rebuilt when hist_gen or the variant count moves
+    mutable ShapeTable shape_cache;
+    mutable uint64_t shape_cache_gen = ~0ull;
+    mutable size_t shape_cache_nvar = 0;
     std::unordered_map<CacheKey, int, CacheHash> cache;
     // learned selector
     std::vector<float> mlp_params;
@@ -560,10 +575,6 @@ std::vector<int> admissible_ids(const Interface& f, double tol) {
 
 // Distinct shapes of the history in order of first appearance, with the last
 // recorded median per variant (NaN where none).
-struct ShapeTable {
-    std::vector<std::tuple<int64_t, int64_t, int64_t>> shapes;
-    std::vector<std::vector<double>> med;
-};
 ShapeTable shape_table(const cmp_ctx* c, size_t nvar) {
     ShapeTable T;
     std::map<std::tuple<int64_t, int64_t, int64_t>, size_t> idx;
@@ -581,11 +592,25 @@ ShapeTable shape_table(const cmp_ctx* c, size_t nvar) {
         }
         if (r.id >= 0 && (size_t)r.id < nvar) T.med[s][r.id] = r.med;
     }
+    T.lg.reserve(T.shapes.size());
+    for (auto& sh : T.shapes)
+        T.lg.push_back({std::log2((double)std::get<0>(sh)), std::log2((double)std::get<1>(sh)),
+                        std::log2((double)std::get<2>(sh))});
     return T;
+}
+// The selectors read the table on every uncached decision; build it once per
+// history change.
+const ShapeTable& shapes_of(const cmp_ctx* c, size_t nvar) {
+    if (c->shape_cache_gen != c->hist_gen || c->shape_cache_nvar != nvar) {
+        c->shape_cache = shape_table(c, nvar);
+        c->shape_cache_gen = c->hist_gen;
+        c->shape_cache_nvar = nvar;
+    }
+    return c->shape_cache;
 }
 
 int select_static(const cmp_ctx* c, const Interface& f, const std::vector<int>& adm) {
-    ShapeTable T = shape_table(c, f.variants.size());
+    const ShapeTable& T = shapes_of(c, f.variants.size());
     std::vector<double> tot(f.variants.size(), 0.0);
     size_t used = 0;
     for (size_t s = 0; s < T.shapes.size(); ++s) {
@@ -605,7 +630,7 @@ int select_static(const cmp_ctx* c, const Interface& f, const std::vector<int>& 
 
 int select_nn(const cmp_ctx* c, const Interface& f, const std::vector<int>& adm, int64_t M,
               int64_t N, int64_t K) {
-    ShapeTable T = shape_table(c, f.variants.size());
+    const ShapeTable& T = shapes_of(c, f.variants.size());
     const double q0 = std::log2((double)M), q1 = std::log2((double)N), q2 = std::log2((double)K);
     int best = -1;
     double bd = 0;
@@ -614,9 +639,9 @@ int select_nn(const cmp_ctx* c, const Interface& f, const std::vector<int>& adm,
         for (int i : adm)
             if (std::isfinite(T.med[s][i])) any = true;
         if (!any) continue;
-        const double d0 = std::log2((double)std::get<0>(T.shapes[s])) - q0;
-        const double d1 = std::log2((double)std::get<1>(T.shapes[s])) - q1;
-        const double d2 = std::log2((double)std::get<2>(T.shapes[s])) - q2;
+        const double d0 = T.lg[s][0] - q0;
+        const double d1 = T.lg[s][1] - q1;
+        const double d2 = T.lg[s][2] - q2;
         const double d = d0 * d0 + d1 * d1 + d2 * d2;
         if (best < 0 || d < bd) {
             best = (int)s;
@@ -1185,6 +1210,7 @@ CMP_API int cmp_history_add(cmp_ctx* c, int64_t M, int64_t N, int64_t K, int id,
     if (id < 0 || id >= (int)f->variants.size()) return fail(c, CMP_EINVAL, "bad variant id %d", id);
     if (!(med > 0) || !std::isfinite(med)) return fail(c, CMP_EINVAL, "median must be > 0");
     c->history.push_back(HistRow{M, N, K, id, reps, med, mn, mean});
+    ++c->hist_gen;
     c->cache.clear();
     return CMP_OK;
 }
@@ -1217,6 +1243,7 @@ CMP_API int cmp_calibrate(cmp_ctx* c, int nshapes, const int64_t* mnk, const flo
             int st = cmp_time_variant(c, (int)v, &a, warmup, reps, stream, &med, &mn, &mean);
             if (st) return st;
             c->history.push_back(HistRow{a.M, a.N, a.K, (int)v, reps, med, mn, mean});
+            ++c->hist_gen;
         }
     }
     c->cache.clear();
@@ -1250,6 +1277,7 @@ CMP_API int cmp_history_get(cmp_ctx* c, int row, int64_t* mnk, int* id, int* rep
 CMP_API int cmp_history_clear(cmp_ctx* c) {
     if (!c) return CMP_EINVAL;
     c->history.clear();
+    ++c->hist_gen;
     c->cache.clear();
     return CMP_OK;
 }
@@ -1326,6 +1354,7 @@ CMP_API int cmp_history_load(cmp_ctx* c, const char* path, int force) {
     }
     if (!header) return fail(c, CMP_EINVAL, "%s is not a compar history file", path);
     c->history.insert(c->history.end(), rows.begin(), rows.end());
+    ++c->hist_gen;
     c->cache.clear();
     return CMP_OK;
 }
