@@ -59,7 +59,10 @@ def test_f32_simt_256_uniform(cx):
 # ---- exactness on small integers ---------------------------------------------
 
 INT_SHAPES = [(1, 1, 1), (7, 5, 3), (256, 256, 256), (300, 520, 200), (257, 255, 129),
-              (64, 1000, 33), (513, 130, 640)]
+              (64, 1000, 33), (513, 130, 640),
+              # extreme aspect ratios: one tile over a long K (many pipeline stages),
+              # a single row or column over several tiles, K just past a block boundary
+              (64, 64, 16384), (1, 4096, 1000), (4096, 1, 1000), (33, 65, 8200)]
 
 
 @pytest.mark.parametrize("name", VARIANTS)
