@@ -185,6 +185,20 @@ int cmp_force_variant(cmp_ctx *ctx, const char *iface, int id);
 
 int cmp_selector_set(cmp_ctx *ctx, int kind);
 int cmp_set_flags(cmp_ctx *ctx, uint32_t flags);
+/* Split-K of the built-in MFMA variants (bf16x3, fp8r, bf16).  With fewer
+ * 256 x 256 output tiles than compute units, these variants can cut K into
+ * slices run by separate workgroups, each writing an M x N float partial sum
+ * to the variant's workspace, then add the partials in slice order (so the
+ * result does not depend on scheduling).  splits = 0 (the default) lets a cost
+ * model choose per call; splits >= 1 forces that many slices, at most 64 and
+ * at most one per 64-byte K block, every slice non-empty (1 disables split-K).
+ * This is a tuning and testing knob: the sum order, hence the rounding, of a
+ * result depends on the slice count. */
+int cmp_set_split_k(cmp_ctx *ctx, int splits);
+/* Slice count a call of built-in variant `id` of "gemm" would use for an
+ * M x N x K product under the current setting (1 for f32_simt and for
+ * variants registered by the caller). */
+int cmp_split_k(cmp_ctx *ctx, int id, int64_t M, int64_t N, int64_t K, int *splits);
 /* Admissible variants for ctx->tol as a bit mask (bit i = id i). */
 int cmp_admissible(cmp_ctx *ctx, const char *iface, const cmp_context *c, uint64_t *mask);
 /* Choose a variant for one context: admissible set, then the selector's

@@ -155,6 +155,15 @@ class Compar:
     def set_flags(self, flags: int):
         self._check(self.L.cmp_set_flags(self.ctx, flags))
 
+    def set_split_k(self, splits: int):
+        """0: the cost model picks the split-K slice count per call; n >= 1 forces n."""
+        self._check(self.L.cmp_set_split_k(self.ctx, splits))
+
+    def split_k(self, vid: int, M: int, N: int, K: int) -> int:
+        n = C.c_int()
+        self._check(self.L.cmp_split_k(self.ctx, vid, M, N, K, C.byref(n)))
+        return n.value
+
     def admissible(self, M, N, K, tol, iface: str = "gemm") -> int:
         q = cmp_context(M, N, K, CMP_F32, tol)
         m = C.c_uint64()

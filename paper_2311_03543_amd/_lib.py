@@ -82,6 +82,8 @@ SIGNATURES = {
     "cmp_force_variant": (_I, [_P, _S, _I]),
     "cmp_selector_set": (_I, [_P, _I]),
     "cmp_set_flags": (_I, [_P, C.c_uint32]),
+    "cmp_set_split_k": (_I, [_P, _I]),
+    "cmp_split_k": (_I, [_P, _I, C.c_int64, C.c_int64, C.c_int64, _IP]),
     "cmp_admissible": (_I, [_P, _S, C.POINTER(cmp_context), C.POINTER(_U64)]),
     "cmp_select": (_I, [_P, _S, C.POINTER(cmp_context), _IP]),
     "cmp_select_batch": (_I, [_P, _S, _I, C.POINTER(cmp_context), _IP]),

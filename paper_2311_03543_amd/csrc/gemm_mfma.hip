@@ -151,11 +151,13 @@ __device__ __forceinline__ void tile_coords(int tiles_m, int tiles_n, int& tm, i
 constexpr int NRING = 4;
 constexpr int RSTAGE = 2 * SLAB;
 static_assert((size_t)NRING * RSTAGE <= kSmem, "ring fits the LDS allocation");
+static_assert(kKBlockBytes == kPanelRowBytes, "split-K counts K in operand-image blocks");
 
 __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void gemm_bf16_ring_kernel(int64_t M, int64_t N, int nkb, float alpha, const uint8_t* __restrict__ Ah,
                            const uint8_t* __restrict__ Bh, float beta, float* __restrict__ C,
-                           int64_t ldc, int tiles_m, int tiles_n) {
+                           int64_t ldc, int tiles_m, int tiles_n, int kb_split,
+                           float* __restrict__ P) {
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
     // LDS ring: slot i = [A slab | B slab] at i * RSTAGE
 
@@ -167,9 +169,12 @@ void gemm_bf16_ring_kernel(int64_t M, int64_t N, int nkb, float alpha, const uin
     const int64_t m0 = (int64_t)tm * TM, n0 = (int64_t)tn * TN;
     const int64_t panel = (int64_t)nkb * SLAB;        // bytes of one 256-row panel
     const int src_off = wave * 4096 + lane * 16;
-    const uint8_t* a_src = Ah + tm * panel + src_off;
-    const uint8_t* b_src = Bh + tn * panel + src_off;
-    const int steps = nkb;
+    // split-K: this workgroup's K blocks [kb0, kb0 + steps) (blockIdx.y = split)
+    const int kb0 = (int)blockIdx.y * kb_split;
+    const int steps = nkb - kb0 < kb_split ? nkb - kb0 : kb_split;
+    const int64_t koff = (int64_t)kb0 * SLAB;
+    const uint8_t* a_src = Ah + tm * panel + koff + src_off;
+    const uint8_t* b_src = Bh + tn * panel + koff + src_off;
 
     floatx16 acc[4][4];
 #pragma unroll
@@ -269,7 +274,10 @@ void gemm_bf16_ring_kernel(int64_t M, int64_t N, int nkb, float alpha, const uin
     for (int s = 0; s + 1 < steps; ++s) one_stage(std::true_type{});
     one_stage(std::false_type{});
     __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 15));   // drain the trailing copies
-    epilogue(acc, M, N, m0, n0, wm, wn, lane, alpha, beta, C, ldc);
+    if (P)   // split-K: raw partial sums of this split, reduced by splitk_reduce_kernel
+        epilogue(acc, M, N, m0, n0, wm, wn, lane, 1.f, 0.f, P + (size_t)blockIdx.y * M * N, N);
+    else
+        epilogue(acc, M, N, m0, n0, wm, wn, lane, alpha, beta, C, ldc);
 }
 
 // ---------------------------------------------------------------------------
@@ -299,7 +307,7 @@ void gemm_bf16x3_slab4_kernel(int64_t M, int64_t N, int nkb, float alpha,
                               const uint8_t* __restrict__ Ah, const uint8_t* __restrict__ Al,
                               const uint8_t* __restrict__ Bh, const uint8_t* __restrict__ Bl,
                               float beta, float* __restrict__ C, int64_t ldc, int tiles_m,
-                              int tiles_n) {
+                              int tiles_n, int kb_split, float* __restrict__ P) {
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
     // LDS ring: slot i = four slabs at i * STAGE4
 
@@ -311,11 +319,14 @@ void gemm_bf16x3_slab4_kernel(int64_t M, int64_t N, int nkb, float alpha,
     const int64_t m0 = (int64_t)tm * TM, n0 = (int64_t)tn * TN;
     const int64_t panel = (int64_t)nkb * SLAB;
     const int src_off = wave * 4096 + lane * 16;
-    const uint8_t* a_hi = Ah + tm * panel + src_off;
-    const uint8_t* b_hi = Bh + tn * panel + src_off;
-    const uint8_t* a_lo = Al + tm * panel + src_off;
-    const uint8_t* b_lo = Bl + tn * panel + src_off;
-    const int steps = nkb;
+    // split-K: this workgroup's K blocks [kb0, kb0 + steps) (blockIdx.y = split)
+    const int kb0 = (int)blockIdx.y * kb_split;
+    const int steps = nkb - kb0 < kb_split ? nkb - kb0 : kb_split;
+    const int64_t koff = (int64_t)kb0 * SLAB;
+    const uint8_t* a_hi = Ah + tm * panel + koff + src_off;
+    const uint8_t* b_hi = Bh + tn * panel + koff + src_off;
+    const uint8_t* a_lo = Al + tm * panel + koff + src_off;
+    const uint8_t* b_lo = Bl + tn * panel + koff + src_off;
 
     floatx16 acc[4][4];
 #pragma unroll
@@ -421,7 +432,10 @@ void gemm_bf16x3_slab4_kernel(int64_t M, int64_t N, int nkb, float alpha,
     for (int s = 0; s + 1 < steps; ++s) one_stage(std::true_type{});
     one_stage(std::false_type{});
     __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 15));   // drain the trailing copies
-    epilogue(acc, M, N, m0, n0, wm, wn, lane, alpha, beta, C, ldc);
+    if (P)   // split-K: raw partial sums of this split, reduced by splitk_reduce_kernel
+        epilogue(acc, M, N, m0, n0, wm, wn, lane, 1.f, 0.f, P + (size_t)blockIdx.y * M * N, N);
+    else
+        epilogue(acc, M, N, m0, n0, wm, wn, lane, alpha, beta, C, ldc);
 }
 
 // ---------------------------------------------------------------------------
@@ -444,7 +458,7 @@ void gemm_fp8r_fused_kernel(int64_t M, int64_t N, int nkb, float alpha,
                             const uint8_t* __restrict__ Bq, const uint8_t* __restrict__ Br,
                             const uint8_t* __restrict__ Bsq, const uint8_t* __restrict__ Bsr,
                             float beta, float* __restrict__ C, int64_t ldc, int tiles_m,
-                            int tiles_n) {
+                            int tiles_n, int kb_split, float* __restrict__ P) {
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
     // LDS ring: slot i = [Aq slab | Bq slab | Ar slab | Br slab] at i * STAGE4
 
@@ -456,11 +470,15 @@ void gemm_fp8r_fused_kernel(int64_t M, int64_t N, int nkb, float alpha,
     const int64_t m0 = (int64_t)tm * TM, n0 = (int64_t)tn * TN;
     const int64_t panel = (int64_t)nkb * SLAB;
     const int src_off = wave * 4096 + lane * 16;
-    const uint8_t* a_q = Aq + tm * panel + src_off;
-    const uint8_t* b_q = Bq + tn * panel + src_off;
-    const uint8_t* a_r = Ar + tm * panel + src_off;
-    const uint8_t* b_r = Br + tn * panel + src_off;
-    const int steps = nkb;                      // one 64-k MFMA step per stage
+    // split-K: this workgroup's K blocks [kb0, kb0 + steps) (blockIdx.y = split),
+    // one 64-k MFMA step per stage
+    const int kb0 = (int)blockIdx.y * kb_split;
+    const int steps = nkb - kb0 < kb_split ? nkb - kb0 : kb_split;
+    const int64_t koff = (int64_t)kb0 * SLAB;
+    const uint8_t* a_q = Aq + tm * panel + koff + src_off;
+    const uint8_t* b_q = Bq + tn * panel + koff + src_off;
+    const uint8_t* a_r = Ar + tm * panel + koff + src_off;
+    const uint8_t* b_r = Br + tn * panel + koff + src_off;
     const int nkt = nkb / 2;                    // 128-k scale tiles per row
     // this wave's 128 rows of A (and columns of C) lie in one 128-row scale tile
     const int64_t a_tile = m0 / 128 + wm, b_tile = n0 / 128 + wn;
@@ -500,7 +518,7 @@ void gemm_fp8r_fused_kernel(int64_t M, int64_t N, int nkb, float alpha,
     uint32_t w_aq = 0, w_ar = 0, w_bq = 0, w_br = 0;
     int sh_a = 0, sh_b = 0;
     auto load_scale_words = [&]() {
-        const int64_t ia = a_tile * nkt + (sc_kb >> 1), ib = b_tile * nkt + (sc_kb >> 1);
+        const int64_t ia = a_tile * nkt + ((kb0 + sc_kb) >> 1), ib = b_tile * nkt + ((kb0 + sc_kb) >> 1);
         const int64_t oa = ia & ~(int64_t)3, ob = ib & ~(int64_t)3;
         w_aq = *reinterpret_cast<const uint32_t*>(Asq + oa);
         w_ar = *reinterpret_cast<const uint32_t*>(Asr + oa);
@@ -617,7 +635,10 @@ void gemm_fp8r_fused_kernel(int64_t M, int64_t N, int nkb, float alpha,
     for (int s = 0; s + 1 < steps; ++s) one_stage(std::true_type{});
     one_stage(std::false_type{});
     __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 15));   // drain the trailing copies
-    epilogue(acc, M, N, m0, n0, wm, wn, lane, alpha, beta, C, ldc);
+    if (P)   // split-K: raw partial sums of this split, reduced by splitk_reduce_kernel
+        epilogue(acc, M, N, m0, n0, wm, wn, lane, 1.f, 0.f, P + (size_t)blockIdx.y * M * N, N);
+    else
+        epilogue(acc, M, N, m0, n0, wm, wn, lane, alpha, beta, C, ldc);
 }
 
 // The kernels use more than the default 64 KiB of dynamic LDS; the limit is a
@@ -634,45 +655,90 @@ hipError_t allow_lds(Kernel kernel, std::atomic<uint64_t>& done) {
     return e;
 }
 
+// Split-K: `splits` > 1 runs the K range in that many slices (grid y), each
+// writing raw partial sums to partial[split] (M x N, tight), which
+// splitk_reduce_kernel then sums in fixed order into C = alpha * sum + beta * C.
+// Returns the K blocks per slice (the kernels' kb_split) for nkb blocks.
+int kb_per_split(int nkb, int splits) { return (nkb + splits - 1) / splits; }
+
+// Partials summed in slice order 0, 1, ..., splits - 1 for every element, so
+// the result does not depend on which slice finished first.
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(int64_t M, int64_t N, int splits,
+                                                            const float* __restrict__ P, float alpha,
+                                                            float beta, float* __restrict__ C,
+                                                            int64_t ldc) {
+    const int64_t plane = M * N;
+    for (int64_t i = blockIdx.y; i < M; i += gridDim.y) {
+        const float* p = P + i * N;
+        float* c = C + i * ldc;
+        for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < N; j += (int64_t)gridDim.x * 256) {
+            float sum = 0.f;
+            for (int k = 0; k < splits; ++k) sum += p[(size_t)k * plane + j];
+            float v = alpha * sum;
+            if (beta != 0.f) v = __builtin_fmaf(beta, c[j], v);
+            c[j] = v;
+        }
+    }
+}
+
 }  // namespace
+
+hipError_t launch_splitk_reduce(int64_t M, int64_t N, int splits, const float* partial, float alpha,
+                                float beta, float* C, int64_t ldc, hipStream_t stream) {
+    if (splits < 2 || !partial || M <= 0 || N <= 0) return hipErrorInvalidValue;
+    const int64_t bx = (N + 255) / 256 < 64 ? (N + 255) / 256 : 64;
+    const int64_t by = M < 4096 ? M : 4096;
+    hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)bx, (unsigned)by), dim3(256), 0, stream, M,
+                       N, splits, partial, alpha, beta, C, ldc);
+    return hipGetLastError();
+}
 
 hipError_t launch_gemm_bf16_tn(int64_t M, int64_t N, int64_t Kp, int nterms, float alpha,
                                const uint16_t* Ah, const uint16_t* Al, const uint16_t* Bh,
-                               const uint16_t* Bl, float beta, float* C, int64_t ldc,
-                               hipStream_t stream) {
+                               const uint16_t* Bl, float beta, float* C, int64_t ldc, int splits,
+                               float* partial, hipStream_t stream) {
     if (Kp % kBf16TileK || Kp <= 0 || (nterms != 1 && nterms != 3) || (nterms == 3 && (!Al || !Bl)))
         return hipErrorInvalidValue;
     const int tiles_m = (int)((M + TM - 1) / TM), tiles_n = (int)((N + TN - 1) / TN);
     const int nkb = (int)(Kp * 2 / kPanelRowBytes);
+    if (splits < 1 || (splits > 1 && !partial)) return hipErrorInvalidValue;
+    const int kbs = kb_per_split(nkb, splits);
+    if ((int64_t)(splits - 1) * kbs >= nkb) return hipErrorInvalidValue;   // every slice non-empty
+    float* P = splits > 1 ? partial : nullptr;
+    const dim3 grid(tiles_m * tiles_n, splits);
     if (nterms == 3) {
         static std::atomic<uint64_t> lds_x3{0};
         if (hipError_t e = allow_lds(gemm_bf16x3_slab4_kernel, lds_x3)) return e;
-        hipLaunchKernelGGL(gemm_bf16x3_slab4_kernel, dim3(tiles_m * tiles_n), dim3(THREADS), kSmem,
-                           stream, M, N, nkb, alpha, (const uint8_t*)Ah, (const uint8_t*)Al,
-                           (const uint8_t*)Bh, (const uint8_t*)Bl, beta, C, ldc, tiles_m, tiles_n);
-        return hipGetLastError();
+        hipLaunchKernelGGL(gemm_bf16x3_slab4_kernel, grid, dim3(THREADS), kSmem, stream, M, N, nkb,
+                           alpha, (const uint8_t*)Ah, (const uint8_t*)Al, (const uint8_t*)Bh,
+                           (const uint8_t*)Bl, beta, C, ldc, tiles_m, tiles_n, kbs, P);
+    } else {
+        static std::atomic<uint64_t> lds_x1{0};
+        if (hipError_t e = allow_lds(gemm_bf16_ring_kernel, lds_x1)) return e;
+        hipLaunchKernelGGL(gemm_bf16_ring_kernel, grid, dim3(THREADS), kSmem, stream, M, N, nkb,
+                           alpha, (const uint8_t*)Ah, (const uint8_t*)Bh, beta, C, ldc, tiles_m,
+                           tiles_n, kbs, P);
     }
-    static std::atomic<uint64_t> lds_x1{0};
-    if (hipError_t e = allow_lds(gemm_bf16_ring_kernel, lds_x1)) return e;
-    hipLaunchKernelGGL(gemm_bf16_ring_kernel, dim3(tiles_m * tiles_n), dim3(THREADS), kSmem, stream,
-                       M, N, nkb, alpha, (const uint8_t*)Ah, (const uint8_t*)Bh, beta, C, ldc, tiles_m,
-                       tiles_n);
     return hipGetLastError();
 }
 
 hipError_t launch_gemm_fp8r_tn(int64_t M, int64_t N, int64_t Kp, float alpha, const uint8_t* Aq,
                                const uint8_t* Ar, const uint8_t* Asq, const uint8_t* Asr,
                                const uint8_t* Bq, const uint8_t* Br, const uint8_t* Bsq,
-                               const uint8_t* Bsr, float beta, float* C, int64_t ldc,
-                               hipStream_t stream) {
+                               const uint8_t* Bsr, float beta, float* C, int64_t ldc, int splits,
+                               float* partial, hipStream_t stream) {
     if (Kp % kFp8TileK || Kp <= 0) return hipErrorInvalidValue;
     static std::atomic<uint64_t> lds_f8{0};
     if (hipError_t e = allow_lds(gemm_fp8r_fused_kernel, lds_f8)) return e;
     const int tiles_m = (int)((M + TM - 1) / TM), tiles_n = (int)((N + TN - 1) / TN);
     const int nkb = (int)(Kp / kPanelRowBytes);
-    hipLaunchKernelGGL(gemm_fp8r_fused_kernel, dim3(tiles_m * tiles_n), dim3(THREADS), kSmem, stream,
-                       M, N, nkb, alpha, Aq, Ar, Asq, Asr, Bq, Br, Bsq, Bsr, beta, C, ldc, tiles_m,
-                       tiles_n);
+    if (splits < 1 || (splits > 1 && !partial)) return hipErrorInvalidValue;
+    const int kbs = kb_per_split(nkb, splits);
+    if ((int64_t)(splits - 1) * kbs >= nkb) return hipErrorInvalidValue;   // every slice non-empty
+    float* P = splits > 1 ? partial : nullptr;
+    hipLaunchKernelGGL(gemm_fp8r_fused_kernel, dim3(tiles_m * tiles_n, splits), dim3(THREADS), kSmem,
+                       stream, M, N, nkb, alpha, Aq, Ar, Asq, Asr, Bq, Br, Bsq, Bsr, beta, C, ldc,
+                       tiles_m, tiles_n, kbs, P);
     return hipGetLastError();
 }
 

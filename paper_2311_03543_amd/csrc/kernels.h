@@ -73,24 +73,70 @@ hipError_t launch_quant_fp8(int64_t rows, int64_t cols, const float* X, int64_t 
 // ---- MFMA GEMMs over pre-pass images -------------------------------------
 // bf16: C = alpha * sum_t A_t * B_t^T + beta * C over `nterms` (1 or 3) operand
 // pairs (t = 0: hi*hi, 1: hi*lo, 2: lo*hi); Ah/Al are Mp x Kp, Bh/Bl Np x Kp.
+// splits > 1 cuts K into that many slices (split-K, every slice non-empty:
+// splits <= Kp / 32 and splits_for() below gives such a count): slice s then
+// writes its raw sum (alpha and beta not applied, C untouched) to
+// partial + s * M * N (M x N, row-major), and launch_splitk_reduce finishes C.
 hipError_t launch_gemm_bf16_tn(int64_t M, int64_t N, int64_t Kp, int nterms, float alpha,
                                const uint16_t* Ah, const uint16_t* Al,
                                const uint16_t* Bh, const uint16_t* Bl,
-                               float beta, float* C, int64_t ldc, hipStream_t stream);
+                               float beta, float* C, int64_t ldc, int splits, float* partial,
+                               hipStream_t stream);
 // fp8 with refinement: C = alpha * (Aq.Bq + Ar.Bq + Aq.Br + Ar.Br) + beta * C,
-// each operand dequantised by its 128 x 128 tile's E8M0 scale byte.
+// each operand dequantised by its 128 x 128 tile's E8M0 scale byte; splits and
+// partial as above (K slices of 64-byte blocks, splits <= Kp / 64).
 hipError_t launch_gemm_fp8r_tn(int64_t M, int64_t N, int64_t Kp, float alpha,
                                const uint8_t* Aq, const uint8_t* Ar,
                                const uint8_t* Asq, const uint8_t* Asr,
                                const uint8_t* Bq, const uint8_t* Br,
                                const uint8_t* Bsq, const uint8_t* Bsr,
-                               float beta, float* C, int64_t ldc, hipStream_t stream);
+                               float beta, float* C, int64_t ldc, int splits, float* partial,
+                               hipStream_t stream);
+
+// C = alpha * (partial[0] + ... + partial[splits - 1]) + beta * C, summed in
+// that order (beta == 0 never reads C); splits >= 2.
+hipError_t launch_splitk_reduce(int64_t M, int64_t N, int splits, const float* partial, float alpha,
+                                float beta, float* C, int64_t ldc, hipStream_t stream);
+
+// Split-K count for an M x N product over nkb K blocks of kKBlockBytes.
+// A workgroup owns one 256 x 256 tile and spends `step_ns` per K block; with
+// fewer tiles than CUs, cutting K into s slices shortens the longest
+// workgroup from nkb to ceil(nkb / s) blocks (while tiles * s still fits the
+// CUs) but costs 2 (s - 1) M N floats of partial-sum traffic plus one
+// reduction launch.  The count minimises that estimate, keeps at least 4 K
+// blocks per slice (the copy ring is 4 stages deep) and every slice
+// non-empty.  1 = no split.
+inline int splits_for(int64_t M, int64_t N, int nkb, double step_ns, int cus = 256) {
+    const int64_t tiles = ((M + 255) / 256) * ((N + 255) / 256);
+    if (tiles >= cus || nkb < 8) return 1;
+    const double bytes_per_ns = 4000.0;         // partial sums, mostly L2 / MALL resident
+    const double launch_ns = 3000.0;
+    auto cost = [&](int64_t s) {
+        const int64_t kbs = (nkb + s - 1) / s;
+        const int64_t waves = (tiles * s + cus - 1) / cus;
+        double t = (double)(waves * kbs) * step_ns;
+        if (s > 1) t += 2.0 * (double)(s - 1) * (double)M * (double)N * 4.0 / bytes_per_ns + launch_ns;
+        return t;
+    };
+    int64_t best = 1;
+    double best_t = cost(1);
+    for (int64_t s = 2; s * tiles <= cus && s <= nkb / 4; ++s) {
+        const double t = cost(s);
+        if (t < best_t) best = s, best_t = t;
+    }
+    const int kbs = (int)((nkb + best - 1) / best);
+    return (nkb + kbs - 1) / kbs;
+}
+// Measured K-block step of one workgroup on MI355X at 8192^3 (ns): one
+// bf16 product, three bf16 products, four fp8 products.
+constexpr double kStepNsBf16 = 790.0, kStepNsBf16x3 = 2100.0, kStepNsFp8r = 2500.0;
 
 // Tile sizes the MFMA kernels assume for padding.
 constexpr int kMfmaTileM = 256;
 constexpr int kMfmaTileN = 256;
 constexpr int kBf16TileK = 64;
 constexpr int kFp8TileK = 128;
+constexpr int kKBlockBytes = 64;   // bytes of K per operand-image block (split-K unit)
 
 // ---- FP64 Freivalds probe -------------------------------------------------
 // out[0] = ||C x - (alpha A (B x) + beta C0 x)||^2, out[1] = ||alpha A(Bx) + beta C0 x||^2.

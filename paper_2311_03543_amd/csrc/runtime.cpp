@@ -121,6 +121,7 @@ struct cmp_ctx {
     std::string last_error;
     int selector = CMP_SEL_NN;
     uint32_t flags = 0;
+    int split_k = 0;                  // 0: cost model; n >= 1: forced slice count
     std::vector<HistRow> history;
     uint64_t hist_gen = 0;            // bumped on every change of `history`
     // shape table of the history, rebuilt when hist_gen or the variant count moves
@@ -248,11 +249,38 @@ Bf16Layout bf16_layout(const cmp_gemm_args* a) {
     L.b_elems = (size_t)L.Np * L.Kp;
     return L;
 }
-size_t ws_bf16(const void* args, void*) {
-    auto L = bf16_layout((const cmp_gemm_args*)args);
-    return (L.a_elems + L.b_elems) * 2;
+// Split-K count for the MFMA variants: the context's CU count decides when
+// the output tiles alone leave CUs idle.
+int cu_count(const void* user) {
+    auto c = (const cmp_ctx*)user;
+    return c && c->gpu && c->props.multiProcessorCount > 0 ? c->props.multiProcessorCount : 256;
 }
-size_t ws_bf16x3(const void* args, void*) { return 2 * ws_bf16(args, nullptr); }
+constexpr int kMaxForcedSplits = 64;
+int gemm_splits(const cmp_gemm_args* a, int64_t Kp_bytes, double step_ns, const void* user) {
+    auto c = (const cmp_ctx*)user;
+    const int nkb = (int)(Kp_bytes / cmp::kKBlockBytes);
+    if (c && c->split_k > 0) {
+        const int s = std::min(c->split_k, nkb);
+        const int kbs = (nkb + s - 1) / s;
+        return (nkb + kbs - 1) / kbs;      // every slice non-empty
+    }
+    return cmp::splits_for(a->M, a->N, nkb, step_ns, cu_count(user));
+}
+// partial sums of a split-K launch: splits x M x N floats, after the operand images
+size_t partial_bytes(const cmp_gemm_args* a, int splits) {
+    return splits > 1 ? (size_t)splits * a->M * a->N * sizeof(float) : 0;
+}
+size_t ws_bf16_terms(const cmp_gemm_args* a, int nterms, const void* user) {
+    auto L = bf16_layout(a);
+    const size_t img = (L.a_elems + L.b_elems) * 2 * (nterms > 1 ? 2 : 1);
+    return img + partial_bytes(a, gemm_splits(a, L.Kp * 2, nterms > 1 ? cmp::kStepNsBf16x3 : cmp::kStepNsBf16, user));
+}
+size_t ws_bf16(const void* args, void* user) {
+    return ws_bf16_terms((const cmp_gemm_args*)args, 1, user);
+}
+size_t ws_bf16x3(const void* args, void* user) {
+    return ws_bf16_terms((const cmp_gemm_args*)args, 3, user);
+}
 
 struct Fp8Layout {
     int64_t Mp, Np, Kp;
@@ -269,9 +297,11 @@ Fp8Layout fp8_layout(const cmp_gemm_args* a) {
     L.bs_bytes = round_up((L.Np / 128) * (L.Kp / 128), 256);
     return L;
 }
-size_t ws_fp8r(const void* args, void*) {
-    auto L = fp8_layout((const cmp_gemm_args*)args);
-    return 2 * (L.a_bytes + L.b_bytes + L.as_bytes + L.bs_bytes);
+size_t ws_fp8r(const void* args, void* user) {
+    auto a = (const cmp_gemm_args*)args;
+    auto L = fp8_layout(a);
+    return 2 * (L.a_bytes + L.b_bytes + L.as_bytes + L.bs_bytes) +
+           partial_bytes(a, gemm_splits(a, L.Kp, cmp::kStepNsFp8r, user));
 }
 
 // Degenerate shapes shared by every built-in: nothing to do, or C = beta * C.
@@ -320,6 +350,17 @@ hipError_t join_aux(cmp_ctx* c, hipStream_t s) {
     return e;
 }
 
+// Sum of the split-K partials into C (nothing to do without a split).
+int finish_split(cmp_ctx* c, const cmp_gemm_args* a, int splits, const float* partial,
+                 hipStream_t s) {
+    if (splits < 2) return CMP_OK;
+    KTimer kt(c, s, "splitk_reduce");
+    return cmp::launch_splitk_reduce(a->M, a->N, splits, partial, a->alpha, a->beta, a->C, a->ldc, s) ==
+                   hipSuccess
+               ? CMP_OK
+               : CMP_EHIP;
+}
+
 int run_bf16(cmp_ctx* c, const cmp_gemm_args* a, void* ws, hipStream_t s, int nterms) {
     int st;
     if (gemm_trivial(a, s, &st)) return st;
@@ -329,6 +370,9 @@ int run_bf16(cmp_ctx* c, const cmp_gemm_args* a, void* ws, hipStream_t s, int nt
     uint16_t* Bh = Ah + L.a_elems;
     uint16_t* Al = nterms > 1 ? Bh + L.b_elems : nullptr;
     uint16_t* Bl = nterms > 1 ? Al + L.a_elems : nullptr;
+    const int splits =
+        gemm_splits(a, L.Kp * 2, nterms > 1 ? cmp::kStepNsBf16x3 : cmp::kStepNsBf16, c);
+    float* partial = (float*)(base + (L.a_elems + L.b_elems) * (nterms > 1 ? 2 : 1));
     {
         KTimer kt(c, s, nterms > 1 ? "split_a_bf16_hilo" : "split_a_bf16");
         if (cmp::launch_split_a_bf16(a->M, a->K, a->A, a->lda, L.Mp, L.Kp, Ah, Al, s) != hipSuccess)
@@ -342,10 +386,10 @@ int run_bf16(cmp_ctx* c, const cmp_gemm_args* a, void* ws, hipStream_t s, int nt
     {
         KTimer kt(c, s, nterms > 1 ? "gemm_bf16x3_tn" : "gemm_bf16_tn");
         if (cmp::launch_gemm_bf16_tn(a->M, a->N, L.Kp, nterms, a->alpha, Ah, Al, Bh, Bl, a->beta,
-                                     a->C, a->ldc, s) != hipSuccess)
+                                     a->C, a->ldc, splits, partial, s) != hipSuccess)
             return CMP_EHIP;
     }
-    return CMP_OK;
+    return finish_split(c, a, splits, partial, s);
 }
 int v_bf16(const void* args, void* ws, size_t, void* stream, void* user) {
     return run_bf16((cmp_ctx*)user, (const cmp_gemm_args*)args, ws, (hipStream_t)stream, 1);
@@ -377,6 +421,9 @@ int v_fp8r(const void* args, void* ws, size_t, void* stream, void* user) {
     uint8_t* Bsq = p;
     p += L.bs_bytes;
     uint8_t* Bsr = p;
+    p += L.bs_bytes;
+    const int splits = gemm_splits(a, L.Kp, cmp::kStepNsFp8r, c);
+    float* partial = (float*)p;
     if (fork_aux(c, s) != hipSuccess) return CMP_EHIP;
     {
         KTimer kt(c, c->aux, "quant_fp8_bt");
@@ -394,10 +441,10 @@ int v_fp8r(const void* args, void* ws, size_t, void* stream, void* user) {
     {
         KTimer kt(c, s, "gemm_fp8r_tn");
         if (cmp::launch_gemm_fp8r_tn(a->M, a->N, L.Kp, a->alpha, Aq, Ar, Asq, Asr, Bq, Br, Bsq, Bsr,
-                                     a->beta, a->C, a->ldc, s) != hipSuccess)
+                                     a->beta, a->C, a->ldc, splits, partial, s) != hipSuccess)
             return CMP_EHIP;
     }
-    return CMP_OK;
+    return finish_split(c, a, splits, partial, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -1030,6 +1077,36 @@ CMP_API int cmp_selector_set(cmp_ctx* c, int kind) {
 CMP_API int cmp_set_flags(cmp_ctx* c, uint32_t flags) {
     if (!c) return CMP_EINVAL;
     c->flags = flags;
+    return CMP_OK;
+}
+
+CMP_API int cmp_set_split_k(cmp_ctx* c, int splits) {
+    if (!c) return CMP_EINVAL;
+    if (splits < 0 || splits > kMaxForcedSplits)
+        return fail(c, CMP_EINVAL, "split count must be 0 (automatic) or 1..%d", kMaxForcedSplits);
+    c->split_k = splits;
+    return CMP_OK;
+}
+
+CMP_API int cmp_split_k(cmp_ctx* c, int id, int64_t M, int64_t N, int64_t K, int* splits) {
+    if (!c || !splits || M < 0 || N < 0 || K < 0) return CMP_EINVAL;
+    Interface* f = find_iface(c, kGemm);
+    if (!f) return fail(c, CMP_ENOTFOUND, "unknown interface");
+    if (id < 0 || id >= (int)f->variants.size()) return fail(c, CMP_EINVAL, "bad variant id %d", id);
+    cmp_gemm_args a{};
+    a.M = M;
+    a.N = N;
+    a.K = K;
+    const cmp_variant_fn fn = f->variants[id].fn;
+    if (M == 0 || N == 0 || K == 0 || f->variants[id].user != c)
+        *splits = 1;
+    else if (fn == v_bf16 || fn == v_bf16x3)
+        *splits = gemm_splits(&a, bf16_layout(&a).Kp * 2,
+                              fn == v_bf16x3 ? cmp::kStepNsBf16x3 : cmp::kStepNsBf16, c);
+    else if (fn == v_fp8r)
+        *splits = gemm_splits(&a, fp8_layout(&a).Kp, cmp::kStepNsFp8r, c);
+    else
+        *splits = 1;
     return CMP_OK;
 }
 

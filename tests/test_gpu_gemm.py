@@ -216,6 +216,104 @@ def test_nan_in_a_propagates(cx, name):
     assert np.all(np.isnan(C[3])) and np.all(np.isfinite(np.delete(C, 3, axis=0)))
 
 
+# ---- split-K: few output tiles over a long K ----------------------------------------
+
+MFMA_VARIANTS = ["bf16x3", "fp8r", "bf16"]
+
+
+def run_split(cx, name, splits, A, B, C0=None, alpha=1.0, beta=0.0):
+    """One call with the slice count forced; returns (C, whether the reduction ran)."""
+    cx.set_split_k(splits)
+    cx.kernel_stats(reset=True)
+    cx.kernel_timing(True)
+    try:
+        say(f"  split-K {splits}")
+        C = run(cx, name, A, B, C0, alpha, beta)
+    finally:
+        cx.kernel_timing(False)
+        cx.set_split_k(0)
+    return C, "splitk_reduce" in cx.kernel_stats(reset=True)
+
+
+@pytest.mark.parametrize("name", VARIANTS)
+def test_split_k_count_choice(cx, name):
+    vid = cx.variant_find(name)
+    assert cx.split_k(vid, 8192, 8192, 8192) == 1          # 1024 tiles fill the CUs
+    assert cx.split_k(vid, 512, 512, 64) == 1              # too few K blocks to cut
+    if name == "f32_simt":
+        assert cx.split_k(vid, 512, 512, 8192) == 1
+        return
+    s = cx.split_k(vid, 512, 512, 8192)                    # 4 tiles over a long K
+    assert 2 <= s <= 64
+    cx.set_split_k(7)
+    try:
+        assert cx.split_k(vid, 512, 512, 8192) == 7
+        assert cx.split_k(vid, 512, 512, 128) <= 4         # at most one slice per K block
+    finally:
+        cx.set_split_k(0)
+    with pytest.raises(Exception):
+        cx.set_split_k(65)
+
+
+# K = 2000: bf16 images hold 64 K blocks of 64 bytes, fp8 images 32; a count of 7
+# gives the fp8 kernel slices of 5 blocks (odd first blocks, so each slice starts
+# half way through a 128-wide scale tile) and a shorter last slice; 64 gives
+# one-block slices.
+@pytest.mark.parametrize("name", MFMA_VARIANTS)
+@pytest.mark.parametrize("splits", [1, 2, 3, 7, 64])
+def test_split_k_integer_exact(cx, name, splits):
+    M, N, K = 300, 520, 2000
+    A = synth.int_matrix(M, K, 101)
+    B = synth.int_matrix(K, N, 202)
+    C, reduced = run_split(cx, name, splits, A, B)
+    assert reduced == (splits > 1)
+    ref = (A.astype(np.int64) @ B.astype(np.int64)).astype(np.float64)
+    assert np.array_equal(C.astype(np.float64), ref)
+
+
+@pytest.mark.parametrize("name", MFMA_VARIANTS)
+@pytest.mark.parametrize("splits", [3, 7])
+def test_split_k_random_alpha_beta(cx, name, splits):
+    M, N, K = 384, 640, 3000
+    A, B = synth.gemm_operands(M, N, K, seed=303)
+    C0 = synth.normal_matrix(M, N, 304)
+    C, reduced = run_split(cx, name, splits, A, B, C0, alpha=-0.5, beta=2.0)
+    assert reduced
+    assert oracle.relfro(C, oracle.gemm(A, B, -0.5, 2.0, C0)) <= BOUND[name]
+    # the partial sums reorder the K sum only: the entrywise bound still holds
+    C1, _ = run_split(cx, name, splits, A, B)
+    prod, bnd = variant_reference(name, A, B)
+    viol = np.abs(C1.astype(np.float64) - prod) - bnd
+    assert np.all(viol <= 0), (name, float(viol.max()))
+
+
+@pytest.mark.parametrize("name", MFMA_VARIANTS)
+def test_split_k_beta_zero_ignores_nan_c_and_nan_propagates(cx, name):
+    M, N, K = 200, 300, 2500
+    A, B = synth.gemm_operands(M, N, K, seed=305)
+    C0 = np.full((M, N), np.nan, np.float32)
+    C, reduced = run_split(cx, name, 5, A, B, C0, beta=0.0)
+    assert reduced and np.all(np.isfinite(C))
+    assert oracle.relfro(C, oracle.gemm(A, B)) <= BOUND[name]
+    A[7, K - 1] = np.nan                                   # only the last slice sees it
+    C, _ = run_split(cx, name, 5, A, B)
+    assert np.all(np.isnan(C[7])) and np.all(np.isfinite(np.delete(C, 7, axis=0)))
+
+
+@pytest.mark.parametrize("name", MFMA_VARIANTS)
+def test_split_k_automatic_repeatable(cx, name):
+    M, N, K = 512, 512, 8192
+    vid = cx.variant_find(name)
+    assert cx.split_k(vid, M, N, K) > 1
+    A, B = synth.gemm_operands(M, N, K, seed=306)
+    c1 = run(cx, name, A, B)
+    c2 = run(cx, name, A, B)
+    assert np.array_equal(c1.view(np.uint32), c2.view(np.uint32))
+    ij = synth.sample_entries(M, N, 2048, 307)
+    err = oracle.relfro(c1[ij[:, 0], ij[:, 1]], oracle.gemm_entries(A, B, ij))
+    assert err <= BOUND[name], err
+
+
 # ---- full-size square sweep point, sampled entries --------------------------------
 
 @pytest.mark.parametrize("name", VARIANTS)
