@@ -5,7 +5,8 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 (``paper_2311_03543_amd``) and never imports it; the two meet only through the
 seeded inputs of the ``synth`` module.
 
-* GEMM, operand encodings and the Freivalds probe: ``oracle.c`` (binary64 C),
+* GEMM, operand encodings (bfloat16, E4M3 with tile scales, MX E2M3 with
+  block scales) and the Freivalds probe: ``oracle.c`` (binary64 C),
   wrapped here with numpy arrays.
 * Selector network (forward, gradient, Adam): ``oracle.mlp`` (numpy binary64).
 * Selection rules (admissibility, exhaustive best, nearest neighbour, regret):
@@ -68,6 +69,14 @@ def lib():
     L.oracle_scale_exp.restype = C.c_int
     L.oracle_quant_fp8.argtypes = [_i64, _i64, _f32p, _i64, _u8p, _u8p, _u8p, _u8p, _f32p]
     L.oracle_quant_fp8.restype = None
+    L.oracle_e2m3_rne.argtypes = [C.c_float]
+    L.oracle_e2m3_rne.restype = C.c_uint8
+    L.oracle_e2m3_to_float.argtypes = [C.c_uint8]
+    L.oracle_e2m3_to_float.restype = C.c_float
+    L.oracle_mx6_scale_exp.argtypes = [C.c_float]
+    L.oracle_mx6_scale_exp.restype = C.c_int
+    L.oracle_quant_mx6.argtypes = [_i64, _i64, _f32p, _i64, _u8p, _u8p, _u8p, _u8p]
+    L.oracle_quant_mx6.restype = None
     L.oracle_freivalds.argtypes = [_i64, _i64, _i64, C.c_float, _f32p, _i64, _f32p, _i64,
                                    C.c_float, C.c_void_p, _f32p, _i64, _f64p]
     L.oracle_freivalds.restype = C.c_double
@@ -216,6 +225,57 @@ def dequant_fp8(q, scale_bytes, rows, cols) -> np.ndarray:
     sb = np.asarray(scale_bytes, dtype=np.int64)
     srow = np.repeat(np.repeat(sb, 128, axis=0), 128, axis=1)[:rows, :cols]
     return np.ldexp(v, srow - 127)
+
+
+def e2m3_rne(x) -> np.ndarray:
+    """OCP MX FP6 E2M3 codes (uint8, low 6 bits), round-to-nearest-even, saturating to +-7.5."""
+    f = lib().oracle_e2m3_rne
+    x = _f32(x)
+    return np.fromiter((f(float(v)) for v in x.ravel()), dtype=np.uint8, count=x.size).reshape(x.shape)
+
+
+def e2m3_to_float(q) -> np.ndarray:
+    f = lib().oracle_e2m3_to_float
+    q = np.ascontiguousarray(q, dtype=np.uint8)
+    return np.fromiter((f(int(v)) for v in q.ravel()), dtype=np.float32, count=q.size).reshape(q.shape)
+
+
+def mx6_scale_exp(amax: float) -> int:
+    return int(lib().oracle_mx6_scale_exp(float(amax)))
+
+
+def quant_mx6(X):
+    """MX E2M3 quantisation with one residual level, blocks of 32 along each row.
+
+    Returns dict(q, qscale, rq, rscale): codes row-major (rows x cols) and E8M0
+    scale bytes (rows x ceil(cols / 32)); 0xff marks a block with a non-finite value.
+    """
+    X = _f32(X)
+    r, c = X.shape
+    nb = (c + 31) // 32
+    q = np.empty((r, c), dtype=np.uint8)
+    rq = np.empty((r, c), dtype=np.uint8)
+    qs = np.empty((r, nb), dtype=np.uint8)
+    rs = np.empty((r, nb), dtype=np.uint8)
+    lib().oracle_quant_mx6(r, c, X, max(c, 1), q, qs, rq, rs)
+    return dict(q=q, qscale=qs, rq=rq, rscale=rs)
+
+
+_E2M3_TABLE = None
+
+
+def dequant_mx6(q, scale_bytes) -> np.ndarray:
+    """float64 values e2m3(q) * 2^(byte - 127), one scale byte per 32 elements of a row
+    (NaN for the 0xff byte)."""
+    global _E2M3_TABLE
+    if _E2M3_TABLE is None:
+        f = lib().oracle_e2m3_to_float
+        _E2M3_TABLE = np.array([f(i) for i in range(64)], dtype=np.float64)
+    q = np.asarray(q, dtype=np.uint8)
+    v = _E2M3_TABLE[q & 63]
+    sb = np.repeat(np.asarray(scale_bytes, dtype=np.int64), 32, axis=1)[:, :q.shape[1]]
+    out = np.ldexp(v, np.where(sb == 0xff, 0, sb) - 127)
+    return np.where(sb == 0xff, np.nan, out)
 
 
 def freivalds(A, B, Cout, x, alpha=1.0, beta=0.0, C0=None) -> float:

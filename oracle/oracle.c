@@ -28,7 +28,9 @@
  * published definitions, the operand encodings the reduced-precision variants
  * use: bfloat16 round-to-nearest-even, the OCP FP8 E4M3 ("e4m3fn") encoding
  * with round-to-nearest-even and saturation to +-448, per-tile power-of-two
- * scales stored as E8M0 exponents, and the FP32 residual of a quantisation.
+ * scales stored as E8M0 exponents, the FP32 residual of a quantisation, and
+ * the OCP Microscaling FP6 E2M3 encoding with one E8M0 scale per block of 32
+ * consecutive elements.
  */
 #include <math.h>
 #include <stdint.h>
@@ -364,6 +366,117 @@ OR_EXPORT void oracle_quant_fp8(int64_t rows, int64_t cols, const float *X, int6
             for (int64_t r = r0; r < r1; ++r)
                 for (int64_t c = c0; c < c1; ++c)
                     rq[r * cols + c] = e4m3_from_double(ldexp((double)resid[r * cols + c], er));
+        }
+}
+
+/* ------------------------------------------------------------------------- */
+/* OCP Microscaling (MX) FP6 E2M3: 1 sign, 2 exponent (bias 1), 3 fraction
+ * bits, no infinity and no NaN.  Normal: (1 + f/8) * 2^(e-1), e = 1..3;
+ * subnormal (e = 0): f/8.  The largest magnitude is 7.5.  Code bits: sign 5,
+ * exponent 4..3, fraction 2..0.  Encoding: round-to-nearest-even onto that
+ * grid, saturating to +-7.5.  Non-finite values have no code; the block
+ * quantisation below marks their block with the E8M0 NaN scale instead and
+ * this function returns the zero code for them.                              */
+
+OR_EXPORT float oracle_e2m3_to_float(uint8_t q)
+{
+    const int s = (q >> 5) & 1, e = (q >> 3) & 3, f = q & 7;
+    const double v = (e == 0) ? f / 8.0 : ldexp(8.0 + f, e - 4);
+    return (float)(s ? -v : v);
+}
+
+static uint8_t e2m3_from_double(double x)
+{
+    if (isnan(x) || isinf(x)) return 0;
+    const uint8_t sign = signbit(x) ? 0x20 : 0;
+    const double a = fabs(x);
+    if (a >= 7.5) return sign | 0x1f;
+    /* grid spacing where a lives: 1/8 below 2 (subnormals and the first
+     * binade share it), else 2^(floor(log2 a) - 3) */
+    int ex;
+    if (a < 2.0) ex = -3;
+    else { int e2; frexp(a, &e2); ex = (e2 - 1) - 3; }
+    const double step = ldexp(1.0, ex);
+    const double lowm = floor(a / step);          /* exact: a / 2^ex is exact */
+    const double rem = a - lowm * step;
+    double m = lowm;
+    if (rem > 0.5 * step || (rem == 0.5 * step && fmod(lowm, 2.0) != 0.0)) m = lowm + 1.0;
+    const double v = m * step;                    /* <= 7.5: 7.5 is on the grid */
+    if (v < 1.0) return sign | (uint8_t)(v * 8.0);
+    int e2; frexp(v, &e2);                        /* v = [0.5,1) * 2^e2, e2 = 1..3 */
+    const int F = (int)(v / ldexp(1.0, e2 - 1) * 8.0) - 8;
+    return sign | (uint8_t)(e2 << 3) | (uint8_t)F;
+}
+
+OR_EXPORT uint8_t oracle_e2m3_rne(float x) { return e2m3_from_double((double)x); }
+
+/*
+ * MX block scale for E2M3: the integer e with amax * 2^e <= 7.5 < amax * 2^(e+1)
+ * (the block's largest magnitude lands in the top binade of the format without
+ * saturating), by exact comparisons; amax == 0 gives 0; clamped to
+ * [-127, 127] so that 2^-e is an E8M0 byte (127 - e).
+ */
+OR_EXPORT int oracle_mx6_scale_exp(float amax)
+{
+    if (!(amax > 0.0f) || isinf(amax)) return 0;
+    int e = 0;
+    const double a = (double)amax;
+    while (ldexp(a, e) > 7.5) --e;
+    while (ldexp(a, e + 1) <= 7.5) ++e;
+    if (e > 127) e = 127;
+    if (e < -127) e = -127;
+    return e;
+}
+
+/*
+ * MX-style E2M3 quantisation with one residual level.  Every row of X is cut
+ * into blocks of 32 consecutive elements (the last block of a row partial;
+ * missing elements count as zero).  For a block B whose elements are finite:
+ *   e  = mx6_scale_exp(max |x|, x in B);   q  = e2m3(x * 2^e)
+ *   r  = x - e2m3val(q) * 2^-e             (exact in binary32)
+ *   er = mx6_scale_exp(max |r|, r in B);   rq = e2m3(r * 2^er)
+ * with E8M0 scale bytes 127 - e and 127 - er.  A block holding a NaN or an
+ * infinity gets the E8M0 NaN byte 0xff at both levels and zero codes, so that
+ * every product it enters is NaN.
+ * Outputs: codes rows x cols (one per byte, row-major); scale bytes
+ * rows x ceil(cols / 32), row-major.
+ */
+OR_EXPORT void oracle_quant_mx6(int64_t rows, int64_t cols, const float *X, int64_t ldx,
+                                uint8_t *q, uint8_t *qscale, uint8_t *rq, uint8_t *rscale)
+{
+    const int64_t nb = (cols + 31) / 32;
+    for (int64_t r = 0; r < rows; ++r)
+        for (int64_t b = 0; b < nb; ++b) {
+            const int64_t c0 = b * 32, c1 = (c0 + 32 < cols) ? c0 + 32 : cols;
+            int finite = 1;
+            float amax = 0.0f;
+            for (int64_t c = c0; c < c1; ++c) {
+                const float x = X[r * ldx + c];
+                if (!isfinite(x)) finite = 0;
+                else if (fabsf(x) > amax) amax = fabsf(x);
+            }
+            if (!finite) {
+                qscale[r * nb + b] = 0xff;
+                rscale[r * nb + b] = 0xff;
+                for (int64_t c = c0; c < c1; ++c) q[r * cols + c] = rq[r * cols + c] = 0;
+                continue;
+            }
+            const int e = oracle_mx6_scale_exp(amax);
+            qscale[r * nb + b] = (uint8_t)(127 - e);
+            float res[32];
+            float ramax = 0.0f;
+            for (int64_t c = c0; c < c1; ++c) {
+                const float x = X[r * ldx + c];
+                const uint8_t qq = e2m3_from_double(ldexp((double)x, e));
+                q[r * cols + c] = qq;
+                const double back = ldexp((double)oracle_e2m3_to_float(qq), -e);
+                res[c - c0] = (float)((double)x - back);
+                if (fabsf(res[c - c0]) > ramax) ramax = fabsf(res[c - c0]);
+            }
+            const int er = oracle_mx6_scale_exp(ramax);
+            rscale[r * nb + b] = (uint8_t)(127 - er);
+            for (int64_t c = c0; c < c1; ++c)
+                rq[r * cols + c] = e2m3_from_double(ldexp((double)res[c - c0], er));
         }
 }
 

@@ -1,5 +1,5 @@
 """Planted mistakes: copies of the oracle with one plausible error each (a transposed operand, a
-flipped sign, a dropped term, a wrong tie rule) are compiled on the CPU and must fail the same
+flipped sign, a dropped term, a wrong tie rule, a wrong format maximum) are compiled on the CPU and must fail the same
 independent pins that the real oracle passes (exact rational arithmetic, torch's E4M3 codes)."""
 import ctypes as C
 import os
@@ -21,8 +21,15 @@ MUTATIONS = {
     "beta_sign": ("r += b * (double)C0[i * ldc + j];", "r -= b * (double)C0[i * ldc + j];"),
     "dropped_last_k": ("                for (int64_t k = 0; k < K; ++k)\n                    s += (double)A[i * lda + k]",
                        "                for (int64_t k = 0; k < K - 1; ++k)\n                    s += (double)A[i * lda + k]"),
-    "e4m3_ties_away": ("if (rem > 0.5 * step || (rem == 0.5 * step && fmod(lowm, 2.0) != 0.0)) m = lowm + 1.0;",
-                       "if (rem >= 0.5 * step) m = lowm + 1.0;"),
+    "e4m3_ties_away": ("if (rem > 0.5 * step || (rem == 0.5 * step && fmod(lowm, 2.0) != 0.0)) m = lowm + 1.0;\n"
+                       "    const double v = m * step;\n    if (v > 448.0)",
+                       "if (rem >= 0.5 * step) m = lowm + 1.0;\n    const double v = m * step;\n    if (v > 448.0)"),
+    "e2m3_ties_away": ("if (rem > 0.5 * step || (rem == 0.5 * step && fmod(lowm, 2.0) != 0.0)) m = lowm + 1.0;\n"
+                       "    const double v = m * step;                    /* <= 7.5",
+                       "if (rem >= 0.5 * step) m = lowm + 1.0;\n"
+                       "    const double v = m * step;                    /* <= 7.5"),
+    "mx6_scale_to_8": ("while (ldexp(a, e) > 7.5) --e;\n    while (ldexp(a, e + 1) <= 7.5) ++e;",
+                       "while (ldexp(a, e) > 8.0) --e;\n    while (ldexp(a, e + 1) <= 8.0) ++e;"),
 }
 
 
@@ -72,10 +79,37 @@ def e4m3_pin_holds(L):
     return np.array_equal(ours, ref)
 
 
+def e2m3_pin_holds(L):
+    """E2M3 rounding of the midpoints of its grid: torch's E4M3 on [1, 7.5], half-to-even
+    multiples of 1/8 below 1."""
+    L.oracle_e2m3_rne.argtypes = [C.c_float]
+    L.oracle_e2m3_rne.restype = C.c_uint8
+    L.oracle_e2m3_to_float.argtypes = [C.c_uint8]
+    L.oracle_e2m3_to_float.restype = C.c_float
+    val = lambda x: float(L.oracle_e2m3_to_float(L.oracle_e2m3_rne(float(x))))
+    pos = np.array([float(v) for v in torch.arange(0, 0x7F, dtype=torch.uint8).view(torch.float8_e4m3fn)
+                    .to(torch.float32)])
+    grid = np.sort(pos[(pos >= 1.0) & (pos <= 7.5)])
+    mids = ((grid[1:] + grid[:-1]) / 2).astype(np.float32)
+    ref = torch.from_numpy(mids).to(torch.float8_e4m3fn).to(torch.float32).numpy()
+    if any(val(m) != float(r) for m, r in zip(mids, ref)):
+        return False
+    sub = (np.arange(16) + 0.5) / 16
+    return all(val(x) == float(np.round(x * 8) / 8) for x in sub)
+
+
+def mx6_scale_pin_holds(L):
+    L.oracle_mx6_scale_exp.argtypes = [C.c_float]
+    L.oracle_mx6_scale_exp.restype = C.c_int
+    return all(L.oracle_mx6_scale_exp(a) == e for a, e in [(7.5, 0), (1.0, 2), (3.75, 1), (7.6, -1)])
+
+
 def test_real_oracle_passes_the_pins(tmp_path):
     import oracle
     assert gemm_pin_holds(oracle.lib())
     assert e4m3_pin_holds(oracle.lib())
+    assert e2m3_pin_holds(oracle.lib())
+    assert mx6_scale_pin_holds(oracle.lib())
 
 
 @pytest.mark.parametrize("name", ["transposed_B", "beta_sign", "dropped_last_k"])
@@ -85,3 +119,11 @@ def test_gemm_mutants_are_caught(name, tmp_path):
 
 def test_e4m3_mutant_is_caught(tmp_path):
     assert not e4m3_pin_holds(build_mutant("e4m3_ties_away", tmp_path))
+
+
+def test_e2m3_mutant_is_caught(tmp_path):
+    assert not e2m3_pin_holds(build_mutant("e2m3_ties_away", tmp_path))
+
+
+def test_mx6_scale_mutant_is_caught(tmp_path):
+    assert not mx6_scale_pin_holds(build_mutant("mx6_scale_to_8", tmp_path))
