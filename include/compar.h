@@ -22,6 +22,13 @@
  *                    products with per-128x128-tile scales  stated bound 1e-3
  *   id 3 "bf16"      bf16 operands, one MFMA product        stated bound 1e-2
  *
+ * and one optional built-in that cmp_register_builtin adds on request:
+ *
+ *   "fp6x3"          OCP MX FP6 (E2M3) with one E8M0 scale
+ *                    per 32 K values and one residual level,
+ *                    three products hi.hi + hi.lo + lo.hi on
+ *                    the scaled MFMA at the FP6 rate        stated bound 1e-2
+ *
  * "Stated bound" is the relative Frobenius error ||C - C_exact||_F/||C_exact||_F
  * the variant is registered with; a call with tolerance tol may only run
  * variants whose bound is <= tol (the "context match" step of OpenMP's
@@ -195,6 +202,12 @@ int cmp_set_flags(cmp_ctx *ctx, uint32_t flags);
  * This is a tuning and testing knob: the sum order, hence the rounding, of a
  * result depends on the slice count. */
 int cmp_set_split_k(cmp_ctx *ctx, int splits);
+/* Register an optional built-in variant of "gemm" by name; "fp6x3" is the only
+ * one.  It takes the next free id (*id, may be NULL).  CMP_EDUP if already
+ * registered, CMP_ENOTFOUND for an unknown name.  The learned selector's
+ * network predicts the four default built-ins; for other variants it uses the
+ * history's nearest timed shape. */
+int cmp_register_builtin(cmp_ctx *ctx, const char *name, int *id);
 /* Slice count a call of built-in variant `id` of "gemm" would use for an
  * M x N x K product under the current setting (1 for f32_simt and for
  * variants registered by the caller). */
@@ -303,6 +316,21 @@ int cmp_split_bf16(cmp_ctx *ctx, int64_t rows, int64_t cols, const float *X, int
  * (127 - e) per tile, tile-row-major ceil(rows/128) x ceil(cols/128). */
 int cmp_quant_fp8(cmp_ctx *ctx, int64_t rows, int64_t cols, const float *X, int64_t ldx,
                   uint8_t *q, uint8_t *qscale, uint8_t *rq, uint8_t *rscale, void *stream);
+/* OCP MX FP6 (E2M3) quantisation with one residual level, blocks of 32
+ * consecutive K values, each with an E8M0 scale byte 127 - e where e is the
+ * largest integer with max|x| * 2^e <= 7.5; q = RNE_e2m3(x * 2^e), then the
+ * FP32 residual quantised the same way with its own block scale (OCP MX
+ * specification v1.0, E2M3 and E8M0 formats).  A block holding a NaN or an
+ * infinity gets scale byte 0xff (E8M0 NaN) at both levels and zero codes.
+ * transpose = 0: K runs along the rows of X (rows x cols); outputs q and rq
+ * are rows x cols bytes and the scales rows x ceil(cols / 32).
+ * transpose != 0: K runs down the columns of X (X is K x N = rows x cols);
+ * outputs are cols x rows bytes (X transposed) and the scales
+ * cols x ceil(rows / 32).  One code per byte (low 6 bits: sign bit 5,
+ * exponent bits 4-3, fraction bits 2-0); device memory, tight, row-major. */
+int cmp_quant_mx6(cmp_ctx *ctx, int64_t rows, int64_t cols, const float *X, int64_t ldx,
+                  int transpose, uint8_t *q, uint8_t *qscale, uint8_t *rq, uint8_t *rscale,
+                  void *stream);
 
 /* ---- grouped launches: many GEMMs of uneven shapes ---------------------- */
 

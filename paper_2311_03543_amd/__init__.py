@@ -20,6 +20,8 @@ from ._lib import (CMP_EDUP, CMP_EHIP, CMP_EINVAL, CMP_ENODATA, CMP_ENOTFOUND,  
 
 GEMM = b"gemm"
 BUILTIN_VARIANTS = ("f32_simt", "bf16x3", "fp8r", "bf16")
+# optional built-ins, registered on request (Compar.register_builtin)
+OPTIONAL_VARIANTS = ("fp6x3",)
 
 
 def library():
@@ -154,6 +156,12 @@ class Compar:
 
     def set_flags(self, flags: int):
         self._check(self.L.cmp_set_flags(self.ctx, flags))
+
+    def register_builtin(self, name: str) -> int:
+        """Register an optional built-in variant ("fp6x3"); returns its id."""
+        vid = C.c_int(-1)
+        self._check(self.L.cmp_register_builtin(self.ctx, name.encode(), C.byref(vid)))
+        return vid.value
 
     def set_split_k(self, splits: int):
         """0: the cost model picks the split-K slice count per call; n >= 1 forces n."""
@@ -328,6 +336,12 @@ class Compar:
         px, r, c, ld = _mat(X, "X")
         self._check(self.L.cmp_quant_fp8(self.ctx, r, c, px, ld, q.data_ptr(), qscale.data_ptr(),
                                          rq.data_ptr(), rscale.data_ptr(), _stream_ptr(stream)))
+
+    def quant_mx6(self, X, q, qscale, rq, rscale, transpose=False, stream=None):
+        px, r, c, ld = _mat(X, "X")
+        self._check(self.L.cmp_quant_mx6(self.ctx, r, c, px, ld, 1 if transpose else 0, q.data_ptr(),
+                                         qscale.data_ptr(), rq.data_ptr(), rscale.data_ptr(),
+                                         _stream_ptr(stream)))
 
     # ---- per-kernel timing ------------------------------------------------------
     def kernel_timing(self, enable: bool):

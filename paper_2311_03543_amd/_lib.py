@@ -83,6 +83,8 @@ SIGNATURES = {
     "cmp_selector_set": (_I, [_P, _I]),
     "cmp_set_flags": (_I, [_P, C.c_uint32]),
     "cmp_set_split_k": (_I, [_P, _I]),
+    "cmp_register_builtin": (_I, [_P, _S, _IP]),
+    "cmp_quant_mx6": (_I, [_P, _I64, _I64, _P, _I64, _I, _P, _P, _P, _P, _P]),
     "cmp_split_k": (_I, [_P, _I, C.c_int64, C.c_int64, C.c_int64, _IP]),
     "cmp_admissible": (_I, [_P, _S, C.POINTER(cmp_context), C.POINTER(_U64)]),
     "cmp_select": (_I, [_P, _S, C.POINTER(cmp_context), _IP]),

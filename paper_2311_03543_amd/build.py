@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcompar.so")
-SOURCES = ["runtime.cpp", "gemm_f32_simt.hip", "gemm_mfma.hip", "prepass.hip", "freivalds.hip",
+SOURCES = ["runtime.cpp", "gemm_f32_simt.hip", "gemm_mfma.hip", "prepass.hip", "mx6.hip", "freivalds.hip",
            "mlp.hip"]
 ARCH = "gfx950"
 

@@ -8,6 +8,9 @@
 //   fp8 refined:    C = alpha * (Aq.Bq + Ar.Bq + Aq.Br + Ar.Br) + beta * C over
 //                   E4M3 images with one E8M0 scale byte per 128 x 128 tile,
 //                   v_mfma_scale_f32_32x32x64_f8f6f4, FP32 accumulation.
+//   MX fp6 x3:      C = alpha * (Ah.Bh + Ah.Bl + Al.Bh) + beta * C over E2M3
+//                   images with one E8M0 scale per 32 K values of a row (the
+//                   OCP MX block), the same MFMA at the FP6 rate.
 //
 // Tiling: 256 x 256 C tile per workgroup of 4 wave64 (2 x 2 waves, 128 x 128
 // per wave = 4 x 4 MFMA blocks of 32 x 32, 256 FP32 accumulators per lane).
@@ -641,6 +644,162 @@ void gemm_fp8r_fused_kernel(int64_t M, int64_t N, int nkb, float alpha,
         epilogue(acc, M, N, m0, n0, wm, wn, lane, alpha, beta, C, ldc);
 }
 
+// ---------------------------------------------------------------------------
+// MX FP6 with one residual level, three products fused per K block.  A stage
+// holds the four slabs [Ah | Bh | Al | Bl] of one 64-value K block (E2M3
+// codes packed 6 bits each with each 32-value half's E8M0 scale byte in the
+// same 32-byte lane chunk); two stages in the ring.  Products, 16 MFMAs each:
+//   h.h  (Ah, Bh)  B block major; under it: read Bl, then Al of this stage
+//   --- stage barrier: stage s + 1 landed, every read of slot s done ---
+//   h.l  (Ah, Bl)  under it: the 16 copies of stage s + 2 into slot s
+//   l.h  (Al, Bh)  B block major; under it: read Ah of stage s + 1, and each
+//                  Bh block of stage s + 1 as soon as its last MFMA has issued
+// The scaled MFMA takes each lane's own scale (its row, its K half), which is
+// dword 6 of the fragment the lane read, so no scale loads are needed.
+__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void gemm_fp6x3_fused_kernel(int64_t M, int64_t N, int nkb, float alpha,
+                             const uint8_t* __restrict__ Ah, const uint8_t* __restrict__ Al,
+                             const uint8_t* __restrict__ Bh, const uint8_t* __restrict__ Bl,
+                             float beta, float* __restrict__ C, int64_t ldc, int tiles_m,
+                             int tiles_n, int kb_split, float* __restrict__ P) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    // LDS ring: slot i = [Ah slab | Bh slab | Al slab | Bl slab] at i * STAGE4
+
+    const int t = threadIdx.x, lane = t & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);   // wave-uniform (SGPR)
+    const int wm = wave >> 1, wn = wave & 1;
+    int tm, tn;
+    tile_coords(tiles_m, tiles_n, tm, tn);
+    const int64_t m0 = (int64_t)tm * TM, n0 = (int64_t)tn * TN;
+    const int64_t panel = (int64_t)nkb * SLAB;
+    const int src_off = wave * 4096 + lane * 16;
+    // split-K: this workgroup's K blocks [kb0, kb0 + steps) (blockIdx.y = split)
+    const int kb0 = (int)blockIdx.y * kb_split;
+    const int steps = nkb - kb0 < kb_split ? nkb - kb0 : kb_split;
+    const int64_t koff = (int64_t)kb0 * SLAB;
+    const uint8_t* a_h = Ah + tm * panel + koff + src_off;
+    const uint8_t* b_h = Bh + tn * panel + koff + src_off;
+    const uint8_t* a_l = Al + tm * panel + koff + src_off;
+    const uint8_t* b_l = Bl + tn * panel + koff + src_off;
+
+    floatx16 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+    // Load cursor (K block, slot); past the last block it re-reads the last
+    // one into the freed slot, so every stage issues the same 16 copies.
+    int ld_kb = 0, ld_left = steps, ld_slot = 0;
+    int64_t kofs = 0;
+    uint8_t* dd = nullptr;
+    auto prepare = [&]() {
+        kofs = (int64_t)ld_kb * SLAB;
+        dd = smem + ld_slot * STAGE4 + wave * 4096;
+        const int go = ld_left > 1 ? 1 : 0;
+        ld_left -= go;
+        ld_kb += go;
+        ld_slot ^= 1;
+    };
+    auto copy = [&](auto part_tag) {            // copy P: slab P / 4, part P % 4
+        constexpr int P = decltype(part_tag)::value;
+        static_assert(P >= 0 && P < 16, "a fused stage is 16 copies");
+        constexpr int S = P / 4;
+        const uint8_t* src = S == 0 ? a_h : (S == 1 ? b_h : (S == 2 ? a_l : b_l));
+        dma_part<P % 4>(src + kofs, dd + S * SLAB);
+    };
+
+    // Operand registers: image X in {Ah, Bh, Al, Bl} (X = 0..3), 32-row block
+    // b, half H % 2 of the lane's 32 bytes: R[X][2 b + half].  Lane l feeds row
+    // l % 32 of a block, K half l / 32 (bytes 32 (l / 32) .. +31 of the row).
+    intx4 R[4][8];
+    const int frag_row = lane & 31;
+    const int frag_c = (lane >> 5) * 2;
+    auto read = [&](int slot, auto x_tag, auto h_tag) {
+        constexpr int X = decltype(x_tag)::value, H = decltype(h_tag)::value;
+        constexpr int blk = H / 2, half = H % 2;
+        const int r = ((X & 1) ? wn : wm) * 128 + blk * 32 + frag_row;
+        R[X][H] = *reinterpret_cast<const intx4*>(smem + slot * STAGE4 + X * SLAB + slab_off(r, frag_c + half));
+    };
+    // MFMA q (0..15) of product P (0 h.h, 1 h.l, 2 l.h); h.h and l.h run B
+    // block major (j = q / 4) so that a B block is finished after 4 MFMAs.
+    auto mfma = [&](auto p_tag, auto q_tag) {
+        constexpr int P = decltype(p_tag)::value, q = decltype(q_tag)::value;
+        constexpr int i = P == 1 ? q / 4 : q % 4, j = P == 1 ? q % 4 : q / 4;
+        constexpr int XA = P == 2 ? 2 : 0, XB = P == 1 ? 3 : 1;
+        const intx8 av = __builtin_shufflevector(R[XA][2 * i], R[XA][2 * i + 1], 0, 1, 2, 3, 4, 5, 6, 7);
+        const intx8 bv = __builtin_shufflevector(R[XB][2 * j], R[XB][2 * j + 1], 0, 1, 2, 3, 4, 5, 6, 7);
+        // operand format 2 = FP6 E2M3 for both; dwords 0-5 are the 32 codes,
+        // dword 6 the lane's E8M0 scale byte (opsel 0 selects its byte 0)
+        acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, acc[i][j], 2, 2, 0, av[6], 0,
+                                                                    bv[6]);
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using I3 = std::integral_constant<int, 3>;
+
+    // prologue: stages 0 and 1 in flight, wait for stage 0, read Ah and Bh of stage 0
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        prepare();
+        static_for<0, 16>(copy);
+    }
+    stage_barrier<16>();                         // stage 1 (16 copies) may stay in flight
+    static_for<0, 8>([&](auto h) { read(0, I0{}, h); });
+    static_for<0, 8>([&](auto h) { read(0, I1{}, h); });
+    int cur = 0;
+    pin();
+
+    auto one_stage = [&](auto more_tag) {
+        constexpr bool MORE = decltype(more_tag)::value;
+        const int nxt = cur ^ 1;
+        // h.h; read Bl then Al of this stage under it
+        static_for<0, 16>([&](auto q) {
+            mfma(I0{}, q);
+            constexpr int k = decltype(q)::value;
+            if constexpr (k < 8) read(cur, I3{}, std::integral_constant<int, k>{});
+            else read(cur, I2{}, std::integral_constant<int, k - 8>{});
+            pin();
+        });
+        if constexpr (MORE) {
+            stage_barrier<0>();                 // stage s + 1 landed, slot `cur` free
+            prepare();
+        }
+        pin();
+        // h.l; the copies of stage s + 2 under it
+        static_for<0, 16>([&](auto q) {
+            mfma(I1{}, q);
+            if constexpr (MORE) copy(q);
+            pin();
+        });
+        pin();
+        // l.h; Ah of stage s + 1 under the first 8 MFMAs, Bh block j of stage
+        // s + 1 once MFMA 4 j + 3 (the last one reading block j) has issued
+        static_for<0, 16>([&](auto q) {
+            mfma(I2{}, q);
+            constexpr int k = decltype(q)::value;
+            if constexpr (MORE && k < 8) read(nxt, I0{}, std::integral_constant<int, k>{});
+            if constexpr (MORE && k % 4 == 3) {
+                read(nxt, I1{}, std::integral_constant<int, 2 * (k / 4)>{});
+                read(nxt, I1{}, std::integral_constant<int, 2 * (k / 4) + 1>{});
+            }
+            pin();
+        });
+        pin();
+        cur = nxt;
+    };
+    for (int s = 0; s + 1 < steps; ++s) one_stage(std::true_type{});
+    one_stage(std::false_type{});
+    __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 15));   // drain the trailing copies
+    if (P)   // split-K: raw partial sums of this split, reduced by splitk_reduce_kernel
+        epilogue(acc, M, N, m0, n0, wm, wn, lane, 1.f, 0.f, P + (size_t)blockIdx.y * M * N, N);
+    else
+        epilogue(acc, M, N, m0, n0, wm, wn, lane, alpha, beta, C, ldc);
+}
+
 // The kernels use more than the default 64 KiB of dynamic LDS; the limit is a
 // per-device function attribute, set once on each device the library runs on.
 template <class Kernel>
@@ -739,6 +898,24 @@ hipError_t launch_gemm_fp8r_tn(int64_t M, int64_t N, int64_t Kp, float alpha, co
     hipLaunchKernelGGL(gemm_fp8r_fused_kernel, dim3(tiles_m * tiles_n, splits), dim3(THREADS), kSmem,
                        stream, M, N, nkb, alpha, Aq, Ar, Asq, Asr, Bq, Br, Bsq, Bsr, beta, C, ldc,
                        tiles_m, tiles_n, kbs, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_fp6x3_tn(int64_t M, int64_t N, int64_t Kp, float alpha, const uint8_t* Ah,
+                                const uint8_t* Al, const uint8_t* Bh, const uint8_t* Bl, float beta,
+                                float* C, int64_t ldc, int splits, float* partial,
+                                hipStream_t stream) {
+    if (Kp % 64 || Kp <= 0) return hipErrorInvalidValue;
+    static std::atomic<uint64_t> lds_f6{0};
+    if (hipError_t e = allow_lds(gemm_fp6x3_fused_kernel, lds_f6)) return e;
+    const int tiles_m = (int)((M + TM - 1) / TM), tiles_n = (int)((N + TN - 1) / TN);
+    const int nkb = (int)(Kp / 64);               // one 64-byte image block per 64 K values
+    if (splits < 1 || (splits > 1 && !partial)) return hipErrorInvalidValue;
+    const int kbs = kb_per_split(nkb, splits);
+    if ((int64_t)(splits - 1) * kbs >= nkb) return hipErrorInvalidValue;   // every slice non-empty
+    float* P = splits > 1 ? partial : nullptr;
+    hipLaunchKernelGGL(gemm_fp6x3_fused_kernel, dim3(tiles_m * tiles_n, splits), dim3(THREADS), kSmem,
+                       stream, M, N, nkb, alpha, Ah, Al, Bh, Bl, beta, C, ldc, tiles_m, tiles_n, kbs, P);
     return hipGetLastError();
 }
 

@@ -70,6 +70,21 @@ hipError_t launch_quant_fp8(int64_t rows, int64_t cols, const float* X, int64_t 
                             uint8_t* q, uint8_t* qscale, uint8_t* rq, uint8_t* rscale,
                             hipStream_t stream);
 
+// MX E2M3 quantisation with one residual level, one E8M0 scale per 32 K values.
+//   transpose = false: X is rows x cols, blocks along its rows (K = cols), one
+//                      output row per row of X.
+//   transpose = true:  X is rows x cols = K x N, blocks along its columns
+//                      (K = rows), one output row per column of X.
+//   tiled = true:  q / rq are panel images of out_rows rows (>= the output
+//                  rows, a multiple of 256) and Kp K values (>= K, a multiple
+//                  of 64) in the packed layout the fp6 GEMM reads; the scales
+//                  live inside the images (qscale, rscale unused).
+//   tiled = false: one code per byte, row-major (output rows x K), scale
+//                  bytes output rows x ceil(K / 32); out_rows, Kp unused.
+hipError_t launch_quant_mx6(int64_t rows, int64_t cols, const float* X, int64_t ldx,
+                            bool transpose, bool tiled, int64_t out_rows, int64_t Kp, uint8_t* q,
+                            uint8_t* qscale, uint8_t* rq, uint8_t* rscale, hipStream_t stream);
+
 // ---- MFMA GEMMs over pre-pass images -------------------------------------
 // bf16: C = alpha * sum_t A_t * B_t^T + beta * C over `nterms` (1 or 3) operand
 // pairs (t = 0: hi*hi, 1: hi*lo, 2: lo*hi); Ah/Al are Mp x Kp, Bh/Bl Np x Kp.
@@ -92,6 +107,14 @@ hipError_t launch_gemm_fp8r_tn(int64_t M, int64_t N, int64_t Kp, float alpha,
                                const uint8_t* Bsq, const uint8_t* Bsr,
                                float beta, float* C, int64_t ldc, int splits, float* partial,
                                hipStream_t stream);
+
+// MX FP6 with one residual level: C = alpha * (Ah.Bh + Ah.Bl + Al.Bh) + beta * C
+// over the tiled E2M3 images of launch_quant_mx6 (Mp / Np rows, Kp K values,
+// Kp % 64 == 0); splits and partial as above (splits <= Kp / 64).
+hipError_t launch_gemm_fp6x3_tn(int64_t M, int64_t N, int64_t Kp, float alpha, const uint8_t* Ah,
+                                const uint8_t* Al, const uint8_t* Bh, const uint8_t* Bl, float beta,
+                                float* C, int64_t ldc, int splits, float* partial,
+                                hipStream_t stream);
 
 // C = alpha * (partial[0] + ... + partial[splits - 1]) + beta * C, summed in
 // that order (beta == 0 never reads C); splits >= 2.
@@ -130,6 +153,8 @@ inline int splits_for(int64_t M, int64_t N, int nkb, double step_ns, int cus = 2
 // Measured K-block step of one workgroup on MI355X at 8192^3 (ns): one
 // bf16 product, three bf16 products, four fp8 products.
 constexpr double kStepNsBf16 = 790.0, kStepNsBf16x3 = 2100.0, kStepNsFp8r = 2500.0;
+// three FP6 products per 64 K values: the MFMA work of 1.5 bf16 K blocks
+constexpr double kStepNsFp6x3 = 1.5 * kStepNsBf16;
 
 // Tile sizes the MFMA kernels assume for padding.
 constexpr int kMfmaTileM = 256;

@@ -1,0 +1,298 @@
+// MX FP6 pre-pass: two-level E2M3 quantisation with one E8M0 scale per block
+// of 32 consecutive K values (the OCP Microscaling block size, which is also
+// the K extent of one lane's operand in the scaled 32x32x64 MFMA).
+//
+// For a block x of 32 values (missing values count as zero):
+//   e  = the largest integer with max|x| * 2^e <= 7.5 (E2M3's largest value)
+//   q  = RNE_e2m3(x * 2^e),   r = x - q * 2^-e  (exact in FP32)
+//   er = the same for max|r|, rq = RNE_e2m3(r * 2^er)
+// with scale bytes 127 - e and 127 - er.  A block holding a NaN or an
+// infinity gets the E8M0 NaN byte 0xff at both levels and zero codes; the
+// MFMA then turns every product of that block into NaN.
+//
+// Panel images (tiled) use the layout of common.h with 64-byte rows per 64 K
+// values: bytes [32 h, 32 h + 24) of a row hold the 32 codes of K half h
+// packed 6 bits each (code j at bit 6 j, little endian), byte 32 h + 24 its
+// scale byte, and the rest of the 32 bytes is zero.  A lane of the GEMM reads
+// its 32 bytes as 8 dwords: dwords 0-5 are the MFMA operand, dword 6 its scale.
+#include "common.h"
+#include "kernels.h"
+
+namespace cmp {
+namespace {
+
+// Largest e with amax * 2^e <= 7.5 = 1.875 * 2^2, from the bits of amax: for
+// a normal amax = 1.m * 2^(E-127) that is e = 129 - E, one less when
+// 1.m > 1.875 (fraction bits above 0x700000).  Zero gives 0, a subnormal
+// amax 127 (the clamp), and e is clamped to [-127, 127].
+__device__ __forceinline__ int mx6_scale_exp(float amax) {
+    if (!(amax > 0.f)) return 0;
+    const uint32_t u = __builtin_bit_cast(uint32_t, amax);
+    const int E = (int)((u >> 23) & 255u);
+    if (E == 0) return 127;
+    const int e = 129 - E - ((u & 0x7fffffu) > 0x700000u ? 1 : 0);
+    return e > 127 ? 127 : (e < -127 ? -127 : e);
+}
+
+// Round-to-nearest-even onto the E2M3 grid for |s| <= 7.5 (which the block
+// scale guarantees).  The grid spacing is 1/8 below 2, 1/4 on [2, 4) and 1/2
+// on [4, 8), so the rounded magnitude is rint(|s| k) / k with k = 8, 4, 2
+// (every step exact); v_rndne rounds halves to even, which on each of these
+// grids is the even code.  Returns the 6-bit code; `val` gets the value.
+__device__ __forceinline__ uint32_t e2m3_code(float s, float& val) {
+    const float a = fabsf(s);
+    const float k = a < 2.f ? 8.f : (a < 4.f ? 4.f : 2.f);
+    const float ik = a < 2.f ? 0.125f : (a < 4.f ? 0.25f : 0.5f);
+    const float v = __builtin_rintf(a * k) * ik;
+    uint32_t code;
+    if (v < 1.f) {
+        code = (uint32_t)(v * 8.f);                           // subnormal: v = f / 8
+    } else {
+        const uint32_t u = __builtin_bit_cast(uint32_t, v);    // v = (1 + f/8) 2^(E-1)
+        code = (((u >> 23) - 126u) << 3) | ((u >> 20) & 7u);
+    }
+    val = __builtin_copysignf(v, s);
+    return ((__builtin_bit_cast(uint32_t, s) >> 31) << 5) | code;
+}
+
+// Residual of one value against its code value qv (scaled domain s = x 2^e):
+// s - qv is exact and scaling back rounds once; a zero code leaves x - qv.
+__device__ __forceinline__ float mx6_resid(float x, float s, float qv, int e) {
+    return qv == 0.f ? x - qv : __builtin_ldexpf(s - qv, -e);
+}
+
+// Byte offset, inside a tiled image, of byte `byte` (0..31) of K half `h` of
+// the 64-value K block `kb` of image row `row`.
+__device__ __forceinline__ int64_t mx6_off(int64_t row, int64_t kb, int h, int byte, int64_t nkb) {
+    return panel_offset(row, kb * 64 + h * 32 + byte, nkb);
+}
+
+// ---------------------------------------------------------------------------
+// Rows of X (blocks along X's rows, K = cols): eight lanes per block, four
+// consecutive values each, so one wave reads 1 KiB of a row with each load.
+// The block's amax and NaN flag are reduced over the eight lanes; each lane
+// then holds 4 codes (24 bits) and lane i < 6 assembles dword i of the packed
+// 192 bits from the 24-bit words of two neighbours.
+template <bool VEC, bool TILED>
+__global__ __launch_bounds__(256) void quant_mx6_rows_kernel(
+    int64_t rows, int64_t cols, const float* __restrict__ X, int64_t ldx, int64_t out_rows,
+    int64_t Kp, uint8_t* __restrict__ q, uint8_t* __restrict__ qscale, uint8_t* __restrict__ rq,
+    uint8_t* __restrict__ rscale) {
+    // grid: x over the 8 nb lanes of one output row (nb * 8 < 2^31), y over rows
+    const int nb = (int)(TILED ? Kp / 32 : (cols + 31) / 32);   // blocks per output row
+    const int64_t nrows = TILED ? out_rows : rows;
+    const int64_t nkb = Kp / 64;
+    const int i = (int)blockIdx.x * 256 + (int)threadIdx.x;    // lane of the row: block i / 8
+    if ((i >> 3) >= nb) return;                                 // whole 8-lane groups only
+    const int lane = threadIdx.x & 63;
+    const int li = lane & 7, gbase = lane & ~7;
+    // source lanes of the packed dword this lane assembles (li < 6)
+    const int src_lo = li < 6 ? gbase + 4 * (li / 3) + li % 3 : lane;
+    const int src_hi = li < 6 ? src_lo + 1 : lane;
+    const int sh = li < 6 ? 8 * (li % 3) : 0;
+    const int b = i >> 3;
+    const int64_t k = (int64_t)b * 32 + 4 * li;
+    for (int64_t r = blockIdx.y; r < nrows; r += gridDim.y) {
+        float v[4] = {0.f, 0.f, 0.f, 0.f};
+        if (r < rows) {
+            const float* p = X + r * ldx + k;
+            if (VEC && k + 3 < cols) {
+                const float4 a = *reinterpret_cast<const float4*>(p);
+                v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (k + j < cols) v[j] = p[j];
+            }
+        }
+        float amax = 0.f;
+        int bad = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (!__builtin_isfinite(v[j])) bad = 1;
+            else amax = fmaxf(amax, fabsf(v[j]));
+        }
+#pragma unroll
+        for (int off = 1; off < 8; off <<= 1) {
+            amax = fmaxf(amax, __shfl_xor(amax, off));
+            bad |= __shfl_xor(bad, off);
+        }
+        uint32_t w0 = 0, w1 = 0, sb0 = 0xffu, sb1 = 0xffu;
+        if (!bad) {
+            const int e0 = mx6_scale_exp(amax);
+            float res[4], ramax = 0.f;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float s = __builtin_ldexpf(v[j], e0);
+                float qv;
+                w0 |= e2m3_code(s, qv) << (6 * j);
+                res[j] = mx6_resid(v[j], s, qv, e0);
+                ramax = fmaxf(ramax, fabsf(res[j]));
+            }
+#pragma unroll
+            for (int off = 1; off < 8; off <<= 1) ramax = fmaxf(ramax, __shfl_xor(ramax, off));
+            const int e1 = mx6_scale_exp(ramax);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                float qv;
+                w1 |= e2m3_code(__builtin_ldexpf(res[j], e1), qv) << (6 * j);
+            }
+            sb0 = (uint32_t)(127 - e0);
+            sb1 = (uint32_t)(127 - e1);
+        }
+        if (TILED) {
+            // dword li of this block's 32 bytes: packed codes, scale byte, zero
+            const uint32_t lo0 = __shfl(w0, src_lo), hi0 = __shfl(w0, src_hi);
+            const uint32_t lo1 = __shfl(w1, src_lo), hi1 = __shfl(w1, src_hi);
+            uint32_t d0, d1;
+            if (li < 6) {
+                d0 = (lo0 >> sh) | (hi0 << (24 - sh));
+                d1 = (lo1 >> sh) | (hi1 << (24 - sh));
+            } else {
+                d0 = li == 6 ? sb0 : 0u;
+                d1 = li == 6 ? sb1 : 0u;
+            }
+            const int64_t o = mx6_off(r, b >> 1, b & 1, 4 * li, nkb);
+            *reinterpret_cast<uint32_t*>(q + o) = d0;
+            *reinterpret_cast<uint32_t*>(rq + o) = d1;
+        } else {
+            // one code per byte, row-major rows x cols; the scales from lane 0
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (k + j < cols) {
+                    q[r * cols + k + j] = (uint8_t)((w0 >> (6 * j)) & 63u);
+                    rq[r * cols + k + j] = (uint8_t)((w1 >> (6 * j)) & 63u);
+                }
+            if (li == 0) {
+                qscale[r * nb + b] = (uint8_t)sb0;
+                rscale[r * nb + b] = (uint8_t)sb1;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Columns of X (X is K x N; output row n = column n of X, blocks along K):
+// one lane per pair of blocks (64 K values, one 64-byte image row segment),
+// consecutive lanes on consecutive columns, so each load of a lane is one
+// coalesced row segment of X and a wave's four 16-byte stores fill a
+// contiguous 4 KiB of the image.  The lane packs its 32 codes per block itself.
+template <bool TILED>
+__global__ __launch_bounds__(256) void quant_mx6_cols_kernel(
+    int64_t K, int64_t N, const float* __restrict__ X, int64_t ldx, int64_t out_rows, int64_t Kp,
+    uint8_t* __restrict__ q, uint8_t* __restrict__ qscale, uint8_t* __restrict__ rq,
+    uint8_t* __restrict__ rscale) {
+    // grid: x over output rows (columns of X), y over pairs of blocks
+    const int64_t nb = TILED ? Kp / 32 : (K + 31) / 32;
+    const int64_t npairs = (nb + 1) / 2;
+    const int64_t nrows = TILED ? out_rows : N;
+    const int64_t nkb = Kp / 64;
+    const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (n >= nrows) return;
+    for (int64_t pr = blockIdx.y; pr < npairs; pr += gridDim.y) {
+#pragma unroll 1
+        for (int h = 0; h < 2; ++h) {
+            const int64_t b = 2 * pr + h;
+            if (b >= nb) break;
+            const int64_t k0 = b * 32;
+            float v[32];
+            float amax = 0.f;
+            bool bad = false;
+#pragma unroll
+            for (int j = 0; j < 32; ++j) {
+                v[j] = (n < N && k0 + j < K) ? X[(k0 + j) * ldx + n] : 0.f;
+                if (!__builtin_isfinite(v[j])) bad = true;
+                else amax = fmaxf(amax, fabsf(v[j]));
+            }
+            // codes packed as they are made: code j at bit 6 j of p0 / p1
+            uint32_t p0[6] = {0, 0, 0, 0, 0, 0}, p1[6] = {0, 0, 0, 0, 0, 0};
+            auto put = [](uint32_t (&p)[6], int j, uint32_t c) {
+                const int bit = 6 * j, d = bit >> 5, sh = bit & 31;
+                p[d] |= c << sh;
+                if (sh > 26) p[d + 1] |= c >> (32 - sh);
+            };
+            uint32_t sb0 = 0xffu, sb1 = 0xffu;
+            if (!bad) {
+                const int e0 = mx6_scale_exp(amax);
+                float ramax = 0.f;
+#pragma unroll
+                for (int j = 0; j < 32; ++j) {
+                    const float s = __builtin_ldexpf(v[j], e0);
+                    float qv;
+                    put(p0, j, e2m3_code(s, qv));
+                    v[j] = mx6_resid(v[j], s, qv, e0);
+                    ramax = fmaxf(ramax, fabsf(v[j]));
+                }
+                const int e1 = mx6_scale_exp(ramax);
+#pragma unroll
+                for (int j = 0; j < 32; ++j) {
+                    float qv;
+                    put(p1, j, e2m3_code(__builtin_ldexpf(v[j], e1), qv));
+                }
+                sb0 = (uint32_t)(127 - e0);
+                sb1 = (uint32_t)(127 - e1);
+            }
+            if (TILED) {
+                const int64_t oa = mx6_off(n, pr, h, 0, nkb), ob = mx6_off(n, pr, h, 16, nkb);
+                *reinterpret_cast<uint4*>(q + oa) = make_uint4(p0[0], p0[1], p0[2], p0[3]);
+                *reinterpret_cast<uint4*>(q + ob) = make_uint4(p0[4], p0[5], sb0, 0u);
+                *reinterpret_cast<uint4*>(rq + oa) = make_uint4(p1[0], p1[1], p1[2], p1[3]);
+                *reinterpret_cast<uint4*>(rq + ob) = make_uint4(p1[4], p1[5], sb1, 0u);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 32; ++j) {
+                    const int bit = 6 * j, d = bit >> 5, sh = bit & 31;
+                    const uint32_t c0 = ((p0[d] >> sh) | (sh > 26 ? p0[d + 1] << (32 - sh) : 0u)) & 63u;
+                    const uint32_t c1 = ((p1[d] >> sh) | (sh > 26 ? p1[d + 1] << (32 - sh) : 0u)) & 63u;
+                    if (k0 + j < K) {
+                        q[n * K + k0 + j] = (uint8_t)c0;
+                        rq[n * K + k0 + j] = (uint8_t)c1;
+                    }
+                }
+                qscale[n * nb + b] = (uint8_t)sb0;
+                rscale[n * nb + b] = (uint8_t)sb1;
+            }
+        }
+    }
+}
+
+unsigned cap(int64_t v, int64_t m) { return (unsigned)(v < 1 ? 1 : (v > m ? m : v)); }
+
+}  // namespace
+
+hipError_t launch_quant_mx6(int64_t rows, int64_t cols, const float* X, int64_t ldx,
+                            bool transpose, bool tiled, int64_t out_rows, int64_t Kp, uint8_t* q,
+                            uint8_t* qscale, uint8_t* rq, uint8_t* rscale, hipStream_t stream) {
+    if (rows <= 0 || cols <= 0 || !X || !q || !rq) return hipErrorInvalidValue;
+    const int64_t orows = transpose ? cols : rows, K = transpose ? rows : cols;
+    if (tiled) {
+        if (out_rows % kPanelRows || out_rows < orows || Kp % 64 || Kp < K)
+            return hipErrorInvalidValue;
+    } else if (!qscale || !rscale) {
+        return hipErrorInvalidValue;
+    }
+    if (!transpose) {
+        const int64_t nb = tiled ? Kp / 32 : (cols + 31) / 32;
+        if (nb * 8 >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+        const dim3 g(cap((nb * 8 + 255) / 256, 1 << 30), cap(tiled ? out_rows : rows, 65535));
+        const bool vec = (ldx % 4 == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
+        auto go = [&](auto kernel) {
+            hipLaunchKernelGGL(kernel, g, dim3(256), 0, stream, rows, cols, X, ldx, out_rows, Kp, q,
+                               qscale, rq, rscale);
+        };
+        if (vec) tiled ? go(quant_mx6_rows_kernel<true, true>) : go(quant_mx6_rows_kernel<true, false>);
+        else tiled ? go(quant_mx6_rows_kernel<false, true>) : go(quant_mx6_rows_kernel<false, false>);
+    } else {
+        const int64_t nb = tiled ? Kp / 32 : (rows + 31) / 32;
+        const dim3 g(cap(((tiled ? out_rows : cols) + 255) / 256, 1 << 30), cap((nb + 1) / 2, 65535));
+        if (tiled)
+            hipLaunchKernelGGL(quant_mx6_cols_kernel<true>, g, dim3(256), 0, stream, rows, cols, X, ldx,
+                               out_rows, Kp, q, qscale, rq, rscale);
+        else
+            hipLaunchKernelGGL(quant_mx6_cols_kernel<false>, g, dim3(256), 0, stream, rows, cols, X, ldx,
+                               out_rows, Kp, q, qscale, rq, rscale);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace cmp

@@ -304,6 +304,27 @@ size_t ws_fp8r(const void* args, void* user) {
            partial_bytes(a, gemm_splits(a, L.Kp, cmp::kStepNsFp8r, user));
 }
 
+// MX FP6 images: one byte of image per K value and level (64-byte rows per 64 K
+// values: 48 bytes of packed codes, two scale bytes, padding).
+struct Fp6Layout {
+    int64_t Mp, Np, Kp;
+    size_t a_bytes, b_bytes;
+};
+Fp6Layout fp6_layout(const cmp_gemm_args* a) {
+    Fp6Layout L;
+    L.Mp = round_up(std::max<int64_t>(a->M, 1), cmp::kMfmaTileM);
+    L.Np = round_up(std::max<int64_t>(a->N, 1), cmp::kMfmaTileN);
+    L.Kp = round_up(std::max<int64_t>(a->K, 1), 64);
+    L.a_bytes = (size_t)L.Mp * L.Kp;
+    L.b_bytes = (size_t)L.Np * L.Kp;
+    return L;
+}
+size_t ws_fp6x3(const void* args, void* user) {
+    auto a = (const cmp_gemm_args*)args;
+    auto L = fp6_layout(a);
+    return 2 * (L.a_bytes + L.b_bytes) + partial_bytes(a, gemm_splits(a, L.Kp, cmp::kStepNsFp6x3, user));
+}
+
 // Degenerate shapes shared by every built-in: nothing to do, or C = beta * C.
 bool gemm_trivial(const cmp_gemm_args* a, hipStream_t s, int* st) {
     if (a->M == 0 || a->N == 0) {
@@ -442,6 +463,43 @@ int v_fp8r(const void* args, void* ws, size_t, void* stream, void* user) {
         KTimer kt(c, s, "gemm_fp8r_tn");
         if (cmp::launch_gemm_fp8r_tn(a->M, a->N, L.Kp, a->alpha, Aq, Ar, Asq, Asr, Bq, Br, Bsq, Bsr,
                                      a->beta, a->C, a->ldc, splits, partial, s) != hipSuccess)
+            return CMP_EHIP;
+    }
+    return finish_split(c, a, splits, partial, s);
+}
+
+int v_fp6x3(const void* args, void* ws, size_t, void* stream, void* user) {
+    auto* c = (cmp_ctx*)user;
+    auto a = (const cmp_gemm_args*)args;
+    auto s = (hipStream_t)stream;
+    int st;
+    if (gemm_trivial(a, s, &st)) return st;
+    auto L = fp6_layout(a);
+    auto* p = (uint8_t*)ws;
+    uint8_t* Ah = p;
+    uint8_t* Al = Ah + L.a_bytes;
+    uint8_t* Bh = Al + L.a_bytes;
+    uint8_t* Bl = Bh + L.b_bytes;
+    const int splits = gemm_splits(a, L.Kp, cmp::kStepNsFp6x3, c);
+    float* partial = (float*)(Bl + L.b_bytes);
+    if (fork_aux(c, s) != hipSuccess) return CMP_EHIP;
+    {
+        KTimer kt(c, c->aux, "quant_mx6_bt");
+        if (cmp::launch_quant_mx6(a->K, a->N, a->B, a->ldb, true, true, L.Np, L.Kp, Bh, nullptr, Bl,
+                                  nullptr, c->aux) != hipSuccess)
+            return CMP_EHIP;
+    }
+    {
+        KTimer kt(c, s, "quant_mx6_a");
+        if (cmp::launch_quant_mx6(a->M, a->K, a->A, a->lda, false, true, L.Mp, L.Kp, Ah, nullptr, Al,
+                                  nullptr, s) != hipSuccess)
+            return CMP_EHIP;
+    }
+    if (join_aux(c, s) != hipSuccess) return CMP_EHIP;
+    {
+        KTimer kt(c, s, "gemm_fp6x3_tn");
+        if (cmp::launch_gemm_fp6x3_tn(a->M, a->N, L.Kp, a->alpha, Ah, Al, Bh, Bl, a->beta, a->C, a->ldc,
+                                      splits, partial, s) != hipSuccess)
             return CMP_EHIP;
     }
     return finish_split(c, a, splits, partial, s);
@@ -699,6 +757,27 @@ int select_nn(const cmp_ctx* c, const Interface& f, const std::vector<int>& adm,
     return argmin_tiebreak(f, adm, T.med[best]);
 }
 
+// ln(microseconds) of variant i at the nearest history shape that timed it
+// (log2-space distance, as select_nn); infinity when no shape did.
+double nn_log_us(const cmp_ctx* c, const Interface& f, int i, int64_t M, int64_t N, int64_t K) {
+    const ShapeTable& T = shapes_of(c, f.variants.size());
+    const double q0 = std::log2((double)std::max<int64_t>(M, 1));
+    const double q1 = std::log2((double)std::max<int64_t>(N, 1));
+    const double q2 = std::log2((double)std::max<int64_t>(K, 1));
+    int best = -1;
+    double bd = 0;
+    for (size_t s = 0; s < T.shapes.size(); ++s) {
+        if (!std::isfinite(T.med[s][i])) continue;
+        const double d0 = T.lg[s][0] - q0, d1 = T.lg[s][1] - q1, d2 = T.lg[s][2] - q2;
+        const double d = d0 * d0 + d1 * d1 + d2 * d2;
+        if (best < 0 || d < bd) {
+            best = (int)s;
+            bd = d;
+        }
+    }
+    return best < 0 ? INFINITY : std::log(T.med[best][i] * 1000.0);
+}
+
 }  // namespace
 
 int mlp_predict(cmp_ctx* c, int n, const float* Xraw, float* Yraw);
@@ -756,9 +835,11 @@ int do_select_batch(cmp_ctx* c, Interface* f, int n, const cmp_context* q, int* 
         std::vector<int> adm = admissible_ids(*f, x.tol);
         int id = -1;
         if (use_mlp) {
+            // the network predicts ln(us) of the four default built-ins; any
+            // other variant is estimated from the history's nearest shape
             std::vector<double> t(f->variants.size(), INFINITY);
             for (int i : adm)
-                if (i < kNumBuiltin) t[i] = pred[4 * p + i];
+                t[i] = i < kNumBuiltin ? pred[4 * p + i] : nn_log_us(c, *f, i, x.M, x.N, x.K);
             id = argmin_tiebreak(*f, adm, t);
         }
         if (id < 0 && c->selector != CMP_SEL_STATIC) id = select_nn(c, *f, adm, x.M, x.N, x.K);
@@ -1080,6 +1161,18 @@ CMP_API int cmp_set_flags(cmp_ctx* c, uint32_t flags) {
     return CMP_OK;
 }
 
+CMP_API int cmp_register_builtin(cmp_ctx* c, const char* name, int* id) {
+    if (!c || !name) return CMP_EINVAL;
+    if (!c->gpu) return fail(c, CMP_EUNSUPPORTED, "built-in variants need a GPU context");
+    if (std::strcmp(name, "fp6x3") != 0) return fail(c, CMP_ENOTFOUND, "no optional built-in named %s", name);
+    int vid = -1;
+    const int st = register_variant(c, kGemm, "fp6x3", CMP_TARGET_HIP, 0, nullptr, v_fp6x3, ws_fp6x3, 1e-2,
+                                    c, &vid);
+    if (st) return st;
+    if (id) *id = vid;
+    return CMP_OK;
+}
+
 CMP_API int cmp_set_split_k(cmp_ctx* c, int splits) {
     if (!c) return CMP_EINVAL;
     if (splits < 0 || splits > kMaxForcedSplits)
@@ -1105,6 +1198,8 @@ CMP_API int cmp_split_k(cmp_ctx* c, int id, int64_t M, int64_t N, int64_t K, int
                               fn == v_bf16x3 ? cmp::kStepNsBf16x3 : cmp::kStepNsBf16, c);
     else if (fn == v_fp8r)
         *splits = gemm_splits(&a, fp8_layout(&a).Kp, cmp::kStepNsFp8r, c);
+    else if (fn == v_fp6x3)
+        *splits = gemm_splits(&a, fp6_layout(&a).Kp, cmp::kStepNsFp6x3, c);
     else
         *splits = 1;
     return CMP_OK;
@@ -1740,6 +1835,19 @@ CMP_API int cmp_quant_fp8(cmp_ctx* c, int64_t rows, int64_t cols, const float* X
         return CMP_OK;
     }
     HIP_TRY(c, cmp::launch_quant_fp8(rows, cols, X, ldx, false, false, rows, cols, q, qs, rq, rs,
+                                     (hipStream_t)stream));
+    return CMP_OK;
+}
+
+CMP_API int cmp_quant_mx6(cmp_ctx* c, int64_t rows, int64_t cols, const float* X, int64_t ldx,
+                          int transpose, uint8_t* q, uint8_t* qs, uint8_t* rq, uint8_t* rs,
+                          void* stream) {
+    if (!c) return CMP_EINVAL;
+    if (!c->gpu) return fail(c, CMP_EUNSUPPORTED, "needs a GPU context");
+    if (rows < 0 || cols < 0 || ldx < std::max<int64_t>(cols, 1)) return fail(c, CMP_EINVAL, "bad shape");
+    if (rows == 0 || cols == 0) return CMP_OK;
+    if (!X || !q || !qs || !rq || !rs) return fail(c, CMP_EINVAL, "null pointer");
+    HIP_TRY(c, cmp::launch_quant_mx6(rows, cols, X, ldx, transpose != 0, false, 0, 0, q, qs, rq, rs,
                                      (hipStream_t)stream));
     return CMP_OK;
 }

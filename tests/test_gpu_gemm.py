@@ -22,8 +22,8 @@ from gpu_util import dev, gamma, host, say
 
 pytestmark = pytest.mark.gpu
 
-VARIANTS = ["f32_simt", "bf16x3", "fp8r", "bf16"]
-BOUND = {"f32_simt": 1e-5, "bf16x3": 1e-5, "fp8r": 1e-3, "bf16": 1e-2}
+VARIANTS = ["f32_simt", "bf16x3", "fp8r", "bf16", "fp6x3"]
+BOUND = {"f32_simt": 1e-5, "bf16x3": 1e-5, "fp8r": 1e-3, "bf16": 1e-2, "fp6x3": 1e-2}
 
 
 @pytest.fixture(scope="module")
@@ -31,6 +31,7 @@ def cx():
     import paper_2311_03543_amd as pa
     c = pa.Compar(0)
     assert c.device()["arch"].startswith("gfx950")
+    assert c.register_builtin("fp6x3") == 4
     yield c
     c.close()
 
@@ -104,6 +105,18 @@ def variant_reference(name, A, B):
         prod = sum(oracle.gemm(x, y) for x in f[:2] for y in f[2:])
         mag = sum(oracle.absgemm(x, y) for x in f[:2] for y in f[2:])
         return prod, gamma(4 * K) * mag
+    if name == "fp6x3":
+        qa, qb = oracle.quant_mx6(A), oracle.quant_mx6(np.ascontiguousarray(B.T))
+        ah = oracle.dequant_mx6(qa["q"], qa["qscale"])
+        al = oracle.dequant_mx6(qa["rq"], qa["rscale"])
+        bh = np.ascontiguousarray(oracle.dequant_mx6(qb["q"], qb["qscale"]).T)
+        bl = np.ascontiguousarray(oracle.dequant_mx6(qb["rq"], qb["rscale"]).T)
+        f = [x.astype(np.float32) for x in (ah, al, bh, bl)]
+        assert all(np.array_equal(x.astype(np.float64), y) for x, y in zip(f, (ah, al, bh, bl)))
+        pairs = [(f[0], f[2]), (f[0], f[3]), (f[1], f[2])]         # hi.hi + hi.lo + lo.hi
+        prod = sum(oracle.gemm(x, y) for x, y in pairs)
+        mag = sum(oracle.absgemm(x, y) for x, y in pairs)
+        return prod, gamma(3 * K) * mag
     raise ValueError(name)
 
 
@@ -125,7 +138,8 @@ def test_random_within_bounds(cx, name, M, N, K):
 
 # expected error levels for normal(0,1) operands: a kernel far off these has a
 # rounding bug (for instance truncation instead of round-to-nearest-even)
-LEVEL = {"f32_simt": (1e-8, 2e-6), "bf16x3": (1e-6, 8e-6), "fp8r": (5e-4, 9.6e-4), "bf16": (1.5e-3, 3.5e-3)}
+LEVEL = {"f32_simt": (1e-8, 2e-6), "bf16x3": (1e-6, 8e-6), "fp8r": (5e-4, 9.6e-4), "bf16": (1.5e-3, 3.5e-3),
+         "fp6x3": (8e-4, 2.5e-3)}
 
 
 @pytest.mark.parametrize("name", VARIANTS)
@@ -218,7 +232,7 @@ def test_nan_in_a_propagates(cx, name):
 
 # ---- split-K: few output tiles over a long K ----------------------------------------
 
-MFMA_VARIANTS = ["bf16x3", "fp8r", "bf16"]
+MFMA_VARIANTS = ["bf16x3", "fp8r", "bf16", "fp6x3"]
 
 
 def run_split(cx, name, splits, A, B, C0=None, alpha=1.0, beta=0.0):

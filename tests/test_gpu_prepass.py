@@ -1,5 +1,6 @@
 """Bit-exact parity of the operand pre-pass kernels (bf16 split, E4M3 tile quantisation with
-residual) against the oracle's encodings, and of the FP64 Freivalds probe."""
+residual, MX E2M3 block quantisation with residual) against the oracle's encodings, and of the
+FP64 Freivalds probe."""
 import numpy as np
 import pytest
 
@@ -89,6 +90,58 @@ def test_quant_fp8_integers_have_zero_residual(cx):
     got = _quant_gpu(cx, X)
     assert np.all((got["rq"] & 0x7F) == 0)
     assert np.array_equal(oracle.dequant_fp8(got["q"], got["qscale"], 256, 256), X.astype(np.float64))
+
+
+# ---- MX FP6 (E2M3) block quantisation -------------------------------------------
+
+def _quant_mx6_gpu(cx, X, transpose):
+    import torch
+    r, c = X.shape
+    orows, K = (c, r) if transpose else (r, c)
+    nb = (K + 31) // 32
+    q = torch.empty((orows, K), dtype=torch.uint8, device="cuda")
+    rq = torch.empty((orows, K), dtype=torch.uint8, device="cuda")
+    qs = torch.empty((orows, nb), dtype=torch.uint8, device="cuda")
+    rs = torch.empty((orows, nb), dtype=torch.uint8, device="cuda")
+    say(f"  quant_mx6 {r}x{c} transpose={transpose}")
+    cx.quant_mx6(dev(X), q, qs, rq, rs, transpose=transpose)
+    return dict(q=host(q), qscale=host(qs), rq=host(rq), rscale=host(rs))
+
+
+@pytest.mark.parametrize("transpose", [False, True])
+@pytest.mark.parametrize("rows,cols,dist", [(1, 1, "normal"), (37, 53, "normal"), (256, 512, "normal"),
+                                            (129, 1000, "normal"), (300, 70, "ill"), (64, 96, "special")])
+def test_quant_mx6_bit_exact(cx, rows, cols, dist, transpose):
+    if dist == "normal":
+        X = synth.normal_matrix(rows, cols, rows * cols + 1)
+    elif dist == "ill":
+        X = synth.ill_conditioned_matrix(rows, cols, 6)
+    else:
+        X = _special_values(rows * cols, 7).reshape(rows, cols)
+    got = _quant_mx6_gpu(cx, X, transpose)
+    ref = oracle.quant_mx6(np.ascontiguousarray(X.T) if transpose else X)
+    for k in ("qscale", "rscale", "q", "rq"):
+        assert np.array_equal(got[k], ref[k]), k
+
+
+@pytest.mark.parametrize("transpose", [False, True])
+def test_quant_mx6_non_finite_blocks(cx, transpose):
+    X = synth.normal_matrix(40, 70, 8)
+    X[3, 40] = np.nan
+    X[35, 2] = np.inf
+    X[20, 69] = -np.inf
+    got = _quant_mx6_gpu(cx, X, transpose)
+    ref = oracle.quant_mx6(np.ascontiguousarray(X.T) if transpose else X)
+    for k in ("qscale", "rscale", "q", "rq"):
+        assert np.array_equal(got[k], ref[k]), k
+    assert np.sum(got["qscale"] == 0xFF) == 3
+
+
+def test_quant_mx6_integers_have_zero_residual(cx):
+    X = synth.int_matrix(64, 256, 9)
+    got = _quant_mx6_gpu(cx, X, False)
+    assert not np.any(got["rq"] & 31)
+    assert np.array_equal(oracle.dequant_mx6(got["q"], got["qscale"]), X.astype(np.float64))
 
 
 # ---- Freivalds probe -----------------------------------------------------------
