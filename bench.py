@@ -2,14 +2,16 @@
 selector's regret against exhaustive timing, on one MI355X.
 
 Phases (all on cuda:0, synthetic seeded inputs, no files read):
-  1. time-and-record: every variant on the square sweep N in {128, ..., 8192}
+  1. time-and-record: every variant (the four default built-ins and the optional
+     MX fp6 variant, unless --no-fp6) on the square sweep N in {128, ..., 8192}
      (normal(0,1) operands, 3 warm-up + 20 timed reps, median) -> history;
   2. timed region: `--steps` steps after `--warmup` steps; one step is one
      cmp_gemm per tolerance class {1e-5, 1e-3, 1e-2} at M = N = K = `--size`
      with the history nearest-neighbour selector, operands resident in HBM;
      per-kernel HIP-event timing is on during this region;
   3. selector experiment (skipped with --no-selector): 2000 training and 500
-     held-out shapes with M, N, K log-uniform in [64, 8192], all variants timed,
+     held-out shapes with M, N, K log-uniform in [64, 8192], the four default
+     variants timed (the network has one output per default variant),
      network trained on the GPU from the training table, regret of each selector
      on the held-out rows of the measured table;
   4. CPU baseline: the FP64 CPU oracle on a bounded row panel of the same product.
@@ -32,7 +34,8 @@ sys.path.insert(0, ROOT)
 import synth  # noqa: E402
 
 PEAK = {  # MI355X published dense peaks (TFLOP/s) and HBM bandwidth (GB/s)
-    "bf16": 2516.6, "fp8": 5033.2, "fp32_vector": 157.3, "fp64_vector": 78.6, "hbm_gbs": 8000.0,
+    "bf16": 2516.6, "fp8": 5033.2, "fp6": 10066.3, "fp32_vector": 157.3, "fp64_vector": 78.6,
+    "hbm_gbs": 8000.0,
 }
 BOUNDS = [1e-5, 1e-5, 1e-3, 1e-2]
 
@@ -53,6 +56,8 @@ def kernel_roofline(name: str, M: int, N: int, K: int):
         return "mfma", 3 * 2.0 * M * N * K, PEAK["bf16"], "TFLOP/s"
     if name == "gemm_fp8r_tn":
         return "mfma", 4 * 2.0 * M * N * K, PEAK["fp8"], "TFLOP/s"
+    if name == "gemm_fp6x3_tn":
+        return "mfma", 3 * 2.0 * M * N * K, PEAK["fp6"], "TFLOP/s"
     # pre-pass kernels: bytes read + written (HBM-bound)
     if name == "split_a_bf16":
         return "hbm", 4.0 * M * K + 2.0 * M * Kp64, PEAK["hbm_gbs"], "GB/s"
@@ -66,6 +71,11 @@ def kernel_roofline(name: str, M: int, N: int, K: int):
         return "hbm", 4.0 * M * K + 2.0 * M * Kp128, PEAK["hbm_gbs"], "GB/s"
     if name == "quant_fp8_bt":
         return "hbm", 4.0 * K * N + 2.0 * N * Kp128, PEAK["hbm_gbs"], "GB/s"
+    # MX fp6 images: one byte per K value and level (packed codes plus the in-row scales)
+    if name == "quant_mx6_a":
+        return "hbm", 4.0 * M * K + 2.0 * M * Kp64, PEAK["hbm_gbs"], "GB/s"
+    if name == "quant_mx6_bt":
+        return "hbm", 4.0 * K * N + 2.0 * N * Kp64, PEAK["hbm_gbs"], "GB/s"
     return None
 
 
@@ -74,6 +84,7 @@ KERNEL_SOURCES = {  # kernel name -> source file (relative to the repo root)
     "gemm_bf16_tn": "paper_2311_03543_amd/csrc/gemm_mfma.hip",
     "gemm_bf16x3_tn": "paper_2311_03543_amd/csrc/gemm_mfma.hip",
     "gemm_fp8r_tn": "paper_2311_03543_amd/csrc/gemm_mfma.hip",
+    "gemm_fp6x3_tn": "paper_2311_03543_amd/csrc/gemm_mfma.hip",
 }
 
 
@@ -133,6 +144,7 @@ def main():
     ap.add_argument("--clock-seconds", type=float, default=8.0,
                     help="sustained bf16 run while sampling board power and GFX clocks (0 = skip)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp6", action="store_true", help="leave the optional MX fp6 variant unregistered")
     ap.add_argument("--sweep", type=str, default="",
                     help="comma-separated square sizes to time and record (default: 128..--size)")
     args = ap.parse_args()
@@ -151,6 +163,12 @@ def main():
     dev = cx.device()
     log(f"device {dev}")
     n = args.size
+    # the four default built-ins plus the optional MX fp6 variant: every one is timed,
+    # recorded, and open to selection
+    names = list(pa.BUILTIN_VARIANTS)
+    if not args.no_fp6:
+        assert cx.register_builtin("fp6x3") == len(names)
+        names.append("fp6x3")
 
     # ---- 1. time and record: square sweep -----------------------------------------
     sweep = {}
@@ -166,7 +184,7 @@ def main():
         dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
         dC = torch.zeros((s, s), dtype=torch.float32, device="cuda")
         row = {}
-        for vid, name in enumerate(pa.BUILTIN_VARIANTS):
+        for vid, name in enumerate(names):
             med, mn, mean = cx.time_variant(vid, dA, dB, dC, warmup=3, reps=args.reps)
             cx.history_add(s, s, s, vid, args.reps, med, mn, mean)
             row[name] = dict(median_ms=med, min_ms=mn, mean_ms=mean, tflops=2.0 * s ** 3 / (med * 1e-3) / 1e12)
@@ -201,7 +219,7 @@ def main():
     flops_step = len(tols) * 2.0 * n ** 3
     value = flops_step / (ms_per_step * 1e-3) / 1e12
     log(f"timed: {ms_per_step:.3f} ms/step, {value:.1f} TFLOP/s; chosen "
-        + ", ".join(f"{t:g}->{pa.BUILTIN_VARIANTS[v]}" for t, v in chosen.items()))
+        + ", ".join(f"{t:g}->{names[v]}" for t, v in chosen.items()))
 
     kernels = {}
     for name, (cnt, tot) in kstats.items():
@@ -221,8 +239,8 @@ def main():
     log("kernels: " + ", ".join(f"{k} {v['avg_ms']:.3f} ms ({v.get('frac', 0):.1%})" for k, v in kernels.items()))
 
     fp32_tflops = sweep[n]["f32_simt"]["tflops"]
-    per_tol = {f"{t:g}": dict(variant=pa.BUILTIN_VARIANTS[v], median_ms=sweep[n][pa.BUILTIN_VARIANTS[v]]["median_ms"],
-                              tflops=sweep[n][pa.BUILTIN_VARIANTS[v]]["tflops"]) for t, v in chosen.items()}
+    per_tol = {f"{t:g}": dict(variant=names[v], median_ms=sweep[n][names[v]]["median_ms"],
+                              tflops=sweep[n][names[v]]["tflops"]) for t, v in chosen.items()}
     del big
     torch.cuda.empty_cache()
 
