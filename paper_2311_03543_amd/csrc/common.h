@@ -47,4 +47,28 @@ __host__ __device__ __forceinline__ int64_t panel_offset(int64_t row, int64_t kb
     return ((rb * nkb + kb) << 14) + (r << 6) + ((c ^ ((r >> 2) & 3)) << 4) + (kbyte & 15);
 }
 
+// MX FP6 panel images (E2M3 codes packed 6 bits each, code j of a 32-value K
+// half at bit 6 j, little endian): per operand three arrays, hi codes, lo
+// codes and scales, cut like the panel images into blocks of 256 rows by one
+// 64-value K block; block (rb, kb) is block number rb * nkb + kb of each array.
+// A code block is 256 rows x 48 bytes (12 KiB); row r holds, at 48 r,
+//   [half 0 bytes 0-15 | half 1 bytes 0-15 | half 0 bytes 16-23 | half 1 bytes 16-23]
+// so that a lane's 24 bytes are one 16-byte and one 8-byte aligned read.  A
+// scale block is 256 rows x 4 bytes (1 KiB): row r holds the E8M0 bytes
+// (half 0 hi, half 0 lo, half 1 hi, half 1 lo) at 4 r, so one 16-bit read
+// gives a lane both levels' scales of its half.
+constexpr int kMx6RowBytes = 48, kMx6Block = kPanelRows * kMx6RowBytes, kMx6ScaleBlock = 1024;
+
+__host__ __device__ __forceinline__ int64_t mx6_code_offset(int64_t row, int64_t kb, int h, int byte,
+                                                            int64_t nkb) {
+    const int64_t rb = row >> 8;
+    const int r = (int)(row & 255);
+    const int pos = byte < 16 ? 16 * h + byte : 32 + 8 * h + (byte - 16);
+    return (rb * nkb + kb) * kMx6Block + r * kMx6RowBytes + pos;
+}
+__host__ __device__ __forceinline__ int64_t mx6_scale_offset(int64_t row, int64_t kb, int h, int level,
+                                                             int64_t nkb) {
+    return (((row >> 8) * nkb + kb) << 10) + (row & 255) * 4 + 2 * h + level;
+}
+
 }  // namespace cmp

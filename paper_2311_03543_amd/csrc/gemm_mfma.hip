@@ -8,9 +8,9 @@
 //   fp8 refined:    C = alpha * (Aq.Bq + Ar.Bq + Aq.Br + Ar.Br) + beta * C over
 //                   E4M3 images with one E8M0 scale byte per 128 x 128 tile,
 //                   v_mfma_scale_f32_32x32x64_f8f6f4, FP32 accumulation.
-//   MX fp6 x3:      C = alpha * (Ah.Bh + Ah.Bl + Al.Bh) + beta * C over E2M3
-//                   images with one E8M0 scale per 32 K values of a row (the
-//                   OCP MX block), the same MFMA at the FP6 rate.
+//   MX fp6 x3:      C = alpha * (Ah.Bh + Ah.Bl + Al.Bh) + beta * C over packed
+//                   E2M3 images with one E8M0 scale per 32 K values of a row
+//                   (the OCP MX block), the same MFMA at the FP6 rate.
 //
 // Tiling: 256 x 256 C tile per workgroup of 4 wave64 (2 x 2 waves, 128 x 128
 // per wave = 4 x 4 MFMA blocks of 32 x 32, 256 FP32 accumulators per lane).
@@ -37,6 +37,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef int intx8 __attribute__((ext_vector_type(8)));
 typedef int intx4 __attribute__((ext_vector_type(4)));
+typedef int intx2 __attribute__((ext_vector_type(2)));
 
 constexpr int TM = 256, TN = 256;
 constexpr int THREADS = 256;
@@ -155,6 +156,7 @@ constexpr int NRING = 4;
 constexpr int RSTAGE = 2 * SLAB;
 static_assert((size_t)NRING * RSTAGE <= kSmem, "ring fits the LDS allocation");
 static_assert(kKBlockBytes == kPanelRowBytes, "split-K counts K in operand-image blocks");
+static_assert(kMx6CodeBlockBytes == kMx6Block && kMx6ScaleBlockBytes == kMx6ScaleBlock, "MX FP6 image blocks");
 
 __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void gemm_bf16_ring_kernel(int64_t M, int64_t N, int nkb, float alpha, const uint8_t* __restrict__ Ah,
@@ -646,24 +648,39 @@ void gemm_fp8r_fused_kernel(int64_t M, int64_t N, int nkb, float alpha,
 
 // ---------------------------------------------------------------------------
 // MX FP6 with one residual level, three products fused per K block.  A stage
-// holds the four slabs [Ah | Bh | Al | Bl] of one 64-value K block (E2M3
-// codes packed 6 bits each with each 32-value half's E8M0 scale byte in the
-// same 32-byte lane chunk); two stages in the ring.  Products, 16 MFMAs each:
+// holds one 64-value K block: the code slabs [Ah | Bh | Al | Bl] (12 KiB each,
+// 48 bytes per row: E2M3 codes packed 6 bits each) and the A and B scale
+// blocks (1 KiB each: per row and K half the E8M0 bytes of both levels);
+// F6NBUF stages in the ring.  Products, 16 MFMAs each:
 //   h.h  (Ah, Bh)  B block major; under it: read Bl, then Al of this stage
 //   --- stage barrier: stage s + 1 landed, every read of slot s done ---
-//   h.l  (Ah, Bl)  under it: the 16 copies of stage s + 2 into slot s
-//   l.h  (Al, Bh)  B block major; under it: read Ah of stage s + 1, and each
-//                  Bh block of stage s + 1 as soon as its last MFMA has issued
-// The scaled MFMA takes each lane's own scale (its row, its K half), which is
-// dword 6 of the fragment the lane read, so no scale loads are needed.
+//   h.l  (Ah, Bl)  under it: the 13 copies of stage s + F6NBUF into slot s
+//   l.h  (Al, Bh)  B block major; under it: read Ah of stage s + 1, each Bh
+//                  block and B scale of stage s + 1 as soon as the last MFMA
+//                  using the current one has issued, and the A scales of stage
+//                  s + 1 over the last four MFMAs, one per A block as it retires
+// A lane's fragment is one 16-byte and one 8-byte LDS read (its 24 code
+// bytes); the scaled MFMA takes each lane's own scale (its row, its K half):
+// one 16-bit read per 32-row block gives both levels, and op_sel picks the
+// byte.  Per stage each wave copies 3 KiB of each code slab and one 1 KiB
+// scale piece (waves 2 and 3 a spare copy of the A piece, so that every wave
+// issues the same 13 copies and the wait counts stay constants).
+constexpr int F6SLAB = kMx6Block;                       // 12 KiB
+constexpr int F6STAGE = 4 * F6SLAB + 4 * kMx6ScaleBlock; // codes, A and B scales, 2 spare KiB
+// Two slots: copies get one stage (32 MFMAs) to land.  A third slot (156 KiB,
+// two stages of cover) measured no faster at 8192^3.
+constexpr int F6NBUF = 2;
+constexpr size_t kSmemF6 = (size_t)F6NBUF * F6STAGE;     // 104 KiB
+static_assert(kSmemF6 <= 160 * 1024, "fp6 ring fits the 160 KiB of LDS");
+
 __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void gemm_fp6x3_fused_kernel(int64_t M, int64_t N, int nkb, float alpha,
                              const uint8_t* __restrict__ Ah, const uint8_t* __restrict__ Al,
-                             const uint8_t* __restrict__ Bh, const uint8_t* __restrict__ Bl,
+                             const uint8_t* __restrict__ As, const uint8_t* __restrict__ Bh,
+                             const uint8_t* __restrict__ Bl, const uint8_t* __restrict__ Bs,
                              float beta, float* __restrict__ C, int64_t ldc, int tiles_m,
                              int tiles_n, int kb_split, float* __restrict__ P) {
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
-    // LDS ring: slot i = [Ah slab | Bh slab | Al slab | Bl slab] at i * STAGE4
 
     const int t = threadIdx.x, lane = t & 63;
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);   // wave-uniform (SGPR)
@@ -671,16 +688,18 @@ void gemm_fp6x3_fused_kernel(int64_t M, int64_t N, int nkb, float alpha,
     int tm, tn;
     tile_coords(tiles_m, tiles_n, tm, tn);
     const int64_t m0 = (int64_t)tm * TM, n0 = (int64_t)tn * TN;
-    const int64_t panel = (int64_t)nkb * SLAB;
-    const int src_off = wave * 4096 + lane * 16;
     // split-K: this workgroup's K blocks [kb0, kb0 + steps) (blockIdx.y = split)
     const int kb0 = (int)blockIdx.y * kb_split;
     const int steps = nkb - kb0 < kb_split ? nkb - kb0 : kb_split;
-    const int64_t koff = (int64_t)kb0 * SLAB;
-    const uint8_t* a_h = Ah + tm * panel + koff + src_off;
-    const uint8_t* b_h = Bh + tn * panel + koff + src_off;
-    const uint8_t* a_l = Al + tm * panel + koff + src_off;
-    const uint8_t* b_l = Bl + tn * panel + koff + src_off;
+    const int64_t a_blk = (int64_t)tm * nkb + kb0, b_blk = (int64_t)tn * nkb + kb0;
+    const int src_off = wave * 3072 + lane * 16;              // this wave's 3 KiB of a code slab
+    const uint8_t* a_h = Ah + a_blk * F6SLAB + src_off;
+    const uint8_t* b_h = Bh + b_blk * F6SLAB + src_off;
+    const uint8_t* a_l = Al + a_blk * F6SLAB + src_off;
+    const uint8_t* b_l = Bl + b_blk * F6SLAB + src_off;
+    // scale piece: wave 1 the B block, the others the A block
+    const uint8_t* s_src = (wave == 1 ? Bs + b_blk * kMx6ScaleBlock : As + a_blk * kMx6ScaleBlock) + lane * 16;
+    const int s_dst = 4 * F6SLAB + wave * kMx6ScaleBlock;   // A at +0, B at +1 KiB, spares after
 
     floatx16 acc[4][4];
 #pragma unroll
@@ -691,37 +710,55 @@ void gemm_fp6x3_fused_kernel(int64_t M, int64_t N, int nkb, float alpha,
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
     // Load cursor (K block, slot); past the last block it re-reads the last
-    // one into the freed slot, so every stage issues the same 16 copies.
+    // one into the freed slot, so every stage issues the same 13 copies.
     int ld_kb = 0, ld_left = steps, ld_slot = 0;
-    int64_t kofs = 0;
+    int64_t kofs = 0, sofs = 0;
     uint8_t* dd = nullptr;
+    uint8_t* sd = nullptr;
     auto prepare = [&]() {
-        kofs = (int64_t)ld_kb * SLAB;
-        dd = smem + ld_slot * STAGE4 + wave * 4096;
+        kofs = (int64_t)ld_kb * F6SLAB;
+        sofs = (int64_t)ld_kb * kMx6ScaleBlock;
+        dd = smem + ld_slot * F6STAGE + wave * 3072;
+        sd = smem + ld_slot * F6STAGE + s_dst;
         const int go = ld_left > 1 ? 1 : 0;
         ld_left -= go;
         ld_kb += go;
-        ld_slot ^= 1;
+        ld_slot = ld_slot == F6NBUF - 1 ? 0 : ld_slot + 1;
     };
-    auto copy = [&](auto part_tag) {            // copy P: slab P / 4, part P % 4
+    auto copy = [&](auto part_tag) {            // copy P < 12: slab P / 3, part P % 3; 12: scales
         constexpr int P = decltype(part_tag)::value;
-        static_assert(P >= 0 && P < 16, "a fused stage is 16 copies");
-        constexpr int S = P / 4;
-        const uint8_t* src = S == 0 ? a_h : (S == 1 ? b_h : (S == 2 ? a_l : b_l));
-        dma_part<P % 4>(src + kofs, dd + S * SLAB);
+        static_assert(P >= 0 && P < 13, "a stage is 13 copies");
+        if constexpr (P == 12) {
+            dma_part<0>(s_src + sofs, sd);
+        } else {
+            constexpr int S = P / 3;
+            const uint8_t* src = S == 0 ? a_h : (S == 1 ? b_h : (S == 2 ? a_l : b_l));
+            dma_part<P % 3>(src + kofs, dd + S * F6SLAB);
+        }
     };
 
-    // Operand registers: image X in {Ah, Bh, Al, Bl} (X = 0..3), 32-row block
-    // b, half H % 2 of the lane's 32 bytes: R[X][2 b + half].  Lane l feeds row
-    // l % 32 of a block, K half l / 32 (bytes 32 (l / 32) .. +31 of the row).
-    intx4 R[4][8];
+    // Operand registers of image X in {Ah, Bh, Al, Bl} (X = 0..3), 32-row block
+    // b: code bytes 0-15 in R4[X][b], 16-23 in R2[X][b].  Lane l feeds row
+    // l % 32 of a block, K half l / 32.  Scales: SA[b] / SB[b] hold (hi, lo)
+    // of A / B block b, replaced by the next stage's as each retires.
+    intx4 R4[4][4];
+    intx2 R2[4][4];
+    int SA[4], SB[4];
     const int frag_row = lane & 31;
-    const int frag_c = (lane >> 5) * 2;
+    const int half = lane >> 5;
+    // H = 2 b + p: p = 0 the 16-byte read, p = 1 the 8-byte read of block b
     auto read = [&](int slot, auto x_tag, auto h_tag) {
         constexpr int X = decltype(x_tag)::value, H = decltype(h_tag)::value;
-        constexpr int blk = H / 2, half = H % 2;
+        constexpr int blk = H / 2, part = H % 2;
         const int r = ((X & 1) ? wn : wm) * 128 + blk * 32 + frag_row;
-        R[X][H] = *reinterpret_cast<const intx4*>(smem + slot * STAGE4 + X * SLAB + slab_off(r, frag_c + half));
+        const uint8_t* row = smem + slot * F6STAGE + X * F6SLAB + r * kMx6RowBytes;
+        if constexpr (part == 0) R4[X][blk] = *reinterpret_cast<const intx4*>(row + 16 * half);
+        else R2[X][blk] = *reinterpret_cast<const intx2*>(row + 32 + 8 * half);
+    };
+    auto read_scale = [&](int slot, int side, int blk) -> int {
+        const int r = (side ? wn : wm) * 128 + blk * 32 + frag_row;
+        return *reinterpret_cast<const uint16_t*>(smem + slot * F6STAGE + 4 * F6SLAB + side * kMx6ScaleBlock +
+                                                  4 * r + 2 * half);
     };
     // MFMA q (0..15) of product P (0 h.h, 1 h.l, 2 l.h); h.h and l.h run B
     // block major (j = q / 4) so that a B block is finished after 4 MFMAs.
@@ -729,33 +766,40 @@ void gemm_fp6x3_fused_kernel(int64_t M, int64_t N, int nkb, float alpha,
         constexpr int P = decltype(p_tag)::value, q = decltype(q_tag)::value;
         constexpr int i = P == 1 ? q / 4 : q % 4, j = P == 1 ? q % 4 : q / 4;
         constexpr int XA = P == 2 ? 2 : 0, XB = P == 1 ? 3 : 1;
-        const intx8 av = __builtin_shufflevector(R[XA][2 * i], R[XA][2 * i + 1], 0, 1, 2, 3, 4, 5, 6, 7);
-        const intx8 bv = __builtin_shufflevector(R[XB][2 * j], R[XB][2 * j + 1], 0, 1, 2, 3, 4, 5, 6, 7);
-        // operand format 2 = FP6 E2M3 for both; dwords 0-5 are the 32 codes,
-        // dword 6 the lane's E8M0 scale byte (opsel 0 selects its byte 0)
-        acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, acc[i][j], 2, 2, 0, av[6], 0,
-                                                                    bv[6]);
+        constexpr int LA = XA == 0 ? 0 : 1, LB = XB == 1 ? 0 : 1;   // scale byte: hi 0, lo 1
+        const intx8 av = __builtin_shufflevector(R4[XA][i], __builtin_shufflevector(R2[XA][i], R2[XA][i], 0, 1, 0, 1),
+                                                 0, 1, 2, 3, 4, 5, 6, 7);
+        const intx8 bv = __builtin_shufflevector(R4[XB][j], __builtin_shufflevector(R2[XB][j], R2[XB][j], 0, 1, 0, 1),
+                                                 0, 1, 2, 3, 4, 5, 6, 7);
+        // operand format 2 = FP6 E2M3 for both (dwords 0-5 used)
+        acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, acc[i][j], 2, 2, LA, SA[i], LB,
+                                                                    SB[j]);
     };
     using I0 = std::integral_constant<int, 0>;
     using I1 = std::integral_constant<int, 1>;
     using I2 = std::integral_constant<int, 2>;
     using I3 = std::integral_constant<int, 3>;
 
-    // prologue: stages 0 and 1 in flight, wait for stage 0, read Ah and Bh of stage 0
+    // prologue: stages 0 .. F6NBUF - 1 in flight, wait for stage 0, read its Ah, Bh and scales
 #pragma unroll
-    for (int p = 0; p < 2; ++p) {
+    for (int p = 0; p < F6NBUF; ++p) {
         prepare();
-        static_for<0, 16>(copy);
+        static_for<0, 13>(copy);
     }
-    stage_barrier<16>();                         // stage 1 (16 copies) may stay in flight
+    stage_barrier<13 * (F6NBUF - 1)>();          // the later stages may stay in flight
     static_for<0, 8>([&](auto h) { read(0, I0{}, h); });
     static_for<0, 8>([&](auto h) { read(0, I1{}, h); });
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        SA[b] = read_scale(0, 0, b);
+        SB[b] = read_scale(0, 1, b);
+    }
     int cur = 0;
     pin();
 
     auto one_stage = [&](auto more_tag) {
         constexpr bool MORE = decltype(more_tag)::value;
-        const int nxt = cur ^ 1;
+        const int nxt = cur == F6NBUF - 1 ? 0 : cur + 1;
         // h.h; read Bl then Al of this stage under it
         static_for<0, 16>([&](auto q) {
             mfma(I0{}, q);
@@ -765,19 +809,21 @@ void gemm_fp6x3_fused_kernel(int64_t M, int64_t N, int nkb, float alpha,
             pin();
         });
         if constexpr (MORE) {
-            stage_barrier<0>();                 // stage s + 1 landed, slot `cur` free
+            stage_barrier<13 * (F6NBUF - 2)>(); // stage s + 1 landed, slot `cur` free
             prepare();
         }
         pin();
-        // h.l; the copies of stage s + 2 under it
+        // h.l; the copies of stage s + F6NBUF under it
         static_for<0, 16>([&](auto q) {
             mfma(I1{}, q);
-            if constexpr (MORE) copy(q);
+            constexpr int k = decltype(q)::value;
+            if constexpr (MORE && k < 13) copy(q);
             pin();
         });
         pin();
-        // l.h; Ah of stage s + 1 under the first 8 MFMAs, Bh block j of stage
-        // s + 1 once MFMA 4 j + 3 (the last one reading block j) has issued
+        // l.h; Ah of stage s + 1 under the first 8 MFMAs; Bh block j and B
+        // scale j of stage s + 1 once MFMA 4 j + 3 (the last one reading them)
+        // has issued; A scale i of stage s + 1 once MFMA 12 + i has issued
         static_for<0, 16>([&](auto q) {
             mfma(I2{}, q);
             constexpr int k = decltype(q)::value;
@@ -785,7 +831,9 @@ void gemm_fp6x3_fused_kernel(int64_t M, int64_t N, int nkb, float alpha,
             if constexpr (MORE && k % 4 == 3) {
                 read(nxt, I1{}, std::integral_constant<int, 2 * (k / 4)>{});
                 read(nxt, I1{}, std::integral_constant<int, 2 * (k / 4) + 1>{});
+                SB[k / 4] = read_scale(nxt, 1, k / 4);
             }
+            if constexpr (MORE && k >= 12) SA[k - 12] = read_scale(nxt, 0, k - 12);
             pin();
         });
         pin();
@@ -803,13 +851,13 @@ void gemm_fp6x3_fused_kernel(int64_t M, int64_t N, int nkb, float alpha,
 // The kernels use more than the default 64 KiB of dynamic LDS; the limit is a
 // per-device function attribute, set once on each device the library runs on.
 template <class Kernel>
-hipError_t allow_lds(Kernel kernel, std::atomic<uint64_t>& done) {
+hipError_t allow_lds(Kernel kernel, std::atomic<uint64_t>& done, size_t bytes = kSmem) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     const uint64_t bit = dev < 64 ? (uint64_t)1 << dev : 0;
     if (bit && (done.load(std::memory_order_relaxed) & bit)) return hipSuccess;
-    e = hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmem);
+    e = hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (e == hipSuccess) done.fetch_or(bit, std::memory_order_relaxed);
     return e;
 }
@@ -902,20 +950,21 @@ hipError_t launch_gemm_fp8r_tn(int64_t M, int64_t N, int64_t Kp, float alpha, co
 }
 
 hipError_t launch_gemm_fp6x3_tn(int64_t M, int64_t N, int64_t Kp, float alpha, const uint8_t* Ah,
-                                const uint8_t* Al, const uint8_t* Bh, const uint8_t* Bl, float beta,
-                                float* C, int64_t ldc, int splits, float* partial,
-                                hipStream_t stream) {
+                                const uint8_t* Al, const uint8_t* As, const uint8_t* Bh,
+                                const uint8_t* Bl, const uint8_t* Bs, float beta, float* C,
+                                int64_t ldc, int splits, float* partial, hipStream_t stream) {
     if (Kp % 64 || Kp <= 0) return hipErrorInvalidValue;
     static std::atomic<uint64_t> lds_f6{0};
-    if (hipError_t e = allow_lds(gemm_fp6x3_fused_kernel, lds_f6)) return e;
+    if (hipError_t e = allow_lds(gemm_fp6x3_fused_kernel, lds_f6, kSmemF6)) return e;
     const int tiles_m = (int)((M + TM - 1) / TM), tiles_n = (int)((N + TN - 1) / TN);
-    const int nkb = (int)(Kp / 64);               // one 64-byte image block per 64 K values
+    const int nkb = (int)(Kp / 64);               // one image block per 64 K values
     if (splits < 1 || (splits > 1 && !partial)) return hipErrorInvalidValue;
     const int kbs = kb_per_split(nkb, splits);
     if ((int64_t)(splits - 1) * kbs >= nkb) return hipErrorInvalidValue;   // every slice non-empty
     float* P = splits > 1 ? partial : nullptr;
-    hipLaunchKernelGGL(gemm_fp6x3_fused_kernel, dim3(tiles_m * tiles_n, splits), dim3(THREADS), kSmem,
-                       stream, M, N, nkb, alpha, Ah, Al, Bh, Bl, beta, C, ldc, tiles_m, tiles_n, kbs, P);
+    hipLaunchKernelGGL(gemm_fp6x3_fused_kernel, dim3(tiles_m * tiles_n, splits), dim3(THREADS), kSmemF6,
+                       stream, M, N, nkb, alpha, Ah, Al, As, Bh, Bl, Bs, beta, C, ldc, tiles_m, tiles_n, kbs,
+                       P);
     return hipGetLastError();
 }
 

@@ -75,10 +75,10 @@ hipError_t launch_quant_fp8(int64_t rows, int64_t cols, const float* X, int64_t 
 //                      output row per row of X.
 //   transpose = true:  X is rows x cols = K x N, blocks along its columns
 //                      (K = rows), one output row per column of X.
-//   tiled = true:  q / rq are panel images of out_rows rows (>= the output
-//                  rows, a multiple of 256) and Kp K values (>= K, a multiple
-//                  of 64) in the packed layout the fp6 GEMM reads; the scales
-//                  live inside the images (qscale, rscale unused).
+//   tiled = true:  q / rq / qscale are the hi-code, lo-code and scale arrays
+//                  of an MX FP6 image (common.h) of out_rows rows (>= the
+//                  output rows, a multiple of 256) and Kp K values (>= K, a
+//                  multiple of 64); rscale unused.
 //   tiled = false: one code per byte, row-major (output rows x K), scale
 //                  bytes output rows x ceil(K / 32); out_rows, Kp unused.
 hipError_t launch_quant_mx6(int64_t rows, int64_t cols, const float* X, int64_t ldx,
@@ -109,12 +109,13 @@ hipError_t launch_gemm_fp8r_tn(int64_t M, int64_t N, int64_t Kp, float alpha,
                                hipStream_t stream);
 
 // MX FP6 with one residual level: C = alpha * (Ah.Bh + Ah.Bl + Al.Bh) + beta * C
-// over the tiled E2M3 images of launch_quant_mx6 (Mp / Np rows, Kp K values,
-// Kp % 64 == 0); splits and partial as above (splits <= Kp / 64).
+// over the MX FP6 images of launch_quant_mx6 (codes Ah / Al and scales As of
+// Mp rows, Bh / Bl / Bs of Np rows, Kp K values, Kp % 64 == 0); splits and
+// partial as above (splits <= Kp / 64).
 hipError_t launch_gemm_fp6x3_tn(int64_t M, int64_t N, int64_t Kp, float alpha, const uint8_t* Ah,
-                                const uint8_t* Al, const uint8_t* Bh, const uint8_t* Bl, float beta,
-                                float* C, int64_t ldc, int splits, float* partial,
-                                hipStream_t stream);
+                                const uint8_t* Al, const uint8_t* As, const uint8_t* Bh,
+                                const uint8_t* Bl, const uint8_t* Bs, float beta, float* C,
+                                int64_t ldc, int splits, float* partial, hipStream_t stream);
 
 // C = alpha * (partial[0] + ... + partial[splits - 1]) + beta * C, summed in
 // that order (beta == 0 never reads C); splits >= 2.
@@ -162,6 +163,8 @@ constexpr int kMfmaTileN = 256;
 constexpr int kBf16TileK = 64;
 constexpr int kFp8TileK = 128;
 constexpr int kKBlockBytes = 64;   // bytes of K per operand-image block (split-K unit)
+// MX FP6 image blocks (256 rows x 64 K values): codes per level, scales (both levels)
+constexpr int kMx6CodeBlockBytes = 256 * 48, kMx6ScaleBlockBytes = 1024;
 
 // ---- FP64 Freivalds probe -------------------------------------------------
 // out[0] = ||C x - (alpha A (B x) + beta C0 x)||^2, out[1] = ||alpha A(Bx) + beta C0 x||^2.

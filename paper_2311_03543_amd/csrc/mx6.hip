@@ -10,11 +10,9 @@
 // infinity gets the E8M0 NaN byte 0xff at both levels and zero codes; the
 // MFMA then turns every product of that block into NaN.
 //
-// Panel images (tiled) use the layout of common.h with 64-byte rows per 64 K
-// values: bytes [32 h, 32 h + 24) of a row hold the 32 codes of K half h
-// packed 6 bits each (code j at bit 6 j, little endian), byte 32 h + 24 its
-// scale byte, and the rest of the 32 bytes is zero.  A lane of the GEMM reads
-// its 32 bytes as 8 dwords: dwords 0-5 are the MFMA operand, dword 6 its scale.
+// Panel images (tiled) are the MX FP6 images of common.h: hi codes, lo codes
+// (48 bytes per row and 64-value K block) and one scale array holding both
+// levels' E8M0 bytes per row and K half.
 #include "common.h"
 #include "kernels.h"
 
@@ -61,18 +59,14 @@ __device__ __forceinline__ float mx6_resid(float x, float s, float qv, int e) {
     return qv == 0.f ? x - qv : __builtin_ldexpf(s - qv, -e);
 }
 
-// Byte offset, inside a tiled image, of byte `byte` (0..31) of K half `h` of
-// the 64-value K block `kb` of image row `row`.
-__device__ __forceinline__ int64_t mx6_off(int64_t row, int64_t kb, int h, int byte, int64_t nkb) {
-    return panel_offset(row, kb * 64 + h * 32 + byte, nkb);
-}
 
 // ---------------------------------------------------------------------------
 // Rows of X (blocks along X's rows, K = cols): eight lanes per block, four
 // consecutive values each, so one wave reads 1 KiB of a row with each load.
 // The block's amax and NaN flag are reduced over the eight lanes; each lane
 // then holds 4 codes (24 bits) and lane i < 6 assembles dword i of the packed
-// 192 bits from the 24-bit words of two neighbours.
+// 192 bits from the 24-bit words of two neighbours; lane 6 writes the block's
+// two scale bytes.
 template <bool VEC, bool TILED>
 __global__ __launch_bounds__(256) void quant_mx6_rows_kernel(
     int64_t rows, int64_t cols, const float* __restrict__ X, int64_t ldx, int64_t out_rows,
@@ -141,20 +135,17 @@ __global__ __launch_bounds__(256) void quant_mx6_rows_kernel(
             sb1 = (uint32_t)(127 - e1);
         }
         if (TILED) {
-            // dword li of this block's 32 bytes: packed codes, scale byte, zero
+            // dword li (< 6) of this block's 24 code bytes; the scales from lane 6
             const uint32_t lo0 = __shfl(w0, src_lo), hi0 = __shfl(w0, src_hi);
             const uint32_t lo1 = __shfl(w1, src_lo), hi1 = __shfl(w1, src_hi);
-            uint32_t d0, d1;
             if (li < 6) {
-                d0 = (lo0 >> sh) | (hi0 << (24 - sh));
-                d1 = (lo1 >> sh) | (hi1 << (24 - sh));
-            } else {
-                d0 = li == 6 ? sb0 : 0u;
-                d1 = li == 6 ? sb1 : 0u;
+                const int64_t o = mx6_code_offset(r, b >> 1, b & 1, 4 * li, nkb);
+                *reinterpret_cast<uint32_t*>(q + o) = (lo0 >> sh) | (hi0 << (24 - sh));
+                *reinterpret_cast<uint32_t*>(rq + o) = (lo1 >> sh) | (hi1 << (24 - sh));
+            } else if (li == 6) {
+                *reinterpret_cast<uint16_t*>(qscale + mx6_scale_offset(r, b >> 1, b & 1, 0, nkb)) =
+                    (uint16_t)(sb0 | (sb1 << 8));
             }
-            const int64_t o = mx6_off(r, b >> 1, b & 1, 4 * li, nkb);
-            *reinterpret_cast<uint32_t*>(q + o) = d0;
-            *reinterpret_cast<uint32_t*>(rq + o) = d1;
         } else {
             // one code per byte, row-major rows x cols; the scales from lane 0
 #pragma unroll
@@ -173,23 +164,29 @@ __global__ __launch_bounds__(256) void quant_mx6_rows_kernel(
 
 // ---------------------------------------------------------------------------
 // Columns of X (X is K x N; output row n = column n of X, blocks along K):
-// one lane per pair of blocks (64 K values, one 64-byte image row segment),
-// consecutive lanes on consecutive columns, so each load of a lane is one
-// coalesced row segment of X and a wave's four 16-byte stores fill a
-// contiguous 4 KiB of the image.  The lane packs its 32 codes per block itself.
+// one lane per pair of blocks (64 K values, one 48-byte image row and its 4
+// scale bytes), consecutive lanes on consecutive columns, so each load of a
+// lane is one coalesced row segment of X and a wave's stores fill contiguous
+// 3 KiB of each code image.  The lane packs its 32 codes per block itself.
 template <bool TILED>
 __global__ __launch_bounds__(256) void quant_mx6_cols_kernel(
     int64_t K, int64_t N, const float* __restrict__ X, int64_t ldx, int64_t out_rows, int64_t Kp,
     uint8_t* __restrict__ q, uint8_t* __restrict__ qscale, uint8_t* __restrict__ rq,
     uint8_t* __restrict__ rscale) {
-    // grid: x over output rows (columns of X), y over pairs of blocks
+    // grid: x over output rows (columns of X), y over pairs of blocks.  Tiled:
+    // a workgroup's 256 rows are one 256-row image block, staged in LDS so that
+    // its two 12 KiB code blocks leave as whole coalesced lines.
+    static_assert(kMx6Block % (16 * 256) == 0, "a staged block is whole 16-byte stores per lane");
+    __shared__ uint4 stage_h[TILED ? kMx6Block / 16 : 1], stage_l[TILED ? kMx6Block / 16 : 1];
     const int64_t nb = TILED ? Kp / 32 : (K + 31) / 32;
     const int64_t npairs = (nb + 1) / 2;
     const int64_t nrows = TILED ? out_rows : N;
     const int64_t nkb = Kp / 64;
-    const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (n >= nrows) return;
+    const int t = threadIdx.x;
+    const int64_t n = (int64_t)blockIdx.x * 256 + t;
+    if (!TILED && n >= nrows) return;        // tiled: out_rows % 256 == 0, every lane has a row
     for (int64_t pr = blockIdx.y; pr < npairs; pr += gridDim.y) {
+        uint32_t scales = 0;                    // (h0 hi, h0 lo, h1 hi, h1 lo) of this row segment
 #pragma unroll 1
         for (int h = 0; h < 2; ++h) {
             const int64_t b = 2 * pr + h;
@@ -233,11 +230,14 @@ __global__ __launch_bounds__(256) void quant_mx6_cols_kernel(
                 sb1 = (uint32_t)(127 - e1);
             }
             if (TILED) {
-                const int64_t oa = mx6_off(n, pr, h, 0, nkb), ob = mx6_off(n, pr, h, 16, nkb);
-                *reinterpret_cast<uint4*>(q + oa) = make_uint4(p0[0], p0[1], p0[2], p0[3]);
-                *reinterpret_cast<uint4*>(q + ob) = make_uint4(p0[4], p0[5], sb0, 0u);
-                *reinterpret_cast<uint4*>(rq + oa) = make_uint4(p1[0], p1[1], p1[2], p1[3]);
-                *reinterpret_cast<uint4*>(rq + ob) = make_uint4(p1[4], p1[5], sb1, 0u);
+                // this row's 48 bytes at 48 t of the staged block (the image's row layout)
+                uint8_t* sh8 = reinterpret_cast<uint8_t*>(stage_h) + t * kMx6RowBytes;
+                uint8_t* sl8 = reinterpret_cast<uint8_t*>(stage_l) + t * kMx6RowBytes;
+                *reinterpret_cast<uint4*>(sh8 + 16 * h) = make_uint4(p0[0], p0[1], p0[2], p0[3]);
+                *reinterpret_cast<uint2*>(sh8 + 32 + 8 * h) = make_uint2(p0[4], p0[5]);
+                *reinterpret_cast<uint4*>(sl8 + 16 * h) = make_uint4(p1[0], p1[1], p1[2], p1[3]);
+                *reinterpret_cast<uint2*>(sl8 + 32 + 8 * h) = make_uint2(p1[4], p1[5]);
+                scales |= (sb0 | (sb1 << 8)) << (16 * h);
             } else {
 #pragma unroll
                 for (int j = 0; j < 32; ++j) {
@@ -253,6 +253,17 @@ __global__ __launch_bounds__(256) void quant_mx6_cols_kernel(
                 rscale[n * nb + b] = (uint8_t)sb1;
             }
         }
+        if (TILED) {
+            *reinterpret_cast<uint32_t*>(qscale + mx6_scale_offset(n, pr, 0, 0, nkb)) = scales;
+            __syncthreads();
+            const int64_t base = ((int64_t)blockIdx.x * nkb + pr) * kMx6Block;
+#pragma unroll
+            for (int c = 0; c < kMx6Block / 16 / 256; ++c) {
+                reinterpret_cast<uint4*>(q + base)[t + 256 * c] = stage_h[t + 256 * c];
+                reinterpret_cast<uint4*>(rq + base)[t + 256 * c] = stage_l[t + 256 * c];
+            }
+            __syncthreads();                     // the stage is rewritten by the next pair
+        }
     }
 }
 
@@ -266,7 +277,7 @@ hipError_t launch_quant_mx6(int64_t rows, int64_t cols, const float* X, int64_t 
     if (rows <= 0 || cols <= 0 || !X || !q || !rq) return hipErrorInvalidValue;
     const int64_t orows = transpose ? cols : rows, K = transpose ? rows : cols;
     if (tiled) {
-        if (out_rows % kPanelRows || out_rows < orows || Kp % 64 || Kp < K)
+        if (out_rows % kPanelRows || out_rows < orows || Kp % 64 || Kp < K || !qscale)
             return hipErrorInvalidValue;
     } else if (!qscale || !rscale) {
         return hipErrorInvalidValue;

@@ -304,25 +304,28 @@ size_t ws_fp8r(const void* args, void* user) {
            partial_bytes(a, gemm_splits(a, L.Kp, cmp::kStepNsFp8r, user));
 }
 
-// MX FP6 images: one byte of image per K value and level (64-byte rows per 64 K
-// values: 48 bytes of packed codes, two scale bytes, padding).
+// MX FP6 images: per operand hi and lo codes (3/4 byte per value) and one
+// scale array (4 bytes per row and 64-value K block).
 struct Fp6Layout {
     int64_t Mp, Np, Kp;
-    size_t a_bytes, b_bytes;
+    size_t a_codes, b_codes, a_scales, b_scales;
 };
 Fp6Layout fp6_layout(const cmp_gemm_args* a) {
     Fp6Layout L;
     L.Mp = round_up(std::max<int64_t>(a->M, 1), cmp::kMfmaTileM);
     L.Np = round_up(std::max<int64_t>(a->N, 1), cmp::kMfmaTileN);
     L.Kp = round_up(std::max<int64_t>(a->K, 1), 64);
-    L.a_bytes = (size_t)L.Mp * L.Kp;
-    L.b_bytes = (size_t)L.Np * L.Kp;
+    L.a_codes = (size_t)(L.Mp / 256) * (L.Kp / 64) * cmp::kMx6CodeBlockBytes;
+    L.b_codes = (size_t)(L.Np / 256) * (L.Kp / 64) * cmp::kMx6CodeBlockBytes;
+    L.a_scales = (size_t)(L.Mp / 256) * (L.Kp / 64) * cmp::kMx6ScaleBlockBytes;
+    L.b_scales = (size_t)(L.Np / 256) * (L.Kp / 64) * cmp::kMx6ScaleBlockBytes;
     return L;
 }
 size_t ws_fp6x3(const void* args, void* user) {
     auto a = (const cmp_gemm_args*)args;
     auto L = fp6_layout(a);
-    return 2 * (L.a_bytes + L.b_bytes) + partial_bytes(a, gemm_splits(a, L.Kp, cmp::kStepNsFp6x3, user));
+    return 2 * (L.a_codes + L.b_codes) + L.a_scales + L.b_scales +
+           partial_bytes(a, gemm_splits(a, L.Kp, cmp::kStepNsFp6x3, user));
 }
 
 // Degenerate shapes shared by every built-in: nothing to do, or C = beta * C.
@@ -477,29 +480,31 @@ int v_fp6x3(const void* args, void* ws, size_t, void* stream, void* user) {
     auto L = fp6_layout(a);
     auto* p = (uint8_t*)ws;
     uint8_t* Ah = p;
-    uint8_t* Al = Ah + L.a_bytes;
-    uint8_t* Bh = Al + L.a_bytes;
-    uint8_t* Bl = Bh + L.b_bytes;
+    uint8_t* Al = Ah + L.a_codes;
+    uint8_t* Bh = Al + L.a_codes;
+    uint8_t* Bl = Bh + L.b_codes;
+    uint8_t* As = Bl + L.b_codes;
+    uint8_t* Bs = As + L.a_scales;
     const int splits = gemm_splits(a, L.Kp, cmp::kStepNsFp6x3, c);
-    float* partial = (float*)(Bl + L.b_bytes);
+    float* partial = (float*)(Bs + L.b_scales);
     if (fork_aux(c, s) != hipSuccess) return CMP_EHIP;
     {
         KTimer kt(c, c->aux, "quant_mx6_bt");
-        if (cmp::launch_quant_mx6(a->K, a->N, a->B, a->ldb, true, true, L.Np, L.Kp, Bh, nullptr, Bl,
+        if (cmp::launch_quant_mx6(a->K, a->N, a->B, a->ldb, true, true, L.Np, L.Kp, Bh, Bs, Bl,
                                   nullptr, c->aux) != hipSuccess)
             return CMP_EHIP;
     }
     {
         KTimer kt(c, s, "quant_mx6_a");
-        if (cmp::launch_quant_mx6(a->M, a->K, a->A, a->lda, false, true, L.Mp, L.Kp, Ah, nullptr, Al,
+        if (cmp::launch_quant_mx6(a->M, a->K, a->A, a->lda, false, true, L.Mp, L.Kp, Ah, As, Al,
                                   nullptr, s) != hipSuccess)
             return CMP_EHIP;
     }
     if (join_aux(c, s) != hipSuccess) return CMP_EHIP;
     {
         KTimer kt(c, s, "gemm_fp6x3_tn");
-        if (cmp::launch_gemm_fp6x3_tn(a->M, a->N, L.Kp, a->alpha, Ah, Al, Bh, Bl, a->beta, a->C, a->ldc,
-                                      splits, partial, s) != hipSuccess)
+        if (cmp::launch_gemm_fp6x3_tn(a->M, a->N, L.Kp, a->alpha, Ah, Al, As, Bh, Bl, Bs, a->beta, a->C,
+                                      a->ldc, splits, partial, s) != hipSuccess)
             return CMP_EHIP;
     }
     return finish_split(c, a, splits, partial, s);
