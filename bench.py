@@ -71,11 +71,11 @@ def kernel_roofline(name: str, M: int, N: int, K: int):
         return "hbm", 4.0 * M * K + 2.0 * M * Kp128, PEAK["hbm_gbs"], "GB/s"
     if name == "quant_fp8_bt":
         return "hbm", 4.0 * K * N + 2.0 * N * Kp128, PEAK["hbm_gbs"], "GB/s"
-    # MX fp6 images: one byte per K value and level (packed codes plus the in-row scales)
+    # MX fp6 images: 3/4 byte per K value and level, plus 4 scale bytes per 64 K values
     if name == "quant_mx6_a":
-        return "hbm", 4.0 * M * K + 2.0 * M * Kp64, PEAK["hbm_gbs"], "GB/s"
+        return "hbm", 4.0 * M * K + 1.5625 * M * Kp64, PEAK["hbm_gbs"], "GB/s"
     if name == "quant_mx6_bt":
-        return "hbm", 4.0 * K * N + 2.0 * N * Kp64, PEAK["hbm_gbs"], "GB/s"
+        return "hbm", 4.0 * K * N + 1.5625 * N * Kp64, PEAK["hbm_gbs"], "GB/s"
     return None
 
 

@@ -47,7 +47,7 @@ def test_roofline_work_per_launch(name):
     mnk = 256 * 512 * 128
     expect = {"gemm_bf16_tn": 2 * mnk, "gemm_bf16x3_tn": 6 * mnk, "gemm_fp8r_tn": 8 * mnk,
               "gemm_f32_simt": 2 * mnk, "gemm_fp6x3_tn": 6 * mnk, "split_a_bf16": 4 * 256 * 128 + 2 * 256 * 128,
-              "quant_fp8_bt": 4 * 128 * 512 + 2 * 512 * 128, "quant_mx6_a": 4 * 256 * 128 + 2 * 256 * 128,
-              "quant_mx6_bt": 4 * 128 * 512 + 2 * 512 * 128}[name]
+              "quant_fp8_bt": 4 * 128 * 512 + 2 * 512 * 128, "quant_mx6_a": 4 * 256 * 128 + 1.5625 * 256 * 128,
+              "quant_mx6_bt": 4 * 128 * 512 + 1.5625 * 512 * 128}[name]
     assert work == expect
     assert (bound == "hbm") == (unit == "GB/s")
