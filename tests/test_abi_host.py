@@ -300,3 +300,31 @@ print(c.admissible(8, 8, 8, 1e-2))
     env = dict(os.environ, COMPAR_VARIANTS="bf16,fp8r", PYTHONPATH=ROOT)
     out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, check=True)
     assert out.stdout.strip() == "12"        # fp8r (bit 2) and bf16 (bit 3) only
+
+
+def test_split_k_and_optional_builtin_argument_checks():
+    c = host_ctx()
+    L, ctx = c.L, c.ctx
+    # forcing knob: 0 (automatic) and 1..64 accepted, anything else refused
+    assert L.cmp_set_split_k(ctx, 0) == pa.CMP_OK
+    assert L.cmp_set_split_k(ctx, 64) == pa.CMP_OK
+    assert L.cmp_set_split_k(ctx, 65) == pa.CMP_EINVAL
+    assert L.cmp_set_split_k(ctx, -1) == pa.CMP_EINVAL
+    assert L.cmp_set_split_k(None, 0) == pa.CMP_EINVAL
+    n = C.c_int(-7)
+    # the host context has no built-in variants: every id is out of range
+    assert L.cmp_split_k(ctx, 0, 512, 512, 8192, C.byref(n)) == pa.CMP_EINVAL
+    assert L.cmp_split_k(ctx, 0, -1, 512, 8192, C.byref(n)) == pa.CMP_EINVAL
+    assert L.cmp_split_k(ctx, 0, 512, 512, 8192, None) == pa.CMP_EINVAL
+    # a host variant reports no split
+    st, vid = c.variant_register("gemm", "host_fake", pa.CMP_TARGET_HOST, _noop, 1e-5)
+    assert st == pa.CMP_OK
+    assert L.cmp_split_k(ctx, vid, 512, 512, 8192, C.byref(n)) == pa.CMP_OK and n.value == 1
+    # optional built-ins need a GPU context; unknown names and null pointers are refused
+    vid = C.c_int(-1)
+    assert L.cmp_register_builtin(ctx, b"fp6x3", C.byref(vid)) == pa.CMP_EUNSUPPORTED
+    assert L.cmp_register_builtin(ctx, None, C.byref(vid)) == pa.CMP_EINVAL
+    assert L.cmp_register_builtin(None, b"fp6x3", C.byref(vid)) == pa.CMP_EINVAL
+    # the MX FP6 quantisation entry needs a GPU context
+    assert L.cmp_quant_mx6(ctx, 4, 4, None, 4, 0, None, None, None, None, None) == pa.CMP_EUNSUPPORTED
+    c.close()

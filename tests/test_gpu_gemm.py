@@ -230,6 +230,16 @@ def test_nan_in_a_propagates(cx, name):
     assert np.all(np.isnan(C[3])) and np.all(np.isfinite(np.delete(C, 3, axis=0)))
 
 
+def test_optional_builtin_registration(cx):
+    import paper_2311_03543_amd as pa
+    assert cx.variant_find("fp6x3") == 4 and cx.variant_count() == 5
+    for name, st in (("fp6x3", pa.CMP_EDUP), ("fp4x9", pa.CMP_ENOTFOUND)):
+        with pytest.raises(pa.ComparError) as e:
+            cx.register_builtin(name)
+        assert e.value.status == st
+    assert cx.variant_count() == 5
+
+
 # ---- split-K: few output tiles over a long K ----------------------------------------
 
 MFMA_VARIANTS = ["bf16x3", "fp8r", "bf16", "fp6x3"]
