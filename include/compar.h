@@ -200,7 +200,9 @@ int cmp_set_flags(cmp_ctx *ctx, uint32_t flags);
  * model choose per call; splits >= 1 forces that many slices, at most 64 and
  * at most one per 64-byte K block, every slice non-empty (1 disables split-K).
  * This is a tuning and testing knob: the sum order, hence the rounding, of a
- * result depends on the slice count. */
+ * result depends on the slice count, and a forced count applies to every
+ * shape, so the workspace grows by splits x M x N floats (CMP_ENOMEM if that
+ * allocation fails). */
 int cmp_set_split_k(cmp_ctx *ctx, int splits);
 /* Register an optional built-in variant of "gemm" by name; "fp6x3" is the only
  * one.  It takes the next free id (*id, may be NULL).  CMP_EDUP if already
