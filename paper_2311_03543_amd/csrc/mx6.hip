@@ -33,32 +33,33 @@ __device__ __forceinline__ int mx6_scale_exp(float amax) {
 }
 
 // Round-to-nearest-even onto the E2M3 grid for |s| <= 7.5 (which the block
-// scale guarantees).  The grid spacing is 1/8 below 2, 1/4 on [2, 4) and 1/2
-// on [4, 8), so the rounded magnitude is rint(|s| k) / k with k = 8, 4, 2
-// (every step exact); v_rndne rounds halves to even, which on each of these
-// grids is the even code.  Returns the 6-bit code; `val` gets the value.
+// scale guarantees), without branches.  Below 1 the grid is k/8 (the
+// subnormal codes 0..7, and k = 8 is the code of 1.0): k = rint(8 |s|), and
+// v_rndne rounds halves to even.  From 1 up the grid keeps 3 fraction bits:
+// rounding |s|'s own bits at bit 20 to nearest even (add 0x7ffff plus the
+// kept last bit, clear the rest) gives the value, and its exponent and top
+// fraction bits are the code, (E - 126) << 3 | f.  Returns the 6-bit code;
+// `val` gets the value.
 __device__ __forceinline__ uint32_t e2m3_code(float s, float& val) {
     const float a = fabsf(s);
-    const float k = a < 2.f ? 8.f : (a < 4.f ? 4.f : 2.f);
-    const float ik = a < 2.f ? 0.125f : (a < 4.f ? 0.25f : 0.5f);
-    const float v = __builtin_rintf(a * k) * ik;
-    uint32_t code;
-    if (v < 1.f) {
-        code = (uint32_t)(v * 8.f);                           // subnormal: v = f / 8
-    } else {
-        const uint32_t u = __builtin_bit_cast(uint32_t, v);    // v = (1 + f/8) 2^(E-1)
-        code = (((u >> 23) - 126u) << 3) | ((u >> 20) & 7u);
-    }
+    const float k = __builtin_rintf(a * 8.f);
+    const uint32_t u = __builtin_bit_cast(uint32_t, a);
+    const uint32_t ur = (u + 0x7ffffu + ((u >> 20) & 1u)) & 0xfff00000u;
+    const bool sub = a < 1.f;
+    const uint32_t code = sub ? (uint32_t)k : (ur >> 20) - (126u << 3);
+    const float v = sub ? k * 0.125f : __builtin_bit_cast(float, ur);
     val = __builtin_copysignf(v, s);
     return ((__builtin_bit_cast(uint32_t, s) >> 31) << 5) | code;
 }
 
 // Residual of one value against its code value qv (scaled domain s = x 2^e):
-// s - qv is exact and scaling back rounds once; a zero code leaves x - qv.
+// s - qv is exact and scaling back rounds once; a zero code leaves x - qv
+// (s may have lost bits below the FP32 range).  Both are formed, one kept.
 __device__ __forceinline__ float mx6_resid(float x, float s, float qv, int e) {
-    return qv == 0.f ? x - qv : __builtin_ldexpf(s - qv, -e);
+    const float scaled = __builtin_ldexpf(s - qv, -e);
+    const float direct = x - qv;
+    return qv == 0.f ? direct : scaled;
 }
-
 
 // ---------------------------------------------------------------------------
 // Rows of X (blocks along X's rows, K = cols): eight lanes per block, four
@@ -195,9 +196,15 @@ __global__ __launch_bounds__(256) void quant_mx6_cols_kernel(
             float v[32];
             float amax = 0.f;
             bool bad = false;
+            // out-of-range lanes load X[0] (in bounds) and keep 0: no branch per load
 #pragma unroll
             for (int j = 0; j < 32; ++j) {
-                v[j] = (n < N && k0 + j < K) ? X[(k0 + j) * ldx + n] : 0.f;
+                const bool in = n < N && k0 + j < K;
+                const float x = X[in ? (k0 + j) * ldx + n : 0];
+                v[j] = in ? x : 0.f;
+            }
+#pragma unroll
+            for (int j = 0; j < 32; ++j) {
                 if (!__builtin_isfinite(v[j])) bad = true;
                 else amax = fmaxf(amax, fabsf(v[j]));
             }
