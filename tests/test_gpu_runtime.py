@@ -82,6 +82,34 @@ def test_verify_mode_probe_matches_oracle(cx):
     assert oracle.relfro(C, oracle.gemm(A, B, 1.0, 0.5, C0)) <= BOUNDS[chosen]
 
 
+@pytest.mark.parametrize("name", ["bf16x3", "fp8r", "bf16"])
+def test_verify_mode_on_a_split_k_call(name):
+    """Verify mode over a split-K launch (4 output tiles over K = 4000): the FP64 probe sees the
+    reduced C, agrees with the oracle's probe of the same C, and no fallback is taken."""
+    import paper_2311_03543_amd as pa
+    c = pa.Compar(0)
+    try:
+        M, N, K = 300, 260, 4000
+        vid = c.variant_find(name)
+        assert c.split_k(vid, M, N, K) > 1
+        A, B = synth.gemm_operands(M, N, K, seed=24)
+        C0 = synth.normal_matrix(M, N, 25)
+        dC = dev(C0)
+        c.force_variant(vid)
+        c.set_flags(pa.CMP_FLAG_VERIFY)
+        say(f"  verify-mode split-K cmp_gemm {name} beta=0.5")
+        chosen = c.gemm(dev(A), dev(B), dC, alpha=1.0, beta=0.5, tol=1e-2)
+        est, fallbacks = c.last_verify()
+        C = host(dC)
+        assert chosen == vid and fallbacks == 0
+        x = oracle.rademacher_splitmix(N, 0x5EED)            # the context's first call
+        ref = oracle.freivalds(A, B, C, x, alpha=1.0, beta=0.5, C0=C0)
+        assert abs(est - ref) <= 1e-9 * max(ref, 1e-300), (est, ref)
+        assert oracle.relfro(C, oracle.gemm(A, B, 1.0, 0.5, C0)) <= BOUNDS[vid]
+    finally:
+        c.close()
+
+
 def test_injected_failure_falls_back(monkeypatch):
     """COMPAR_FAULT=bf16:1 makes every bf16 call fail; cmp_gemm must fall back once to the
     best other admissible variant (fp8r by the recorded times) and still meet tol."""
