@@ -2,8 +2,9 @@
 selector's regret against exhaustive timing, on one MI355X.
 
 Phases (all on cuda:0, synthetic seeded inputs, no files read):
-  1. time-and-record: every variant (the four default built-ins and the optional
-     MX fp6 variant, unless --no-fp6) on the square sweep N in {128, ..., 8192}
+  1. time-and-record: every variant (the four default built-ins, the optional
+     MX fp6 variant unless --no-fp6, and the host CPU variant up to --host-max)
+     on the square sweep N in {128, ..., 8192}
      (normal(0,1) operands, 3 warm-up + 20 timed reps, median) -> history;
   2. timed region: `--steps` steps after `--warmup` steps; one step is one
      cmp_gemm per tolerance class {1e-5, 1e-3, 1e-2} at M = N = K = `--size`
@@ -145,6 +146,8 @@ def main():
                     help="sustained bf16 run while sampling board power and GFX clocks (0 = skip)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp6", action="store_true", help="leave the optional MX fp6 variant unregistered")
+    ap.add_argument("--host-max", type=int, default=1024,
+                    help="time the host CPU variant on sweep sizes up to this N (0: leave it unregistered)")
     ap.add_argument("--sweep", type=str, default="",
                     help="comma-separated square sizes to time and record (default: 128..--size)")
     args = ap.parse_args()
@@ -169,6 +172,10 @@ def main():
     if not args.no_fp6:
         assert cx.register_builtin("fp6x3") == len(names)
         names.append("fp6x3")
+    # the host CPU variant: timed (and so selectable) up to --host-max only
+    if args.host_max > 0:
+        assert cx.register_builtin("host_f32") == len(names)
+        names.append("host_f32")
 
     # ---- 1. time and record: square sweep -----------------------------------------
     sweep = {}
@@ -185,6 +192,8 @@ def main():
         dC = torch.zeros((s, s), dtype=torch.float32, device="cuda")
         row = {}
         for vid, name in enumerate(names):
+            if name == "host_f32" and s > args.host_max:
+                continue
             med, mn, mean = cx.time_variant(vid, dA, dB, dC, warmup=3, reps=args.reps)
             cx.history_add(s, s, s, vid, args.reps, med, mn, mean)
             row[name] = dict(median_ms=med, min_ms=mn, mean_ms=mean, tflops=2.0 * s ** 3 / (med * 1e-3) / 1e12)

@@ -22,12 +22,14 @@
  *                    products with per-128x128-tile scales  stated bound 1e-3
  *   id 3 "bf16"      bf16 operands, one MFMA product        stated bound 1e-2
  *
- * and one optional built-in that cmp_register_builtin adds on request:
+ * and two optional built-ins that cmp_register_builtin adds on request:
  *
  *   "fp6x3"          OCP MX FP6 (E2M3) with one E8M0 scale
  *                    per 32 K values and one residual level,
  *                    three products hi.hi + hi.lo + lo.hi on
  *                    the scaled MFMA at the FP6 rate        stated bound 1e-2
+ *   "host_f32"       FP32 GEMM on the host CPU (the paper's
+ *                    CPU codelet beside the GPU ones)      stated bound 1e-5
  *
  * "Stated bound" is the relative Frobenius error ||C - C_exact||_F/||C_exact||_F
  * the variant is registered with; a call with tolerance tol may only run
@@ -204,11 +206,16 @@ int cmp_set_flags(cmp_ctx *ctx, uint32_t flags);
  * shape, so the workspace grows by splits x M x N floats (CMP_ENOMEM if that
  * allocation fails). */
 int cmp_set_split_k(cmp_ctx *ctx, int splits);
-/* Register an optional built-in variant of "gemm" by name; "fp6x3" is the only
- * one.  It takes the next free id (*id, may be NULL).  CMP_EDUP if already
- * registered, CMP_ENOTFOUND for an unknown name.  The learned selector's
- * network predicts the four default built-ins; for other variants it uses the
- * history's nearest timed shape. */
+/* Register an optional built-in variant of "gemm" by name: "fp6x3" (GPU
+ * contexts only) or "host_f32" (CMP_TARGET_HOST).  It takes the next free id
+ * (*id, may be NULL).  CMP_EDUP if already registered, CMP_ENOTFOUND for an
+ * unknown name.  "host_f32" in a GPU context copies A, B (and C when
+ * beta != 0) from the device after the work queued on `stream`, multiplies on
+ * up to 16 host threads and copies C back before the call returns
+ * (synchronous); in a host-only context the cmp_gemm_args pointers are host
+ * memory and are used in place.  The learned selector's network predicts the
+ * four default built-ins; for other variants it uses the history's nearest
+ * timed shape. */
 int cmp_register_builtin(cmp_ctx *ctx, const char *name, int *id);
 /* Slice count a call of built-in variant `id` of "gemm" would use for an
  * M x N x K product under the current setting (1 for f32_simt and for

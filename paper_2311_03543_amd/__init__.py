@@ -21,7 +21,7 @@ from ._lib import (CMP_EDUP, CMP_EHIP, CMP_EINVAL, CMP_ENODATA, CMP_ENOTFOUND,  
 GEMM = b"gemm"
 BUILTIN_VARIANTS = ("f32_simt", "bf16x3", "fp8r", "bf16")
 # optional built-ins, registered on request (Compar.register_builtin)
-OPTIONAL_VARIANTS = ("fp6x3",)
+OPTIONAL_VARIANTS = ("fp6x3", "host_f32")
 
 
 def library():
@@ -158,7 +158,7 @@ class Compar:
         self._check(self.L.cmp_set_flags(self.ctx, flags))
 
     def register_builtin(self, name: str) -> int:
-        """Register an optional built-in variant ("fp6x3"); returns its id."""
+        """Register an optional built-in variant ("fp6x3" or "host_f32"); returns its id."""
         vid = C.c_int(-1)
         self._check(self.L.cmp_register_builtin(self.ctx, name.encode(), C.byref(vid)))
         return vid.value

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcompar.so")
 SOURCES = ["runtime.cpp", "gemm_f32_simt.hip", "gemm_mfma.hip", "prepass.hip", "mx6.hip", "freivalds.hip",
-           "mlp.hip"]
+           "mlp.hip", "host_gemm.cpp"]
 ARCH = "gfx950"
 
 

@@ -9,6 +9,12 @@
 
 namespace cmp {
 
+// ---- FP32 GEMM on the host CPU (host_gemm.cpp) ------------------------------
+// C = alpha * A * B + beta * C over host arrays (beta == 0: C not read), row
+// tiles over at most max_threads threads.  Synchronous.
+void host_gemm_f32(int64_t M, int64_t N, int64_t K, float alpha, const float* A, int64_t lda,
+                   const float* B, int64_t ldb, float beta, float* C, int64_t ldc, int max_threads);
+
 // ---- FP32 SIMT GEMM (vector-ALU FMA, LDS-staged tiles) -------------------
 hipError_t launch_gemm_f32_simt(int64_t M, int64_t N, int64_t K, float alpha,
                                 const float* A, int64_t lda, const float* B, int64_t ldb,

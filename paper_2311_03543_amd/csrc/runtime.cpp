@@ -14,6 +14,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
+#include <thread>
 #include <map>
 #include <sstream>
 #include <string>
@@ -508,6 +509,40 @@ int v_fp6x3(const void* args, void* ws, size_t, void* stream, void* user) {
             return CMP_EHIP;
     }
     return finish_split(c, a, splits, partial, s);
+}
+
+// The optional host variant: FP32 GEMM on the CPU.  In a GPU context the
+// operands are device memory: A, B (and C when beta != 0) are copied to host
+// buffers after the work already queued on the stream, multiplied, and C is
+// copied back before the call returns (the call is synchronous).  In a
+// host-only context the pointers are host memory and are used in place.
+int v_host_f32(const void* args, void*, size_t, void* stream, void* user) {
+    auto* c = (cmp_ctx*)user;
+    auto a = (const cmp_gemm_args*)args;
+    const int threads = (int)std::min<unsigned>(std::max(1u, std::thread::hardware_concurrency()), 16u);
+    if (a->M == 0 || a->N == 0) return CMP_OK;
+    if (!c->gpu) {
+        cmp::host_gemm_f32(a->M, a->N, a->K, a->alpha, a->A, a->lda, a->B, a->ldb, a->beta, a->C, a->ldc,
+                           threads);
+        return CMP_OK;
+    }
+    auto s = (hipStream_t)stream;
+    int st;
+    if (gemm_trivial(a, s, &st)) return st;
+    std::vector<float> hA((size_t)a->M * a->K), hB((size_t)a->K * a->N), hC((size_t)a->M * a->N);
+    const size_t f = sizeof(float);
+    if (hipMemcpy2DAsync(hA.data(), a->K * f, a->A, a->lda * f, a->K * f, a->M, hipMemcpyDeviceToHost, s) ||
+        hipMemcpy2DAsync(hB.data(), a->N * f, a->B, a->ldb * f, a->N * f, a->K, hipMemcpyDeviceToHost, s) ||
+        (a->beta != 0.f &&
+         hipMemcpy2DAsync(hC.data(), a->N * f, a->C, a->ldc * f, a->N * f, a->M, hipMemcpyDeviceToHost, s)) ||
+        hipStreamSynchronize(s))
+        return CMP_EHIP;
+    cmp::host_gemm_f32(a->M, a->N, a->K, a->alpha, hA.data(), a->K, hB.data(), a->N, a->beta, hC.data(), a->N,
+                       threads);
+    if (hipMemcpy2DAsync(a->C, a->ldc * f, hC.data(), a->N * f, a->N * f, a->M, hipMemcpyHostToDevice, s) ||
+        hipStreamSynchronize(s))
+        return CMP_EHIP;
+    return CMP_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -1168,11 +1203,16 @@ CMP_API int cmp_set_flags(cmp_ctx* c, uint32_t flags) {
 
 CMP_API int cmp_register_builtin(cmp_ctx* c, const char* name, int* id) {
     if (!c || !name) return CMP_EINVAL;
-    if (!c->gpu) return fail(c, CMP_EUNSUPPORTED, "built-in variants need a GPU context");
-    if (std::strcmp(name, "fp6x3") != 0) return fail(c, CMP_ENOTFOUND, "no optional built-in named %s", name);
-    int vid = -1;
-    const int st = register_variant(c, kGemm, "fp6x3", CMP_TARGET_HIP, 0, nullptr, v_fp6x3, ws_fp6x3, 1e-2,
-                                    c, &vid);
+    int vid = -1, st;
+    if (std::strcmp(name, "host_f32") == 0) {
+        st = register_variant(c, kGemm, "host_f32", CMP_TARGET_HOST, 0, nullptr, v_host_f32, ws_none, 1e-5, c,
+                              &vid);
+    } else if (std::strcmp(name, "fp6x3") == 0) {
+        if (!c->gpu) return fail(c, CMP_EUNSUPPORTED, "fp6x3 needs a GPU context");
+        st = register_variant(c, kGemm, "fp6x3", CMP_TARGET_HIP, 0, nullptr, v_fp6x3, ws_fp6x3, 1e-2, c, &vid);
+    } else {
+        return fail(c, CMP_ENOTFOUND, "no optional built-in named %s", name);
+    }
     if (st) return st;
     if (id) *id = vid;
     return CMP_OK;

@@ -320,9 +320,12 @@ def test_split_k_and_optional_builtin_argument_checks():
     st, vid = c.variant_register("gemm", "host_fake", pa.CMP_TARGET_HOST, _noop, 1e-5)
     assert st == pa.CMP_OK
     assert L.cmp_split_k(ctx, vid, 512, 512, 8192, C.byref(n)) == pa.CMP_OK and n.value == 1
-    # optional built-ins need a GPU context; unknown names and null pointers are refused
+    # fp6x3 needs a GPU context, host_f32 does not; unknown names and null pointers are refused
     vid = C.c_int(-1)
     assert L.cmp_register_builtin(ctx, b"fp6x3", C.byref(vid)) == pa.CMP_EUNSUPPORTED
+    assert L.cmp_register_builtin(ctx, b"host_f32", C.byref(vid)) == pa.CMP_OK and vid.value >= 0
+    assert L.cmp_register_builtin(ctx, b"host_f32", C.byref(vid)) == pa.CMP_EDUP
+    assert L.cmp_register_builtin(ctx, b"fp4", C.byref(vid)) == pa.CMP_ENOTFOUND
     assert L.cmp_register_builtin(ctx, None, C.byref(vid)) == pa.CMP_EINVAL
     assert L.cmp_register_builtin(None, b"fp6x3", C.byref(vid)) == pa.CMP_EINVAL
     # the MX FP6 quantisation entry needs a GPU context
