@@ -139,6 +139,8 @@ struct cmp_ctx {
     void* ws = nullptr;
     size_t ws_bytes = 0;
     void* vws = nullptr;     // verify-mode workspace (C0 copy, probe vector, partial sums)
+    void* hbuf = nullptr;    // pinned host staging of the host variant (A | B | C)
+    size_t hbuf_bytes = 0;
     size_t vws_bytes = 0;
     float* mlp_dev = nullptr;  // params | m | v | X | Y | loss | grad | infer io
     hipStream_t side = nullptr;
@@ -529,19 +531,37 @@ int v_host_f32(const void* args, void*, size_t, void* stream, void* user) {
     auto s = (hipStream_t)stream;
     int st;
     if (gemm_trivial(a, s, &st)) return st;
-    std::vector<float> hA((size_t)a->M * a->K), hB((size_t)a->K * a->N), hC((size_t)a->M * a->N);
+    // pinned staging, grown on demand: A (M x K) | B (K x N) | C (M x N), tight
+    const size_t na = (size_t)a->M * a->K, nb = (size_t)a->K * a->N, nc = (size_t)a->M * a->N;
+    const size_t need = (na + nb + nc) * sizeof(float);
+    if (need > c->hbuf_bytes) {
+        if (c->hbuf && hipStreamSynchronize(s) == hipSuccess) (void)hipHostFree(c->hbuf);
+        c->hbuf = nullptr;
+        c->hbuf_bytes = 0;
+        if (hipHostMalloc(&c->hbuf, need, hipHostMallocDefault) != hipSuccess) {
+            c->hbuf = nullptr;
+            (void)hipGetLastError();
+            return fail(c, CMP_ENOMEM, "pinned host staging of %zu bytes failed", need);
+        }
+        c->hbuf_bytes = need;
+    }
+    float* hA = (float*)c->hbuf;
+    float* hB = hA + na;
+    float* hC = hB + nb;
     const size_t f = sizeof(float);
-    if (hipMemcpy2DAsync(hA.data(), a->K * f, a->A, a->lda * f, a->K * f, a->M, hipMemcpyDeviceToHost, s) ||
-        hipMemcpy2DAsync(hB.data(), a->N * f, a->B, a->ldb * f, a->N * f, a->K, hipMemcpyDeviceToHost, s) ||
-        (a->beta != 0.f &&
-         hipMemcpy2DAsync(hC.data(), a->N * f, a->C, a->ldc * f, a->N * f, a->M, hipMemcpyDeviceToHost, s)) ||
-        hipStreamSynchronize(s))
+    // one linear copy when the rows are tight, a pitched copy otherwise
+    auto get = [&](float* dst, const float* src, int64_t rows, int64_t cols, int64_t ld) {
+        return ld == cols ? hipMemcpyAsync(dst, src, (size_t)rows * cols * f, hipMemcpyDeviceToHost, s)
+                          : hipMemcpy2DAsync(dst, cols * f, src, ld * f, cols * f, rows, hipMemcpyDeviceToHost, s);
+    };
+    if (get(hA, a->A, a->M, a->K, a->lda) || get(hB, a->B, a->K, a->N, a->ldb) ||
+        (a->beta != 0.f && get(hC, a->C, a->M, a->N, a->ldc)) || hipStreamSynchronize(s))
         return CMP_EHIP;
-    cmp::host_gemm_f32(a->M, a->N, a->K, a->alpha, hA.data(), a->K, hB.data(), a->N, a->beta, hC.data(), a->N,
-                       threads);
-    if (hipMemcpy2DAsync(a->C, a->ldc * f, hC.data(), a->N * f, a->N * f, a->M, hipMemcpyHostToDevice, s) ||
-        hipStreamSynchronize(s))
-        return CMP_EHIP;
+    cmp::host_gemm_f32(a->M, a->N, a->K, a->alpha, hA, a->K, hB, a->N, a->beta, hC, a->N, threads);
+    const hipError_t e = a->ldc == a->N
+        ? hipMemcpyAsync(a->C, hC, nc * f, hipMemcpyHostToDevice, s)
+        : hipMemcpy2DAsync(a->C, a->ldc * f, hC, a->N * f, a->N * f, a->M, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess || hipStreamSynchronize(s) != hipSuccess) return CMP_EHIP;
     return CMP_OK;
 }
 
@@ -1088,6 +1108,7 @@ CMP_API int cmp_terminate(cmp_ctx* c) {
         (void)hipDeviceSynchronize();
         if (c->ws) (void)hipFree(c->ws);
         if (c->vws) (void)hipFree(c->vws);
+        if (c->hbuf) (void)hipHostFree(c->hbuf);
         if (c->mlp_dev) (void)hipFree(c->mlp_dev);
         for (auto& k : c->kpending) {
             (void)hipEventDestroy(k.a);
