@@ -110,6 +110,36 @@ def test_verify_mode_on_a_split_k_call(name):
         c.close()
 
 
+def test_mlp_selector_estimates_optional_variants_from_history():
+    """With the learned selector, the four default variants are predicted by the network and any
+    other variant by the ln(us) of its nearest timed history shape; the choice is the argmin over
+    both, admissible variants only."""
+    import math
+    import paper_2311_03543_amd as pa
+    c = pa.Compar(0)
+    try:
+        f6, hv = c.register_builtin("fp6x3"), c.register_builtin("host_f32")
+        assert (f6, hv) == (4, 5)
+        p = np.zeros(synth.mlp_param_count(), np.float32)
+        p[-4:] = [3.0, 2.0, 1.0, 0.5]                       # constant ln(us) per default variant
+        c.mlp_set_params(p)
+        c.mlp_set_norm(np.zeros(4), np.ones(4), np.zeros(4), np.ones(4))
+        c.selector_set(pa.CMP_SEL_MLP)
+        ms = lambda ln_us: math.exp(ln_us) / 1000.0
+        c.history_add(1024, 1024, 1024, f6, 1, ms(0.2))
+        c.history_add(1024, 1024, 1024, hv, 1, ms(0.3))
+        c.history_add(64, 64, 64, hv, 1, ms(9.0))           # farther from the query below
+        q = (1000, 1000, 1000)
+        assert c.select(*q, 1e-2) == f6                     # 0.2 beats 0.5 (bf16) and 0.3
+        assert c.select(*q, 1e-3) == hv                     # fp6x3 inadmissible: 0.3 beats 1.0
+        assert c.select(*q, 1e-5) == hv                     # 0.3 beats 2.0 (bf16x3)
+        c.history_add(1024, 1024, 1024, hv, 1, ms(5.0))     # the later record of a shape counts
+        assert c.select(*q, 1e-5) == 1 and c.select(*q, 1e-3) == 2
+        assert c.select(70, 70, 70, 1e-5) == 1              # nearest host record: 9.0
+    finally:
+        c.close()
+
+
 def test_injected_failure_falls_back(monkeypatch):
     """COMPAR_FAULT=bf16:1 makes every bf16 call fail; cmp_gemm must fall back once to the
     best other admissible variant (fp8r by the recorded times) and still meet tol."""
