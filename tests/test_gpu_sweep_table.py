@@ -13,8 +13,8 @@ import synth
 from gpu_util import dev, host, say
 
 pytestmark = pytest.mark.gpu
-VARIANTS = ["f32_simt", "bf16x3", "fp8r", "bf16"]
-BOUND = {"f32_simt": 1e-5, "bf16x3": 1e-5, "fp8r": 1e-3, "bf16": 1e-2}
+VARIANTS = ["f32_simt", "bf16x3", "fp8r", "bf16", "fp6x3"]
+BOUND = {"f32_simt": 1e-5, "bf16x3": 1e-5, "fp8r": 1e-3, "bf16": 1e-2, "fp6x3": 1e-2}
 
 
 def _errors(cx, A, B):
@@ -32,6 +32,7 @@ def _errors(cx, A, B):
 def test_error_table():
     import paper_2311_03543_amd as pa
     cx = pa.Compar(0)
+    cx.register_builtin("fp6x3")
     rows = []
     try:
         for n in synth.square_sweep_sizes():
