@@ -48,6 +48,11 @@
  *     features) are read or written during the call only.
  *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
  *     GEMM calls are asynchronous on that stream unless stated otherwise.
+ *     After one call of a shape on a context (which sizes the workspace and
+ *     records the selection), further calls of that shape with the built-in
+ *     GPU variants only enqueue kernels and stream/event waits, so they can be
+ *     captured into a graph (stream capture) and replayed; verify mode and the
+ *     host variant synchronise and cannot.
  *   - A cmp_ctx is not thread-safe: use one context per host thread.
  *   - Name strings are copied on registration.
  */

@@ -1,0 +1,55 @@
+"""cmp_gemm captured into a graph: after one eager call of the shape (which sizes the workspace
+and fills the decision cache), the selected variant's launches — pre-passes on the caller's and
+the auxiliary stream, the GEMM, the split-K reduction — are recorded by a stream capture and
+replayed.  Every replay follows eager work that changes the operands, and is checked against
+the FP64 oracle on the operands it saw."""
+import pytest
+
+import oracle
+import synth
+from gpu_util import host, say
+
+pytestmark = pytest.mark.gpu
+BOUND = {"f32_simt": 1e-5, "bf16x3": 1e-5, "fp8r": 1e-3, "bf16": 1e-2, "fp6x3": 1e-2}
+
+
+@pytest.mark.parametrize("name", list(BOUND))
+@pytest.mark.parametrize("M,N,K", [(512, 384, 1000), (300, 260, 4000)])   # the second splits K
+def test_captured_gemm_replays(name, M, N, K):
+    import torch
+    import paper_2311_03543_amd as pa
+    cx = pa.Compar(0)
+    try:
+        cx.register_builtin("fp6x3")
+        cx.force_variant(cx.variant_find(name))
+        tol = BOUND[name]
+        A0, B0 = synth.gemm_operands(M, N, K, seed=M + K)
+        dA = torch.from_numpy(A0).cuda()
+        dB = torch.from_numpy(B0).cuda()
+        dC = torch.zeros((M, N), device="cuda")
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            say(f"  eager warm-up {name} M={M} N={N} K={K}")
+            vid = cx.gemm(dA, dB, dC, tol=tol, stream=s)
+            s.synchronize()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=s):
+                cx.gemm(dA, dB, dC, tol=tol, stream=s)
+        torch.cuda.synchronize()
+        assert cx.variant_info(vid)[0] == name
+        for r in range(3):
+            # eager work between replays: new operand values in place
+            dA.mul_(-0.5 if r % 2 else 1.5)
+            dB.add_(0.25)
+            dC.zero_()
+            torch.cuda.synchronize()
+            say(f"  replay {r} of {name}")
+            g.replay()
+            torch.cuda.synchronize()
+            A, B = host(dA), host(dB)
+            err = oracle.relfro(host(dC), oracle.gemm(A, B))
+            assert err <= tol, (name, r, err)
+        del g
+    finally:
+        cx.close()
