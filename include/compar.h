@@ -346,6 +346,44 @@ int cmp_quant_mx6(cmp_ctx *ctx, int64_t rows, int64_t cols, const float *X, int6
                   int transpose, uint8_t *q, uint8_t *qscale, uint8_t *rq, uint8_t *rscale,
                   void *stream);
 
+/* Operand images of a built-in pre-passed variant (bf16, bf16x3, fp8r,
+ * fp6x3), exposed so that the pre-pass a variant runs on its hot path can be
+ * checked bit for bit: cmp_prepass_images launches exactly the kernels, with
+ * the same launch configuration, that the variant launches on A and B before
+ * its GEMM kernel, but writes the images to `out` instead of the library's
+ * workspace.  The images are the variant's panel images (bf16, E4M3, MX FP6
+ * encodings as in cmp_split_bf16, cmp_quant_fp8, cmp_quant_mx6, of A and of
+ * B transposed), zero-padded to Mp x Kp and Np x Kp:
+ *   bf16 / FP8 codes: element (row, k) of an image with Kb bytes of K per row
+ *     (Kb = 2 Kp or Kp) is at byte b(row, kbyte) with kbyte = 2 k or k, where
+ *     b = ((row / 256) * (Kb / 64) + kbyte / 64) * 16384 + (row % 256) * 64
+ *         + (((kbyte / 16) % 4) ^ ((row % 256) / 4 % 4)) * 16 + kbyte % 16;
+ *   FP8 tile scales: one E8M0 byte per 128 x 128 tile, tile-row-major
+ *     (Mp / 128) x (Kp / 128) (A) or (Np / 128) x (Kp / 128) (B^T);
+ *   MX FP6: per 256-row by 64-value K block, a 12 KiB code block (48 bytes
+ *     per row: [half 0 bytes 0-15 | half 1 bytes 0-15 | half 0 bytes 16-23 |
+ *     half 1 bytes 16-23], the 32 codes of a half packed 6 bits each, code j
+ *     at bit 6 j) and a 1 KiB scale block (4 bytes per row: half 0 hi,
+ *     half 0 lo, half 1 hi, half 1 lo); block (rb, kb) is block rb * (Kp / 64)
+ *     + kb of its array.
+ * Image order (offset[i]): bf16: A hi, B^T hi; bf16x3: A hi, B^T hi, A lo,
+ * B^T lo; fp8r: A q, A r, B^T q, B^T r, then the tile scales of A q, A r,
+ * B^T q, B^T r; fp6x3: A hi, A lo, B^T hi, B^T lo, A scales, B^T scales.
+ * Unused entries have offset -1.  CMP_EUNSUPPORTED for a variant without a
+ * pre-pass; CMP_EINVAL for M, N or K < 1, null pointers, or out_bytes < total.
+ * alpha, beta and C of args are ignored.  Asynchronous on stream. */
+typedef struct cmp_image_layout {
+    int64_t Mp, Np, Kp;
+    int32_t count;          /* number of images */
+    int64_t offset[8];      /* byte offset of image i in `out` (-1: unused) */
+    int64_t bytes[8];       /* its size in bytes */
+    int64_t total;          /* bytes `out` must hold */
+} cmp_image_layout;
+int cmp_prepass_layout(cmp_ctx *ctx, int id, int64_t M, int64_t N, int64_t K,
+                       cmp_image_layout *layout);
+int cmp_prepass_images(cmp_ctx *ctx, int id, const cmp_gemm_args *args, void *out,
+                       size_t out_bytes, void *stream);
+
 /* ---- grouped launches: many GEMMs of uneven shapes ---------------------- */
 
 /* A plan runs `count` independent gemm problems (FP32 SIMT arithmetic, each

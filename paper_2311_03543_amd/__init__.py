@@ -315,6 +315,10 @@ class Compar:
     def freivalds(self, A, B, C_, probe, alpha=1.0, beta=0.0, C0=None, stream=None) -> float:
         import numpy as np
         a = gemm_args(A, B, C_, alpha, beta)
+        if C0 is not None:
+            p0, m0, n0, ld0 = _mat(C0, "C0")
+            if (m0, n0) != (a.M, a.N) or (a.M > 1 and ld0 != a.ldc):
+                raise ValueError("C0 must have C's shape and leading dimension")
         x = np.ascontiguousarray(probe, dtype=np.float64)
         est = C.c_double()
         self._check(self.L.cmp_freivalds(self.ctx, C.byref(a), None if C0 is None else C0.data_ptr(),
@@ -336,6 +340,28 @@ class Compar:
         px, r, c, ld = _mat(X, "X")
         self._check(self.L.cmp_quant_fp8(self.ctx, r, c, px, ld, q.data_ptr(), qscale.data_ptr(),
                                          rq.data_ptr(), rscale.data_ptr(), _stream_ptr(stream)))
+
+    def prepass_layout(self, vid: int, M: int, N: int, K: int) -> dict:
+        L = _lib.cmp_image_layout()
+        self._check(self.L.cmp_prepass_layout(self.ctx, vid, M, N, K, C.byref(L)))
+        return dict(Mp=L.Mp, Np=L.Np, Kp=L.Kp, offset=list(L.offset[:L.count]),
+                    bytes=list(L.bytes[:L.count]), total=L.total)
+
+    def prepass_images(self, vid: int, A, B, out, stream=None) -> dict:
+        """Run variant ``vid``'s own operand pre-pass on A and B into the uint8 device tensor
+        ``out``; returns the layout (offsets of the images in ``out``)."""
+        import torch
+        pa, M, K, lda = _mat(A, "A")
+        pb, K2, N, ldb = _mat(B, "B")
+        if K != K2:
+            raise ValueError("shape mismatch")
+        lay = self.prepass_layout(vid, M, N, K)
+        if out.dtype != torch.uint8 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous uint8 tensor")
+        a = cmp_gemm_args(M, N, K, lda, ldb, N, 1.0, 0.0, pa, pb, None)
+        self._check(self.L.cmp_prepass_images(self.ctx, vid, C.byref(a), out.data_ptr(), out.numel(),
+                                              _stream_ptr(stream)))
+        return lay
 
     def quant_mx6(self, X, q, qscale, rq, rscale, transpose=False, stream=None):
         px, r, c, ld = _mat(X, "X")

@@ -45,6 +45,11 @@ class cmp_gemm_args(C.Structure):
                 ("A", C.c_void_p), ("B", C.c_void_p), ("C", C.c_void_p)]
 
 
+class cmp_image_layout(C.Structure):
+    _fields_ = [("Mp", C.c_int64), ("Np", C.c_int64), ("Kp", C.c_int64), ("count", C.c_int32),
+                ("offset", C.c_int64 * 8), ("bytes", C.c_int64 * 8), ("total", C.c_int64)]
+
+
 class cmp_context(C.Structure):
     _fields_ = [("M", C.c_int64), ("N", C.c_int64), ("K", C.c_int64),
                 ("dtype", C.c_int32), ("tol", C.c_double)]
@@ -113,6 +118,8 @@ SIGNATURES = {
     "cmp_last_verify": (_I, [_P, _DP, _IP]),
     "cmp_split_bf16": (_I, [_P, _I64, _I64, _P, _I64, _P, _P, _P]),
     "cmp_quant_fp8": (_I, [_P, _I64, _I64, _P, _I64, _P, _P, _P, _P, _P]),
+    "cmp_prepass_layout": (_I, [_P, _I, _I64, _I64, _I64, C.POINTER(cmp_image_layout)]),
+    "cmp_prepass_images": (_I, [_P, _I, C.POINTER(cmp_gemm_args), _P, C.c_size_t, _P]),
     "cmp_grouped_config_count": (_I, []),
     "cmp_grouped_config_info": (_I, [_I, _IP, _IP, _IP]),
     "cmp_grouped_plan_create": (_I, [_P, _I, C.POINTER(cmp_gemm_args), _I, _I, _P, C.POINTER(_P)]),

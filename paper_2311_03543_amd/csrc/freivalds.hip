@@ -34,7 +34,8 @@ __global__ __launch_bounds__(256) void bx_kernel(int64_t K, int64_t N, const flo
 __global__ __launch_bounds__(256) void rows_kernel(int64_t M, int64_t N, int64_t K, float alpha,
                                                    const float* __restrict__ A, int64_t lda,
                                                    float beta, const float* __restrict__ C0,
-                                                   const float* __restrict__ C, int64_t ldc,
+                                                   int64_t ldc0, const float* __restrict__ C,
+                                                   int64_t ldc,
                                                    const double* __restrict__ x,
                                                    const double* __restrict__ y,
                                                    double* __restrict__ out) {
@@ -46,7 +47,7 @@ __global__ __launch_bounds__(256) void rows_kernel(int64_t M, int64_t N, int64_t
             for (int64_t k = lane; k < K; k += 64) za += (double)A[i * lda + k] * y[k];
         for (int64_t j = lane; j < N; j += 64) {
             w += (double)C[i * ldc + j] * x[j];
-            if (beta != 0.f) c0 += (double)C0[i * ldc + j] * x[j];
+            if (beta != 0.f) c0 += (double)C0[i * ldc0 + j] * x[j];
         }
         za = wave_sum(za);
         w = wave_sum(w);
@@ -84,15 +85,15 @@ unsigned waves_grid(int64_t rows) {
 
 hipError_t launch_freivalds(int64_t M, int64_t N, int64_t K, float alpha, const float* A,
                             int64_t lda, const float* B, int64_t ldb, float beta, const float* C0,
-                            const float* C, int64_t ldc, const double* x, double* ws, double* out,
-                            hipStream_t stream) {
+                            int64_t ldc0, const float* C, int64_t ldc, const double* x, double* ws,
+                            double* out, hipStream_t stream) {
     double* y = ws;
     hipLaunchKernelGGL(bx_kernel, dim3(waves_grid(K)), dim3(256), 0, stream,
                        (alpha != 0.f) ? K : (int64_t)0, N, B, ldb, x, y, out);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(rows_kernel, dim3(waves_grid(M)), dim3(256), 0, stream, M, N, K, alpha, A,
-                       lda, beta, C0, C, ldc, x, y, out);
+                       lda, beta, C0, ldc0, C, ldc, x, y, out);
     return hipGetLastError();
 }
 

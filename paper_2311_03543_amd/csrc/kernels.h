@@ -177,8 +177,8 @@ constexpr int kMx6CodeBlockBytes = 256 * 48, kMx6ScaleBlockBytes = 1024;
 // x: N doubles on the device; ws: at least (K + 2) doubles; out: 2 doubles (device).
 hipError_t launch_freivalds(int64_t M, int64_t N, int64_t K, float alpha, const float* A,
                             int64_t lda, const float* B, int64_t ldb, float beta,
-                            const float* C0, const float* C, int64_t ldc, const double* x,
-                            double* ws, double* out, hipStream_t stream);
+                            const float* C0, int64_t ldc0, const float* C, int64_t ldc,
+                            const double* x, double* ws, double* out, hipStream_t stream);
 // x[j] = +-1 from splitmix64(seed + j): the top bit set gives -1.
 hipError_t launch_rademacher(int64_t n, uint64_t seed, double* x, hipStream_t stream);
 

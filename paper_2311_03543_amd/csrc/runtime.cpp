@@ -239,19 +239,6 @@ int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
 size_t ws_none(const void*, void*) { return 0; }
 
-struct Bf16Layout {
-    int64_t Mp, Np, Kp;
-    size_t a_elems, b_elems;
-};
-Bf16Layout bf16_layout(const cmp_gemm_args* a) {
-    Bf16Layout L;
-    L.Mp = round_up(std::max<int64_t>(a->M, 1), cmp::kMfmaTileM);
-    L.Np = round_up(std::max<int64_t>(a->N, 1), cmp::kMfmaTileN);
-    L.Kp = round_up(std::max<int64_t>(a->K, 1), cmp::kBf16TileK);
-    L.a_elems = (size_t)L.Mp * L.Kp;
-    L.b_elems = (size_t)L.Np * L.Kp;
-    return L;
-}
 // Split-K count for the MFMA variants: the context's CU count decides when
 // the output tiles alone leave CUs idle.
 int cu_count(const void* user) {
@@ -273,63 +260,79 @@ int gemm_splits(const cmp_gemm_args* a, int64_t Kp_bytes, double step_ns, const 
 size_t partial_bytes(const cmp_gemm_args* a, int splits) {
     return splits > 1 ? (size_t)splits * a->M * a->N * sizeof(float) : 0;
 }
-size_t ws_bf16_terms(const cmp_gemm_args* a, int nterms, const void* user) {
-    auto L = bf16_layout(a);
-    const size_t img = (L.a_elems + L.b_elems) * 2 * (nterms > 1 ? 2 : 1);
-    return img + partial_bytes(a, gemm_splits(a, L.Kp * 2, nterms > 1 ? cmp::kStepNsBf16x3 : cmp::kStepNsBf16, user));
-}
-size_t ws_bf16(const void* args, void* user) {
-    return ws_bf16_terms((const cmp_gemm_args*)args, 1, user);
-}
-size_t ws_bf16x3(const void* args, void* user) {
-    return ws_bf16_terms((const cmp_gemm_args*)args, 3, user);
-}
 
-struct Fp8Layout {
-    int64_t Mp, Np, Kp;
-    size_t a_bytes, b_bytes, as_bytes, bs_bytes;
+// Operand images of the pre-passed (MFMA) variants.  Each keeps its images at
+// the front of its workspace in a fixed order, which is also the order
+// cmp_prepass_layout reports, followed by the split-K partial sums:
+//   bf16   : A hi | B^T hi                                   (bf16 panel images)
+//   bf16x3 : A hi | B^T hi | A lo | B^T lo                   (bf16 panel images)
+//   fp8r   : A q | A r | B^T q | B^T r | E8M0 tile scales of A q, A r, B^T q, B^T r
+//   fp6x3  : A hi | A lo | B^T hi | B^T lo | A scales | B^T scales (MX FP6 images)
+// Mp and Np round M and N up to the 256-row MFMA tile; Kp rounds K up to 64
+// (bf16, FP6) or 128 (FP8: whole 128 x 128 scale tiles).  Padding is zero.
+enum ImageKind { kImgNone = -1, kImgBf16 = 0, kImgBf16x3 = 1, kImgFp8r = 2, kImgFp6x3 = 3 };
+struct Images {
+    int64_t Mp = 0, Np = 0, Kp = 0;
+    int n = 0;
+    size_t off[8] = {}, bytes[8] = {};
+    size_t total = 0;  // bytes of all images (the split-K partials follow)
+    uint8_t* at(void* base, int i) const { return (uint8_t*)base + off[i]; }
 };
-Fp8Layout fp8_layout(const cmp_gemm_args* a) {
-    Fp8Layout L;
-    L.Mp = round_up(std::max<int64_t>(a->M, 1), cmp::kMfmaTileM);
-    L.Np = round_up(std::max<int64_t>(a->N, 1), cmp::kMfmaTileN);
-    L.Kp = round_up(std::max<int64_t>(a->K, 1), cmp::kFp8TileK);
-    L.a_bytes = (size_t)L.Mp * L.Kp;
-    L.b_bytes = (size_t)L.Np * L.Kp;
-    L.as_bytes = round_up((L.Mp / 128) * (L.Kp / 128), 256);
-    L.bs_bytes = round_up((L.Np / 128) * (L.Kp / 128), 256);
-    return L;
+Images images_of(int kind, int64_t M, int64_t N, int64_t K) {
+    Images I;
+    I.Mp = round_up(std::max<int64_t>(M, 1), cmp::kMfmaTileM);
+    I.Np = round_up(std::max<int64_t>(N, 1), cmp::kMfmaTileN);
+    std::vector<size_t> b;
+    if (kind == kImgBf16 || kind == kImgBf16x3) {
+        I.Kp = round_up(std::max<int64_t>(K, 1), cmp::kBf16TileK);
+        const size_t ab = (size_t)I.Mp * I.Kp * 2, bb = (size_t)I.Np * I.Kp * 2;
+        b = {ab, bb};
+        if (kind == kImgBf16x3) b.insert(b.end(), {ab, bb});
+    } else if (kind == kImgFp8r) {
+        I.Kp = round_up(std::max<int64_t>(K, 1), cmp::kFp8TileK);
+        const size_t ab = (size_t)I.Mp * I.Kp, bb = (size_t)I.Np * I.Kp;
+        const size_t as = (size_t)round_up((I.Mp / 128) * (I.Kp / 128), 256);
+        const size_t bs = (size_t)round_up((I.Np / 128) * (I.Kp / 128), 256);
+        b = {ab, ab, bb, bb, as, as, bs, bs};
+    } else {
+        I.Kp = round_up(std::max<int64_t>(K, 1), 64);
+        const size_t nkb = (size_t)(I.Kp / 64);
+        const size_t ac = (size_t)(I.Mp / 256) * nkb * cmp::kMx6CodeBlockBytes;
+        const size_t bc = (size_t)(I.Np / 256) * nkb * cmp::kMx6CodeBlockBytes;
+        const size_t as = (size_t)(I.Mp / 256) * nkb * cmp::kMx6ScaleBlockBytes;
+        const size_t bs = (size_t)(I.Np / 256) * nkb * cmp::kMx6ScaleBlockBytes;
+        b = {ac, ac, bc, bc, as, bs};
+    }
+    size_t o = 0;
+    for (size_t i = 0; i < b.size(); ++i) {
+        I.off[i] = o;
+        I.bytes[i] = b[i];
+        o += b[i];
+    }
+    I.n = (int)b.size();
+    I.total = o;
+    return I;
 }
-size_t ws_fp8r(const void* args, void* user) {
+// Split-K count of an image variant: K blocks of 64 bytes (bf16: 32 values,
+// FP8: 64 values, FP6: one 64-value block) priced at the variant's measured
+// time per K block.
+int image_splits(int kind, const cmp_gemm_args* a, const Images& I, const void* user) {
+    switch (kind) {
+        case kImgBf16: return gemm_splits(a, I.Kp * 2, cmp::kStepNsBf16, user);
+        case kImgBf16x3: return gemm_splits(a, I.Kp * 2, cmp::kStepNsBf16x3, user);
+        case kImgFp8r: return gemm_splits(a, I.Kp, cmp::kStepNsFp8r, user);
+        default: return gemm_splits(a, I.Kp, cmp::kStepNsFp6x3, user);
+    }
+}
+size_t ws_images(int kind, const void* args, const void* user) {
     auto a = (const cmp_gemm_args*)args;
-    auto L = fp8_layout(a);
-    return 2 * (L.a_bytes + L.b_bytes + L.as_bytes + L.bs_bytes) +
-           partial_bytes(a, gemm_splits(a, L.Kp, cmp::kStepNsFp8r, user));
+    const Images I = images_of(kind, a->M, a->N, a->K);
+    return I.total + partial_bytes(a, image_splits(kind, a, I, user));
 }
-
-// MX FP6 images: per operand hi and lo codes (3/4 byte per value) and one
-// scale array (4 bytes per row and 64-value K block).
-struct Fp6Layout {
-    int64_t Mp, Np, Kp;
-    size_t a_codes, b_codes, a_scales, b_scales;
-};
-Fp6Layout fp6_layout(const cmp_gemm_args* a) {
-    Fp6Layout L;
-    L.Mp = round_up(std::max<int64_t>(a->M, 1), cmp::kMfmaTileM);
-    L.Np = round_up(std::max<int64_t>(a->N, 1), cmp::kMfmaTileN);
-    L.Kp = round_up(std::max<int64_t>(a->K, 1), 64);
-    L.a_codes = (size_t)(L.Mp / 256) * (L.Kp / 64) * cmp::kMx6CodeBlockBytes;
-    L.b_codes = (size_t)(L.Np / 256) * (L.Kp / 64) * cmp::kMx6CodeBlockBytes;
-    L.a_scales = (size_t)(L.Mp / 256) * (L.Kp / 64) * cmp::kMx6ScaleBlockBytes;
-    L.b_scales = (size_t)(L.Np / 256) * (L.Kp / 64) * cmp::kMx6ScaleBlockBytes;
-    return L;
-}
-size_t ws_fp6x3(const void* args, void* user) {
-    auto a = (const cmp_gemm_args*)args;
-    auto L = fp6_layout(a);
-    return 2 * (L.a_codes + L.b_codes) + L.a_scales + L.b_scales +
-           partial_bytes(a, gemm_splits(a, L.Kp, cmp::kStepNsFp6x3, user));
-}
+size_t ws_bf16(const void* args, void* user) { return ws_images(kImgBf16, args, user); }
+size_t ws_bf16x3(const void* args, void* user) { return ws_images(kImgBf16x3, args, user); }
+size_t ws_fp8r(const void* args, void* user) { return ws_images(kImgFp8r, args, user); }
+size_t ws_fp6x3(const void* args, void* user) { return ws_images(kImgFp6x3, args, user); }
 
 // Degenerate shapes shared by every built-in: nothing to do, or C = beta * C.
 bool gemm_trivial(const cmp_gemm_args* a, hipStream_t s, int* st) {
@@ -388,129 +391,104 @@ int finish_split(cmp_ctx* c, const cmp_gemm_args* a, int splits, const float* pa
                : CMP_EHIP;
 }
 
-int run_bf16(cmp_ctx* c, const cmp_gemm_args* a, void* ws, hipStream_t s, int nterms) {
+// The pre-pass of an image variant: the kernels that turn A and B into the
+// variant's images at `base` (laid out by images_of).  The FP8 and FP6
+// quantisations of B run on the auxiliary stream beside those of A.
+int prepass(cmp_ctx* c, int kind, const cmp_gemm_args* a, const Images& I, void* base,
+            hipStream_t s) {
+    if (kind == kImgBf16 || kind == kImgBf16x3) {
+        const bool lo = kind == kImgBf16x3;
+        auto* Ah = (uint16_t*)I.at(base, 0);
+        auto* Bh = (uint16_t*)I.at(base, 1);
+        auto* Al = lo ? (uint16_t*)I.at(base, 2) : nullptr;
+        auto* Bl = lo ? (uint16_t*)I.at(base, 3) : nullptr;
+        {
+            KTimer kt(c, s, lo ? "split_a_bf16_hilo" : "split_a_bf16");
+            if (cmp::launch_split_a_bf16(a->M, a->K, a->A, a->lda, I.Mp, I.Kp, Ah, Al, s) != hipSuccess)
+                return CMP_EHIP;
+        }
+        KTimer kt(c, s, lo ? "split_bt_bf16_hilo" : "split_bt_bf16");
+        if (cmp::launch_split_bt_bf16(a->K, a->N, a->B, a->ldb, I.Np, I.Kp, Bh, Bl, s) != hipSuccess)
+            return CMP_EHIP;
+        return CMP_OK;
+    }
+    if (fork_aux(c, s) != hipSuccess) return CMP_EHIP;
+    if (kind == kImgFp8r) {
+        {
+            KTimer kt(c, c->aux, "quant_fp8_bt");
+            if (cmp::launch_quant_fp8(a->K, a->N, a->B, a->ldb, true, true, I.Np, I.Kp, I.at(base, 2),
+                                      I.at(base, 6), I.at(base, 3), I.at(base, 7), c->aux) != hipSuccess)
+                return CMP_EHIP;
+        }
+        KTimer kt(c, s, "quant_fp8_a");
+        if (cmp::launch_quant_fp8(a->M, a->K, a->A, a->lda, false, true, I.Mp, I.Kp, I.at(base, 0),
+                                  I.at(base, 4), I.at(base, 1), I.at(base, 5), s) != hipSuccess)
+            return CMP_EHIP;
+    } else {
+        {
+            KTimer kt(c, c->aux, "quant_mx6_bt");
+            if (cmp::launch_quant_mx6(a->K, a->N, a->B, a->ldb, true, true, I.Np, I.Kp, I.at(base, 2),
+                                      I.at(base, 5), I.at(base, 3), nullptr, c->aux) != hipSuccess)
+                return CMP_EHIP;
+        }
+        KTimer kt(c, s, "quant_mx6_a");
+        if (cmp::launch_quant_mx6(a->M, a->K, a->A, a->lda, false, true, I.Mp, I.Kp, I.at(base, 0),
+                                  I.at(base, 4), I.at(base, 1), nullptr, s) != hipSuccess)
+            return CMP_EHIP;
+    }
+    return join_aux(c, s) == hipSuccess ? CMP_OK : CMP_EHIP;
+}
+
+// An image variant: pre-pass, then its GEMM kernel over the images (with
+// split-K partials after the images when the cost model splits K).
+int run_images(cmp_ctx* c, int kind, const cmp_gemm_args* a, void* ws, hipStream_t s) {
     int st;
     if (gemm_trivial(a, s, &st)) return st;
-    auto L = bf16_layout(a);
-    auto* base = (uint16_t*)ws;
-    uint16_t* Ah = base;
-    uint16_t* Bh = Ah + L.a_elems;
-    uint16_t* Al = nterms > 1 ? Bh + L.b_elems : nullptr;
-    uint16_t* Bl = nterms > 1 ? Al + L.a_elems : nullptr;
-    const int splits =
-        gemm_splits(a, L.Kp * 2, nterms > 1 ? cmp::kStepNsBf16x3 : cmp::kStepNsBf16, c);
-    float* partial = (float*)(base + (L.a_elems + L.b_elems) * (nterms > 1 ? 2 : 1));
-    {
-        KTimer kt(c, s, nterms > 1 ? "split_a_bf16_hilo" : "split_a_bf16");
-        if (cmp::launch_split_a_bf16(a->M, a->K, a->A, a->lda, L.Mp, L.Kp, Ah, Al, s) != hipSuccess)
-            return CMP_EHIP;
+    const Images I = images_of(kind, a->M, a->N, a->K);
+    const int splits = image_splits(kind, a, I, c);
+    auto* partial = (float*)((uint8_t*)ws + I.total);
+    if ((st = prepass(c, kind, a, I, ws, s))) return st;
+    hipError_t e;
+    if (kind == kImgBf16 || kind == kImgBf16x3) {
+        const bool lo = kind == kImgBf16x3;
+        KTimer kt(c, s, lo ? "gemm_bf16x3_tn" : "gemm_bf16_tn");
+        e = cmp::launch_gemm_bf16_tn(a->M, a->N, I.Kp, lo ? 3 : 1, a->alpha, (uint16_t*)I.at(ws, 0),
+                                     lo ? (uint16_t*)I.at(ws, 2) : nullptr, (uint16_t*)I.at(ws, 1),
+                                     lo ? (uint16_t*)I.at(ws, 3) : nullptr, a->beta, a->C, a->ldc,
+                                     splits, partial, s);
+    } else if (kind == kImgFp8r) {
+        KTimer kt(c, s, "gemm_fp8r_tn");
+        e = cmp::launch_gemm_fp8r_tn(a->M, a->N, I.Kp, a->alpha, I.at(ws, 0), I.at(ws, 1), I.at(ws, 4),
+                                     I.at(ws, 5), I.at(ws, 2), I.at(ws, 3), I.at(ws, 6), I.at(ws, 7),
+                                     a->beta, a->C, a->ldc, splits, partial, s);
+    } else {
+        KTimer kt(c, s, "gemm_fp6x3_tn");
+        e = cmp::launch_gemm_fp6x3_tn(a->M, a->N, I.Kp, a->alpha, I.at(ws, 0), I.at(ws, 1), I.at(ws, 4),
+                                      I.at(ws, 2), I.at(ws, 3), I.at(ws, 5), a->beta, a->C, a->ldc,
+                                      splits, partial, s);
     }
-    {
-        KTimer kt(c, s, nterms > 1 ? "split_bt_bf16_hilo" : "split_bt_bf16");
-        if (cmp::launch_split_bt_bf16(a->K, a->N, a->B, a->ldb, L.Np, L.Kp, Bh, Bl, s) != hipSuccess)
-            return CMP_EHIP;
-    }
-    {
-        KTimer kt(c, s, nterms > 1 ? "gemm_bf16x3_tn" : "gemm_bf16_tn");
-        if (cmp::launch_gemm_bf16_tn(a->M, a->N, L.Kp, nterms, a->alpha, Ah, Al, Bh, Bl, a->beta,
-                                     a->C, a->ldc, splits, partial, s) != hipSuccess)
-            return CMP_EHIP;
-    }
+    if (e != hipSuccess) return CMP_EHIP;
     return finish_split(c, a, splits, partial, s);
 }
 int v_bf16(const void* args, void* ws, size_t, void* stream, void* user) {
-    return run_bf16((cmp_ctx*)user, (const cmp_gemm_args*)args, ws, (hipStream_t)stream, 1);
+    return run_images((cmp_ctx*)user, kImgBf16, (const cmp_gemm_args*)args, ws, (hipStream_t)stream);
 }
 int v_bf16x3(const void* args, void* ws, size_t, void* stream, void* user) {
-    return run_bf16((cmp_ctx*)user, (const cmp_gemm_args*)args, ws, (hipStream_t)stream, 3);
+    return run_images((cmp_ctx*)user, kImgBf16x3, (const cmp_gemm_args*)args, ws, (hipStream_t)stream);
 }
-
 int v_fp8r(const void* args, void* ws, size_t, void* stream, void* user) {
-    auto* c = (cmp_ctx*)user;
-    auto a = (const cmp_gemm_args*)args;
-    auto s = (hipStream_t)stream;
-    int st;
-    if (gemm_trivial(a, s, &st)) return st;
-    auto L = fp8_layout(a);
-    auto* p = (uint8_t*)ws;
-    uint8_t* Aq = p;
-    p += L.a_bytes;
-    uint8_t* Ar = p;
-    p += L.a_bytes;
-    uint8_t* Bq = p;
-    p += L.b_bytes;
-    uint8_t* Br = p;
-    p += L.b_bytes;
-    uint8_t* Asq = p;
-    p += L.as_bytes;
-    uint8_t* Asr = p;
-    p += L.as_bytes;
-    uint8_t* Bsq = p;
-    p += L.bs_bytes;
-    uint8_t* Bsr = p;
-    p += L.bs_bytes;
-    const int splits = gemm_splits(a, L.Kp, cmp::kStepNsFp8r, c);
-    float* partial = (float*)p;
-    if (fork_aux(c, s) != hipSuccess) return CMP_EHIP;
-    {
-        KTimer kt(c, c->aux, "quant_fp8_bt");
-        if (cmp::launch_quant_fp8(a->K, a->N, a->B, a->ldb, true, true, L.Np, L.Kp, Bq, Bsq, Br, Bsr,
-                                  c->aux) != hipSuccess)
-            return CMP_EHIP;
-    }
-    {
-        KTimer kt(c, s, "quant_fp8_a");
-        if (cmp::launch_quant_fp8(a->M, a->K, a->A, a->lda, false, true, L.Mp, L.Kp, Aq, Asq, Ar, Asr, s) !=
-            hipSuccess)
-            return CMP_EHIP;
-    }
-    if (join_aux(c, s) != hipSuccess) return CMP_EHIP;
-    {
-        KTimer kt(c, s, "gemm_fp8r_tn");
-        if (cmp::launch_gemm_fp8r_tn(a->M, a->N, L.Kp, a->alpha, Aq, Ar, Asq, Asr, Bq, Br, Bsq, Bsr,
-                                     a->beta, a->C, a->ldc, splits, partial, s) != hipSuccess)
-            return CMP_EHIP;
-    }
-    return finish_split(c, a, splits, partial, s);
+    return run_images((cmp_ctx*)user, kImgFp8r, (const cmp_gemm_args*)args, ws, (hipStream_t)stream);
 }
-
 int v_fp6x3(const void* args, void* ws, size_t, void* stream, void* user) {
-    auto* c = (cmp_ctx*)user;
-    auto a = (const cmp_gemm_args*)args;
-    auto s = (hipStream_t)stream;
-    int st;
-    if (gemm_trivial(a, s, &st)) return st;
-    auto L = fp6_layout(a);
-    auto* p = (uint8_t*)ws;
-    uint8_t* Ah = p;
-    uint8_t* Al = Ah + L.a_codes;
-    uint8_t* Bh = Al + L.a_codes;
-    uint8_t* Bl = Bh + L.b_codes;
-    uint8_t* As = Bl + L.b_codes;
-    uint8_t* Bs = As + L.a_scales;
-    const int splits = gemm_splits(a, L.Kp, cmp::kStepNsFp6x3, c);
-    float* partial = (float*)(Bs + L.b_scales);
-    if (fork_aux(c, s) != hipSuccess) return CMP_EHIP;
-    {
-        KTimer kt(c, c->aux, "quant_mx6_bt");
-        if (cmp::launch_quant_mx6(a->K, a->N, a->B, a->ldb, true, true, L.Np, L.Kp, Bh, Bs, Bl,
-                                  nullptr, c->aux) != hipSuccess)
-            return CMP_EHIP;
-    }
-    {
-        KTimer kt(c, s, "quant_mx6_a");
-        if (cmp::launch_quant_mx6(a->M, a->K, a->A, a->lda, false, true, L.Mp, L.Kp, Ah, As, Al,
-                                  nullptr, s) != hipSuccess)
-            return CMP_EHIP;
-    }
-    if (join_aux(c, s) != hipSuccess) return CMP_EHIP;
-    {
-        KTimer kt(c, s, "gemm_fp6x3_tn");
-        if (cmp::launch_gemm_fp6x3_tn(a->M, a->N, L.Kp, a->alpha, Ah, Al, As, Bh, Bl, Bs, a->beta, a->C,
-                                      a->ldc, splits, partial, s) != hipSuccess)
-            return CMP_EHIP;
-    }
-    return finish_split(c, a, splits, partial, s);
+    return run_images((cmp_ctx*)user, kImgFp6x3, (const cmp_gemm_args*)args, ws, (hipStream_t)stream);
+}
+// The image kind of a registered variant (kImgNone: no operand pre-pass).
+int image_kind(const Variant& v) {
+    if (v.fn == v_bf16) return kImgBf16;
+    if (v.fn == v_bf16x3) return kImgBf16x3;
+    if (v.fn == v_fp8r) return kImgFp8r;
+    if (v.fn == v_fp6x3) return kImgFp6x3;
+    return kImgNone;
 }
 
 // The optional host variant: FP32 GEMM on the CPU.  In a GPU context the
@@ -1006,13 +984,15 @@ VLayout vlayout(const cmp_gemm_args* a, bool keep_c0) {
     return L;
 }
 
-int probe(cmp_ctx* c, const cmp_gemm_args* a, const float* c0, const double* x_dev, hipStream_t s,
-          double* est) {
+// c0 (read only when beta != 0) has leading dimension ldc0: N for the packed
+// copy verify mode keeps, the caller's ldc for cmp_freivalds.
+int probe(cmp_ctx* c, const cmp_gemm_args* a, const float* c0, int64_t ldc0, const double* x_dev,
+          hipStream_t s, double* est) {
     const VLayout L = vlayout(a, false);
     double* base = (double*)c->vws;  // sized by the caller (ensure_vws with vlayout)
     double* out = base + L.out_d;
     HIP_TRY(c, cmp::launch_freivalds(a->M, a->N, a->K, a->alpha, a->A, a->lda, a->B, a->ldb,
-                                     a->beta, c0, a->C, a->ldc, x_dev, base, out, s));
+                                     a->beta, c0, ldc0, a->C, a->ldc, x_dev, base, out, s));
     double h[2];
     HIP_TRY(c, hipMemcpyAsync(h, out, sizeof h, hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipStreamSynchronize(s));
@@ -1256,18 +1236,11 @@ CMP_API int cmp_split_k(cmp_ctx* c, int id, int64_t M, int64_t N, int64_t K, int
     a.M = M;
     a.N = N;
     a.K = K;
-    const cmp_variant_fn fn = f->variants[id].fn;
-    if (M == 0 || N == 0 || K == 0 || f->variants[id].user != c)
+    const int kind = image_kind(f->variants[id]);
+    if (M == 0 || N == 0 || K == 0 || f->variants[id].user != c || kind == kImgNone)
         *splits = 1;
-    else if (fn == v_bf16 || fn == v_bf16x3)
-        *splits = gemm_splits(&a, bf16_layout(&a).Kp * 2,
-                              fn == v_bf16x3 ? cmp::kStepNsBf16x3 : cmp::kStepNsBf16, c);
-    else if (fn == v_fp8r)
-        *splits = gemm_splits(&a, fp8_layout(&a).Kp, cmp::kStepNsFp8r, c);
-    else if (fn == v_fp6x3)
-        *splits = gemm_splits(&a, fp6_layout(&a).Kp, cmp::kStepNsFp6x3, c);
     else
-        *splits = 1;
+        *splits = image_splits(kind, &a, images_of(kind, M, N, K), c);
     return CMP_OK;
 }
 
@@ -1365,7 +1338,7 @@ CMP_API int cmp_gemm(cmp_ctx* c, const cmp_gemm_args* a, double tol, void* strea
     }
     if (verify) {
         double est = 0;
-        if ((st = probe(c, a, c0, xdev, s, &est))) return st;
+        if ((st = probe(c, a, c0, a->N, xdev, s, &est))) return st;
         c->last_verify = est;
         if (est > verify_threshold(tol, a->M)) {
             // rerun once with the best admissible variant of strictly tighter bound
@@ -1382,7 +1355,7 @@ CMP_API int cmp_gemm(cmp_ctx* c, const cmp_gemm_args* a, double tol, void* strea
             if ((st = restore_c())) return st;
             if ((st = run_variant(c, *f, id2, a, stream))) return st;
             id = id2;
-            if ((st = probe(c, a, c0, xdev, s, &est))) return st;
+            if ((st = probe(c, a, c0, a->N, xdev, s, &est))) return st;
             c->last_verify = est;
             if (est > verify_threshold(tol, a->M))
                 return fail(c, CMP_ECHECK, "residual probe %.3g exceeds tol %g after fallback", est, tol);
@@ -1853,7 +1826,7 @@ CMP_API int cmp_freivalds(cmp_ctx* c, const cmp_gemm_args* a, const float* c0, c
     if (st) return st;
     double* xdev = (double*)c->vws + L.x_d;
     HIP_TRY(c, hipMemcpyAsync(xdev, x, (size_t)a->N * 8, hipMemcpyHostToDevice, s));
-    return probe(c, a, c0, xdev, s, est);
+    return probe(c, a, c0, a->ldc, xdev, s, est);
 }
 
 CMP_API int cmp_last_verify(cmp_ctx* c, double* est, int* fallbacks) {
@@ -1916,6 +1889,48 @@ CMP_API int cmp_quant_mx6(cmp_ctx* c, int64_t rows, int64_t cols, const float* X
     HIP_TRY(c, cmp::launch_quant_mx6(rows, cols, X, ldx, transpose != 0, false, 0, 0, q, qs, rq, rs,
                                      (hipStream_t)stream));
     return CMP_OK;
+}
+
+CMP_API int cmp_prepass_layout(cmp_ctx* c, int id, int64_t M, int64_t N, int64_t K,
+                               cmp_image_layout* out) {
+    if (!c || !out || M < 1 || N < 1 || K < 1) return CMP_EINVAL;
+    Interface* f = find_iface(c, kGemm);
+    if (!f || id < 0 || id >= (int)f->variants.size()) return fail(c, CMP_EINVAL, "bad variant id %d", id);
+    const int kind = image_kind(f->variants[id]);
+    if (kind == kImgNone)
+        return fail(c, CMP_EUNSUPPORTED, "variant %s has no operand pre-pass",
+                    f->variants[id].name.c_str());
+    const Images I = images_of(kind, M, N, K);
+    *out = cmp_image_layout{};
+    out->Mp = I.Mp;
+    out->Np = I.Np;
+    out->Kp = I.Kp;
+    out->count = I.n;
+    for (int i = 0; i < 8; ++i) {
+        out->offset[i] = i < I.n ? (int64_t)I.off[i] : -1;
+        out->bytes[i] = i < I.n ? (int64_t)I.bytes[i] : 0;
+    }
+    out->total = (int64_t)I.total;
+    return CMP_OK;
+}
+
+CMP_API int cmp_prepass_images(cmp_ctx* c, int id, const cmp_gemm_args* a, void* out,
+                               size_t out_bytes, void* stream) {
+    if (!c || !a) return CMP_EINVAL;
+    if (!c->gpu) return fail(c, CMP_EUNSUPPORTED, "needs a GPU context");
+    cmp_image_layout L;
+    int st = cmp_prepass_layout(c, id, a->M, a->N, a->K, &L);
+    if (st) return st;
+    if (!a->A || !a->B || !out) return fail(c, CMP_EINVAL, "null pointer");
+    if (a->lda < a->K || a->ldb < a->N) return fail(c, CMP_EINVAL, "lda < K or ldb < N");
+    if (out_bytes < (size_t)L.total)
+        return fail(c, CMP_EINVAL, "image buffer of %zu bytes, %lld needed", out_bytes,
+                    (long long)L.total);
+    Interface* f = find_iface(c, kGemm);
+    const int kind = image_kind(f->variants[id]);
+    st = prepass(c, kind, a, images_of(kind, a->M, a->N, a->K), out, (hipStream_t)stream);
+    if (st == CMP_EHIP) return hip_fail(c, hipGetLastError(), "pre-pass launch");
+    return st;
 }
 
 // ---------------------------------------------------------------------------

@@ -48,6 +48,16 @@ def ill_conditioned_matrix(rows: int, cols: int, seed: int, umax: int = 20) -> n
     return np.ldexp(x, u).astype(np.float32)
 
 
+def tile_scaled_matrix(rows: int, cols: int, seed: int, tile: int = 128) -> np.ndarray:
+    """normal(0,1) entries with tile (i, j) of `tile` x `tile` entries scaled by
+    2^((3 i + 5 j) mod 23 - 11), so neighbouring tiles (and blocks inside them) have different
+    magnitudes and therefore different scale exponents."""
+    X = normal_matrix(rows, cols, seed).astype(np.float64)
+    i = (np.arange(rows) // tile)[:, None]
+    j = (np.arange(cols) // tile)[None, :]
+    return (X * np.exp2((3 * i + 5 * j) % 23 - 11)).astype(np.float32)
+
+
 def gemm_operands(M: int, N: int, K: int, seed: int, dist: str = "normal"):
     """A (M x K) then B (K x N) from one stream, as float32 row-major arrays."""
     g = rng(seed)

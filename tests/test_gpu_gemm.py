@@ -63,7 +63,10 @@ INT_SHAPES = [(1, 1, 1), (7, 5, 3), (256, 256, 256), (300, 520, 200), (257, 255,
               (64, 1000, 33), (513, 130, 640),
               # extreme aspect ratios: one tile over a long K (many pipeline stages),
               # a single row or column over several tiles, K just past a block boundary
-              (64, 64, 16384), (1, 4096, 1000), (4096, 1, 1000), (33, 65, 8200)]
+              (64, 64, 16384), (1, 4096, 1000), (4096, 1, 1000), (33, 65, 8200),
+              # many 256 x 256 tiles in both M and N: the XCD renumbering and the
+              # grouped tile walk of the MFMA kernels cover a 9 x 10 tile grid
+              (2304, 2560, 384)]
 
 
 @pytest.mark.parametrize("name", VARIANTS)
@@ -72,7 +75,8 @@ def test_integer_exact(cx, name, M, N, K):
     A = synth.int_matrix(M, K, M * 7 + K)
     B = synth.int_matrix(K, N, N * 11 + K)
     C = run(cx, name, A, B)
-    ref = (A.astype(np.int64) @ B.astype(np.int64)).astype(np.float64)
+    # entries are small integers and every partial sum is below 2^53: exact in float64
+    ref = A.astype(np.float64) @ B.astype(np.float64)
     assert np.array_equal(C.astype(np.float64), ref)
 
 
@@ -351,3 +355,39 @@ def test_square_8192_sampled(cx, name):
     err = oracle.relfro(got, ref)
     say(f"  {name} 8192^3 sampled rel-Frobenius {err:.3e}")
     assert err <= BOUND[name], err
+
+
+# ---- operands whose magnitude changes from tile to tile ----------------------------
+# Tile (i, j) of 128 x 128 entries of A and of B^T is scaled by 2^((3 i + 5 j) mod 23 - 11):
+# every FP8 tile scale and MX block scale differs from its neighbours, so a swapped or
+# shifted scale index (A tile, transposed-B tile, K block of a split-K slice that starts
+# inside a tile) breaks the entrywise bound.
+
+def tile_operands(M, N, K, seed):
+    A = synth.tile_scaled_matrix(M, K, seed)
+    B = np.ascontiguousarray(synth.tile_scaled_matrix(N, K, seed + 1).T)
+    return A, B
+
+
+@pytest.mark.parametrize("name", VARIANTS)
+@pytest.mark.parametrize("M,N,K", [(640, 768, 1024), (385, 300, 260), (1000, 129, 520)])
+def test_tile_scaled_within_entrywise_bound(cx, name, M, N, K):
+    A, B = tile_operands(M, N, K, M + N + K)
+    C = run(cx, name, A, B)
+    prod, bnd = variant_reference(name, A, B)
+    viol = np.abs(C.astype(np.float64) - prod) - bnd
+    assert np.all(viol <= 0), (name, float(viol.max()))
+
+
+@pytest.mark.parametrize("name", MFMA_VARIANTS)
+def test_tile_scaled_split_k_3(cx, name):
+    """Forced split-K 3 over K = 896: the fp8 and fp6 images hold 14 K blocks of 64 values,
+    cut into slices of 5, 5 and 4 blocks, so the second slice starts half way through a
+    128-wide FP8 scale tile."""
+    M, N, K = 640, 768, 896
+    A, B = tile_operands(M, N, K, 11)
+    C, reduced = run_split(cx, name, 3, A, B)
+    assert reduced
+    prod, bnd = variant_reference(name, A, B)
+    viol = np.abs(C.astype(np.float64) - prod) - bnd
+    assert np.all(viol <= 0), (name, float(viol.max()))

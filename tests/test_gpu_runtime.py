@@ -82,6 +82,46 @@ def test_verify_mode_probe_matches_oracle(cx):
     assert oracle.relfro(C, oracle.gemm(A, B, 1.0, 0.5, C0)) <= BOUNDS[chosen]
 
 
+@pytest.mark.parametrize("name", ["f32_simt", "bf16", "fp8r"])
+def test_verify_mode_with_a_column_slice_of_c(name):
+    """Verify mode with beta != 0 and C a column slice of a wider matrix (ldc > N): the probe
+    reads the kept old C at its own packed pitch, so it equals the oracle's probe of the same
+    C, no fallback is taken, and the columns of the wide matrix outside the slice are untouched.
+    cmp_freivalds itself takes the caller's old C at ldc: a strided slice there too."""
+    import paper_2311_03543_amd as pa
+    c = pa.Compar(0)
+    try:
+        M, N, K, W, off = 300, 200, 250, 333, 71
+        A, B = synth.gemm_operands(M, N, K, seed=26)
+        wide0 = synth.normal_matrix(M, W, 27)
+        dwide = dev(wide0)
+        dC = dwide[:, off:off + N]
+        assert dC.stride(0) == W
+        vid = c.variant_find(name)
+        c.force_variant(vid)
+        c.set_flags(pa.CMP_FLAG_VERIFY)
+        say(f"  verify-mode cmp_gemm {name} beta=0.5 on a column slice (ldc {W}, N {N})")
+        chosen = c.gemm(dev(A), dev(B), dC, alpha=1.0, beta=0.5, tol=1e-2)
+        est, fallbacks = c.last_verify()
+        wide = host(dwide)
+        assert chosen == vid and fallbacks == 0
+        C0 = np.ascontiguousarray(wide0[:, off:off + N])
+        Cout = np.ascontiguousarray(wide[:, off:off + N])
+        x = oracle.rademacher_splitmix(N, 0x5EED)
+        ref = oracle.freivalds(A, B, Cout, x, alpha=1.0, beta=0.5, C0=C0)
+        assert abs(est - ref) <= 1e-9 * max(ref, 1e-300), (est, ref)
+        assert oracle.relfro(Cout, oracle.gemm(A, B, 1.0, 0.5, C0)) <= BOUNDS[vid]
+        assert np.array_equal(wide[:, :off], wide0[:, :off])
+        assert np.array_equal(wide[:, off + N:], wide0[:, off + N:])
+        # the probe entry point with a strided old C (ld = ldc of the product's C)
+        say("  cmp_freivalds with strided C and old C")
+        dC0 = dev(wide0)[:, off:off + N]
+        got = c.freivalds(dev(A), dev(B), dC, x, alpha=1.0, beta=0.5, C0=dC0)
+        assert abs(got - ref) <= 1e-9 * max(ref, 1e-300), (got, ref)
+    finally:
+        c.close()
+
+
 @pytest.mark.parametrize("name", ["bf16x3", "fp8r", "bf16"])
 def test_verify_mode_on_a_split_k_call(name):
     """Verify mode over a split-K launch (4 output tiles over K = 4000): the FP64 probe sees the

@@ -171,3 +171,33 @@ def test_relfro_metric():
     assert oracle.relfro(E, Z) == 5.0
     E[2, 2] = np.nan
     assert oracle.relfro(E, Z) == math.inf
+
+
+def test_relfro_list_metric():
+    """The sampled-entry form of the metric (a 1-D list of values against their references),
+    pinned by hand values: a 3-4-5 triangle, a zero reference (absolute norm), a NaN or an
+    infinity anywhere in the list (infinity), and the 2-D form over the same entries."""
+    f32 = lambda v: np.array(v, np.float32)
+    f64 = lambda v: np.array(v, np.float64)
+    # ||(0, 1)|| / ||(3, 4)|| = 1/5: a dropped square root would give 1/25
+    assert oracle.relfro(f32([3.0, 5.0]), f64([3.0, 4.0])) == 0.2
+    # ||(3, 4)|| against a zero reference is the absolute norm 5
+    assert oracle.relfro(f32([3.0, 4.0]), f64([0.0, 0.0])) == 5.0
+    # an exact match is 0; a one-element list
+    assert oracle.relfro(f32([1.5, -2.0, 8.0]), f64([1.5, -2.0, 8.0])) == 0.0
+    assert oracle.relfro(f32([2.0]), f64([4.0])) == 0.5
+    for bad in (np.nan, np.inf, -np.inf):
+        for pos in (0, 2, 4):
+            c = f32([1.0, 2.0, 3.0, 4.0, 5.0])
+            c[pos] = bad
+            assert oracle.relfro(c, f64([1.0, 2.0, 3.0, 4.0, 5.0])) == math.inf
+    # the list form over sampled entries equals the 2-D form over the same entries
+    R = synth.normal_matrix(40, 50, 3).astype(np.float64)
+    C = (R + 1e-3 * synth.normal_matrix(40, 50, 4)).astype(np.float32)
+    assert math.isclose(oracle.relfro(C.ravel(), R.ravel()), oracle.relfro(C, R), rel_tol=1e-13)
+    rng = np.random.default_rng(5)
+    ij = rng.integers(0, 40, size=(300, 2))
+    ij[:, 1] = rng.integers(0, 50, size=300)
+    c, r = C[ij[:, 0], ij[:, 1]], R[ij[:, 0], ij[:, 1]]
+    d = c.astype(np.float64) - r
+    assert math.isclose(oracle.relfro(c, r), math.sqrt(np.sum(d * d) / np.sum(r * r)), rel_tol=1e-13)

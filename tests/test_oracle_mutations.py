@@ -30,6 +30,9 @@ MUTATIONS = {
                        "    const double v = m * step;                    /* <= 7.5"),
     "mx6_scale_to_8": ("while (ldexp(a, e) > 7.5) --e;\n    while (ldexp(a, e + 1) <= 7.5) ++e;",
                        "while (ldexp(a, e) > 8.0) --e;\n    while (ldexp(a, e + 1) <= 8.0) ++e;"),
+    "relfro_list_no_sqrt": ("        den += r[t] * r[t];\n    }\n    return den > 0.0 ? sqrt(num) / sqrt(den) : sqrt(num);",
+                            "        den += r[t] * r[t];\n    }\n    return den > 0.0 ? num / den : num;"),
+    "relfro_list_no_nan_check": ("        if (!isfinite(cv)) return INFINITY;\n", ""),
 }
 
 
@@ -104,12 +107,23 @@ def mx6_scale_pin_holds(L):
     return all(L.oracle_mx6_scale_exp(a) == e for a, e in [(7.5, 0), (1.0, 2), (3.75, 1), (7.6, -1)])
 
 
+def relfro_list_pin_holds(L):
+    """The sampled-entry metric on hand values: 1/5 for a 3-4-5 triangle, infinity for a NaN."""
+    fp, dp = C.POINTER(C.c_float), C.POINTER(C.c_double)
+    L.oracle_relfro_list.argtypes = [C.c_int64, fp, dp]
+    L.oracle_relfro_list.restype = C.c_double
+    f = lambda c, r: L.oracle_relfro_list(len(c), np.array(c, np.float32).ctypes.data_as(fp),
+                                          np.array(r, np.float64).ctypes.data_as(dp))
+    return f([3.0, 5.0], [3.0, 4.0]) == 0.2 and f([1.0, np.nan], [1.0, 1.0]) == float("inf")
+
+
 def test_real_oracle_passes_the_pins(tmp_path):
     import oracle
     assert gemm_pin_holds(oracle.lib())
     assert e4m3_pin_holds(oracle.lib())
     assert e2m3_pin_holds(oracle.lib())
     assert mx6_scale_pin_holds(oracle.lib())
+    assert relfro_list_pin_holds(oracle.lib())
 
 
 @pytest.mark.parametrize("name", ["transposed_B", "beta_sign", "dropped_last_k"])
@@ -127,3 +141,8 @@ def test_e2m3_mutant_is_caught(tmp_path):
 
 def test_mx6_scale_mutant_is_caught(tmp_path):
     assert not mx6_scale_pin_holds(build_mutant("mx6_scale_to_8", tmp_path))
+
+
+@pytest.mark.parametrize("name", ["relfro_list_no_sqrt", "relfro_list_no_nan_check"])
+def test_relfro_list_mutants_are_caught(name, tmp_path):
+    assert not relfro_list_pin_holds(build_mutant(name, tmp_path))
