@@ -100,8 +100,10 @@ typedef enum cmp_selector_kind {
 } cmp_selector_kind;
 
 enum {
-    CMP_FLAG_VERIFY = 1u    /* after each cmp_gemm, run the FP64 Freivalds probe and fall
+    CMP_FLAG_VERIFY = 1u,   /* after each cmp_gemm, run the FP64 Freivalds probe and fall
                                back to the next tighter variant if it exceeds tol */
+    CMP_FLAG_LOG = 2u       /* append one JSON line per cmp_gemm call to the log sink
+                               (cmp_set_log_file; stderr by default), see below */
 };
 
 /* One parameter of an interface (the parameter directive, Sec. 2.1).  `extent`
@@ -198,7 +200,33 @@ int cmp_force_variant(cmp_ctx *ctx, const char *iface, int id);
 /* ---- selection (the runtime's choice of codelet, Sec. 2.2.2) ------------ */
 
 int cmp_selector_set(cmp_ctx *ctx, int kind);
+/* Flags: a combination of CMP_FLAG_VERIFY and CMP_FLAG_LOG (CMP_EINVAL for
+ * other bits). */
 int cmp_set_flags(cmp_ctx *ctx, uint32_t flags);
+/* Per-call log (the performance-history record of each task, Sec. 3.2).  With
+ * CMP_FLAG_LOG set, every cmp_gemm call appends one JSON object per line:
+ *   {"call": n, "M": .., "N": .., "K": .., "tol": .., "selector": s,
+ *    "variant": name, "id": i, "predicted_us": p, "measured_us": t,
+ *    "residual": r, "fallbacks": f}
+ * s is "nn", "mlp" or "static" (the context's selector), "forced" (a forced
+ * variant) or "only" (one admissible variant).  p is the time the selector
+ * ranked the chosen variant by (the network's prediction, or the recorded
+ * median at the history's nearest shape that timed it), null when none (the
+ * static choice, a forced or only variant, or a fallback's variant).  t is the
+ * duration of the run that produced C, from a HIP event pair on the stream
+ * around all the work the variant queued (host variants: the host clock);
+ * null when the call was made while the stream was being captured.  r is the
+ * verify-mode probe estimate (null without CMP_FLAG_VERIFY).  f counts the
+ * fallbacks this call took.  Records are written in call order once their
+ * events have completed: at a later cmp_gemm call, cmp_log_flush, a change of
+ * sink or cmp_terminate.  The environment variable COMPAR_LOG=<path> at
+ * cmp_init opens that file and sets CMP_FLAG_LOG.
+ * path NULL or "" selects stderr; otherwise the file is opened for appending
+ * (CMP_EINVAL if it cannot be).  Records still pending go to the old sink
+ * first. */
+int cmp_set_log_file(cmp_ctx *ctx, const char *path);
+/* Wait for the pending log records' events and write them. */
+int cmp_log_flush(cmp_ctx *ctx);
 /* Split-K of the built-in MFMA variants (bf16x3, fp8r, bf16).  With fewer
  * 256 x 256 output tiles than compute units, these variants can cut K into
  * slices run by separate workgroups, each writing an M x N float partial sum

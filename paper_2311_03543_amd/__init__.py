@@ -15,7 +15,7 @@ from ._lib import (CMP_EDUP, CMP_EHIP, CMP_EINVAL, CMP_ENODATA, CMP_ENOTFOUND,  
                    CMP_ENOVARIANT, CMP_ESIG, CMP_EUNSUPPORTED, CMP_ECHECK, CMP_OK, CMP_F32,
                    CMP_F64, CMP_I32, CMP_I64, CMP_BF16, CMP_F8E4M3, CMP_READ, CMP_WRITE,
                    CMP_READWRITE, CMP_SEL_MLP, CMP_SEL_NN, CMP_SEL_STATIC, CMP_TARGET_HIP,
-                   CMP_TARGET_HOST, CMP_FLAG_VERIFY, ComparError, cmp_context, cmp_gemm_args,
+                   CMP_TARGET_HOST, CMP_FLAG_VERIFY, CMP_FLAG_LOG, ComparError, cmp_context, cmp_gemm_args,
                    cmp_param_desc)
 
 GEMM = b"gemm"
@@ -156,6 +156,12 @@ class Compar:
 
     def set_flags(self, flags: int):
         self._check(self.L.cmp_set_flags(self.ctx, flags))
+
+    def set_log_file(self, path: str | None):
+        self._check(self.L.cmp_set_log_file(self.ctx, path.encode() if path else None))
+
+    def log_flush(self):
+        self._check(self.L.cmp_log_flush(self.ctx))
 
     def register_builtin(self, name: str) -> int:
         """Register an optional built-in variant ("fp6x3" or "host_f32"); returns its id."""

@@ -31,6 +31,7 @@ CMP_F32, CMP_BF16, CMP_F8E4M3, CMP_F64, CMP_I32, CMP_I64 = range(6)
 CMP_READ, CMP_WRITE, CMP_READWRITE = 1, 2, 3
 CMP_SEL_STATIC, CMP_SEL_NN, CMP_SEL_MLP = 0, 1, 2
 CMP_FLAG_VERIFY = 1
+CMP_FLAG_LOG = 2
 
 
 class cmp_param_desc(C.Structure):
@@ -87,6 +88,8 @@ SIGNATURES = {
     "cmp_force_variant": (_I, [_P, _S, _I]),
     "cmp_selector_set": (_I, [_P, _I]),
     "cmp_set_flags": (_I, [_P, C.c_uint32]),
+    "cmp_set_log_file": (_I, [_P, C.c_char_p]),
+    "cmp_log_flush": (_I, [_P]),
     "cmp_set_split_k": (_I, [_P, _I]),
     "cmp_register_builtin": (_I, [_P, _S, _IP]),
     "cmp_quant_mx6": (_I, [_P, _I64, _I64, _P, _I64, _I, _P, _P, _P, _P, _P]),

@@ -88,6 +88,12 @@ struct CacheKey {
         return M == o.M && N == o.N && K == o.K && tol == o.tol;
     }
 };
+// A cached decision: the chosen id and the selector's predicted ln(us) for it
+// (NaN when the selector predicts no time: the static choice).
+struct CacheVal {
+    int id;
+    double pred_ln_us;
+};
 struct CacheHash {
     size_t operator()(const CacheKey& k) const {
         uint64_t h = 1469598103934665603ull;
@@ -129,7 +135,7 @@ struct cmp_ctx {
     mutable ShapeTable shape_cache;
     mutable uint64_t shape_cache_gen = ~0ull;
     mutable size_t shape_cache_nvar = 0;
-    std::unordered_map<CacheKey, int, CacheHash> cache;
+    std::unordered_map<CacheKey, CacheVal, CacheHash> cache;
     // learned selector
     std::vector<float> mlp_params;
     float mu_x[4] = {0, 0, 0, 0}, sd_x[4] = {1, 1, 1, 1};
@@ -163,6 +169,24 @@ struct cmp_ctx {
     std::vector<KEv> kpending;
     std::vector<hipEvent_t> kpool;
     std::map<std::string, std::pair<long long, double>> kstats;  // launches, total ms
+    // per-call log (CMP_FLAG_LOG): one JSON line per cmp_gemm, written once the
+    // call's HIP event pair has completed (records stay in call order)
+    struct LogRec {
+        uint64_t call;
+        int64_t M, N, K;
+        double tol;
+        const char* how;         // how the variant was chosen
+        int id;
+        std::string name;
+        double pred_us;          // NaN: no prediction
+        double residual;         // NaN: no probe
+        int fallbacks;           // fallbacks taken by this call
+        hipEvent_t a, b;         // GPU variants: events around the variant's work
+        double host_us;          // host variants: steady-clock duration
+    };
+    std::vector<LogRec> log_pending;
+    FILE* log_fp = nullptr;      // nullptr: stderr
+    uint64_t log_calls = 0;
     // COMPAR_VARIANTS / COMPAR_FORCE, applied by name to gemm variants as they register
     bool env_restrict = false;
     std::vector<std::string> env_allow;
@@ -224,6 +248,80 @@ struct KTimer {
         c->kpending.push_back({name, a, b});
     }
 };
+
+// ---------------------------------------------------------------------------
+// Per-call log (CMP_FLAG_LOG)
+
+void json_str(std::string& out, const std::string& v) {
+    out += '"';
+    for (unsigned char ch : v) {
+        if (ch == '"' || ch == '\\') {
+            out += '\\';
+            out += (char)ch;
+        } else if (ch < 0x20) {
+            char b[8];
+            std::snprintf(b, sizeof b, "\\u%04x", ch);
+            out += b;
+        } else {
+            out += (char)ch;
+        }
+    }
+    out += '"';
+}
+void json_num(std::string& out, double v) {
+    char b[32];
+    if (std::isfinite(v)) std::snprintf(b, sizeof b, "%.9g", v);
+    else std::snprintf(b, sizeof b, "null");
+    out += b;
+}
+void log_write(cmp_ctx* c, const cmp_ctx::LogRec& r, double measured_us) {
+    std::string l;
+    char b[160];
+    std::snprintf(b, sizeof b, "{\"call\": %llu, \"M\": %lld, \"N\": %lld, \"K\": %lld, \"tol\": ",
+                  (unsigned long long)r.call, (long long)r.M, (long long)r.N, (long long)r.K);
+    l += b;
+    json_num(l, r.tol);
+    l += ", \"selector\": \"";
+    l += r.how;
+    l += "\", \"variant\": ";
+    json_str(l, r.name);
+    std::snprintf(b, sizeof b, ", \"id\": %d, \"predicted_us\": ", r.id);
+    l += b;
+    json_num(l, r.pred_us);
+    l += ", \"measured_us\": ";
+    json_num(l, measured_us);
+    l += ", \"residual\": ";
+    json_num(l, r.residual);
+    std::snprintf(b, sizeof b, ", \"fallbacks\": %d}\n", r.fallbacks);
+    l += b;
+    FILE* fp = c->log_fp ? c->log_fp : stderr;
+    std::fwrite(l.data(), 1, l.size(), fp);
+    std::fflush(fp);
+}
+// Write the pending records whose events have completed, in call order
+// (stopping at the first one still running); with `wait`, all of them.
+void log_drain(cmp_ctx* c, bool wait) {
+    size_t done = 0;
+    for (; done < c->log_pending.size(); ++done) {
+        auto& r = c->log_pending[done];
+        double us = r.host_us;
+        if (r.b) {
+            const hipError_t e = wait ? hipEventSynchronize(r.b) : hipEventQuery(r.b);
+            if (e == hipErrorNotReady) break;
+            float ms = 0.f;
+            if (e == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+                us = 1e3 * (double)ms;
+            } else {
+                us = NAN;
+                (void)hipGetLastError();
+            }
+            c->kpool.push_back(r.a);
+            c->kpool.push_back(r.b);
+        }
+        log_write(c, r, us);
+    }
+    c->log_pending.erase(c->log_pending.begin(), c->log_pending.begin() + (std::ptrdiff_t)done);
+}
 
 Interface* find_iface(cmp_ctx* c, const char* name) {
     if (!name) return nullptr;
@@ -673,6 +771,9 @@ void read_env(cmp_ctx* c) {
             if (!tok.empty()) c->env_allow.push_back(tok);
     }
     if (const char* s = std::getenv("COMPAR_FORCE")) c->env_force = s;
+    if (const char* s = std::getenv("COMPAR_LOG")) {
+        if (*s && (c->log_fp = std::fopen(s, "a"))) c->flags |= CMP_FLAG_LOG;
+    }
     if (const char* s = std::getenv("COMPAR_FAULT")) {
         std::string v = s;
         auto p = v.find(':');
@@ -845,7 +946,7 @@ int do_select_batch(cmp_ctx* c, Interface* f, int n, const cmp_context* q, int* 
         }
         auto it = c->cache.find(CacheKey{x.M, x.N, x.K, x.tol});
         if (it != c->cache.end()) {
-            ids[r] = it->second;
+            ids[r] = it->second.id;
             continue;
         }
         ids[r] = -1;
@@ -872,6 +973,7 @@ int do_select_batch(cmp_ctx* c, Interface* f, int n, const cmp_context* q, int* 
         const cmp_context& x = q[pending[p]];
         std::vector<int> adm = admissible_ids(*f, x.tol);
         int id = -1;
+        double pred_ln = NAN;
         if (use_mlp) {
             // the network predicts ln(us) of the four default built-ins; any
             // other variant is estimated from the history's nearest shape
@@ -879,12 +981,16 @@ int do_select_batch(cmp_ctx* c, Interface* f, int n, const cmp_context* q, int* 
             for (int i : adm)
                 t[i] = i < kNumBuiltin ? pred[4 * p + i] : nn_log_us(c, *f, i, x.M, x.N, x.K);
             id = argmin_tiebreak(*f, adm, t);
+            if (id >= 0) pred_ln = t[id];
         }
-        if (id < 0 && c->selector != CMP_SEL_STATIC) id = select_nn(c, *f, adm, x.M, x.N, x.K);
+        if (id < 0 && c->selector != CMP_SEL_STATIC) {
+            id = select_nn(c, *f, adm, x.M, x.N, x.K);
+            if (id >= 0) pred_ln = nn_log_us(c, *f, id, x.M, x.N, x.K);
+        }
         if (id < 0) id = select_static(c, *f, adm);
         if (id < 0) return fail(c, CMP_ENOVARIANT, "selection failed");
         ids[pending[p]] = id;
-        c->cache[CacheKey{x.M, x.N, x.K, x.tol}] = id;
+        c->cache[CacheKey{x.M, x.N, x.K, x.tol}] = CacheVal{id, pred_ln};
     }
     return CMP_OK;
 }
@@ -1081,6 +1187,9 @@ CMP_API int cmp_init(int device, cmp_ctx** out) {
 
 CMP_API int cmp_terminate(cmp_ctx* c) {
     if (!c) return CMP_OK;
+    if (c->gpu) (void)hipSetDevice(c->device);
+    log_drain(c, true);
+    if (c->log_fp) std::fclose(c->log_fp);
     if (c->gpu) {
         (void)hipSetDevice(c->device);
         if (c->side) (void)hipStreamSynchronize(c->side);
@@ -1198,7 +1307,25 @@ CMP_API int cmp_selector_set(cmp_ctx* c, int kind) {
 
 CMP_API int cmp_set_flags(cmp_ctx* c, uint32_t flags) {
     if (!c) return CMP_EINVAL;
+    if (flags & ~(uint32_t)(CMP_FLAG_VERIFY | CMP_FLAG_LOG)) return fail(c, CMP_EINVAL, "unknown flag bits 0x%x", flags);
     c->flags = flags;
+    return CMP_OK;
+}
+
+CMP_API int cmp_set_log_file(cmp_ctx* c, const char* path) {
+    if (!c) return CMP_EINVAL;
+    FILE* fp = nullptr;
+    if (path && *path && !(fp = std::fopen(path, "a")))
+        return fail(c, CMP_EINVAL, "cannot open log file %s", path);
+    log_drain(c, true);   // earlier records go to the earlier sink
+    if (c->log_fp) std::fclose(c->log_fp);
+    c->log_fp = fp;
+    return CMP_OK;
+}
+
+CMP_API int cmp_log_flush(cmp_ctx* c) {
+    if (!c) return CMP_EINVAL;
+    log_drain(c, true);
     return CMP_OK;
 }
 
@@ -1301,6 +1428,56 @@ CMP_API int cmp_gemm(cmp_ctx* c, const cmp_gemm_args* a, double tol, void* strea
     if (st) return st;
     const bool verify = (c->flags & CMP_FLAG_VERIFY) && c->gpu && a->M > 0 && a->N > 0;
     auto s = (hipStream_t)stream;
+    // CMP_FLAG_LOG: HIP events around the run that produces C (none while the
+    // stream is being captured: the record then has no measured time)
+    const bool logging = (c->flags & CMP_FLAG_LOG) != 0;
+    hipEvent_t ev_a = nullptr, ev_b = nullptr;
+    double host_us = NAN;
+    const int fallbacks0 = c->fallbacks;
+    struct EvGuard {   // events not handed to a log record go back to the pool
+        cmp_ctx* c;
+        hipEvent_t* a;
+        hipEvent_t* b;
+        ~EvGuard() {
+            if (*a) c->kpool.push_back(*a);
+            if (*b) c->kpool.push_back(*b);
+        }
+    } ev_guard{c, &ev_a, &ev_b};
+    auto timed_run = [&](int vid) -> int {
+        const bool hip_v = f->variants[vid].target == CMP_TARGET_HIP && c->gpu;
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (logging && hip_v && hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone) {
+            if (!ev_a) ev_a = kev_get(c);
+            if (ev_a) (void)hipEventRecord(ev_a, s);
+        }
+        const auto t0 = std::chrono::steady_clock::now();
+        const int rst = run_variant(c, *f, vid, a, stream);
+        const auto t1 = std::chrono::steady_clock::now();
+        host_us = hip_v ? NAN : std::chrono::duration<double, std::micro>(t1 - t0).count();
+        if (logging && hip_v && ev_a && cs == hipStreamCaptureStatusNone) {
+            if (!ev_b) ev_b = kev_get(c);
+            if (ev_b) (void)hipEventRecord(ev_b, s);
+        }
+        return rst;
+    };
+    auto log_call = [&](int vid, double residual) {
+        if (!logging) return;
+        const char* how = c->selector == CMP_SEL_MLP ? "mlp" : (c->selector == CMP_SEL_NN ? "nn" : "static");
+        double pred = NAN;
+        const auto it = c->cache.find(CacheKey{a->M, a->N, a->K, tol});
+        if (f->forced >= 0) how = "forced";
+        else if (admissible_ids(*f, tol).size() == 1) how = "only";
+        else if (it != c->cache.end() && it->second.id == vid) pred = std::exp(it->second.pred_ln_us);
+        if (ev_a && !ev_b) {
+            c->kpool.push_back(ev_a);
+            ev_a = nullptr;
+        }
+        c->log_pending.push_back(cmp_ctx::LogRec{++c->log_calls, a->M, a->N, a->K, tol, how, vid,
+                                                 f->variants[vid].name, pred, residual,
+                                                 c->fallbacks - fallbacks0, ev_a, ev_b, host_us});
+        ev_a = ev_b = nullptr;
+        log_drain(c, false);
+    };
     float* c0 = nullptr;
     double* xdev = nullptr;
     auto restore_c = [&]() -> int {
@@ -1322,7 +1499,7 @@ CMP_API int cmp_gemm(cmp_ctx* c, const cmp_gemm_args* a, double tol, void* strea
         }
         HIP_TRY(c, cmp::launch_rademacher(a->N, 0x5eedull + c->verify_calls++, xdev, s));
     }
-    st = run_variant(c, *f, id, a, stream);
+    st = timed_run(id);
     if (st != CMP_OK && st != CMP_EINVAL) {
         // a failing variant gets one fallback: the best other admissible variant
         std::vector<int> rest;
@@ -1333,9 +1510,10 @@ CMP_API int cmp_gemm(cmp_ctx* c, const cmp_gemm_args* a, double tol, void* strea
         if ((st = reselect(c, f, q, rest, &id2))) return st;
         ++c->fallbacks;
         if ((st = restore_c())) return st;
-        if ((st = run_variant(c, *f, id2, a, stream))) return st;
+        if ((st = timed_run(id2))) return st;
         id = id2;
     }
+    double residual = NAN;
     if (verify) {
         double est = 0;
         if ((st = probe(c, a, c0, a->N, xdev, s, &est))) return st;
@@ -1346,21 +1524,27 @@ CMP_API int cmp_gemm(cmp_ctx* c, const cmp_gemm_args* a, double tol, void* strea
             std::vector<int> tighter;
             for (int i : admissible_ids(*f, tol))
                 if (f->variants[i].bound < b) tighter.push_back(i);
-            if (tighter.empty())
+            if (tighter.empty()) {
+                log_call(id, est);
                 return fail(c, CMP_ECHECK, "residual probe %.3g exceeds tol %g (variant %s)", est,
                             tol, f->variants[id].name.c_str());
+            }
             int id2 = -1;
             if ((st = reselect(c, f, q, tighter, &id2))) return st;
             ++c->fallbacks;
             if ((st = restore_c())) return st;
-            if ((st = run_variant(c, *f, id2, a, stream))) return st;
+            if ((st = timed_run(id2))) return st;
             id = id2;
             if ((st = probe(c, a, c0, a->N, xdev, s, &est))) return st;
             c->last_verify = est;
-            if (est > verify_threshold(tol, a->M))
+            if (est > verify_threshold(tol, a->M)) {
+                log_call(id, est);
                 return fail(c, CMP_ECHECK, "residual probe %.3g exceeds tol %g after fallback", est, tol);
+            }
         }
+        residual = est;
     }
+    log_call(id, residual);
     if (chosen) *chosen = id;
     return CMP_OK;
 }

@@ -331,3 +331,71 @@ def test_split_k_and_optional_builtin_argument_checks():
     # the MX FP6 quantisation entry needs a GPU context
     assert L.cmp_quant_mx6(ctx, 4, 4, None, 4, 0, None, None, None, None, None) == pa.CMP_EUNSUPPORTED
     c.close()
+
+
+def test_call_log_records(tmp_path):
+    """CMP_FLAG_LOG: one JSON line per cmp_gemm with the context, the choice, the selector's
+    predicted time (the recorded median at the nearest timed shape), the measured time of the
+    run that produced C, and null residual without verify mode; unknown flag bits refused."""
+    import json
+    c = host_ctx()
+    L, ctx = c.L, c.ctx
+    assert L.cmp_set_flags(ctx, 4) == pa.CMP_EINVAL
+    vid = c.register_builtin("host_f32")
+    st, fake = c.variant_register("gemm", "fake_fast", pa.CMP_TARGET_HOST, _noop, 1e-2)
+    assert st == 0
+    c.history_add(32, 32, 32, vid, 5, 0.25)      # ms -> 250 us
+    c.history_add(32, 32, 32, fake, 5, 0.5)
+    c.history_add(64, 64, 64, vid, 5, 1.5)
+    path = str(tmp_path / "calls.jsonl")
+    assert c.set_log_file(path) is None
+    c.set_flags(pa.CMP_FLAG_LOG)
+    A, B = synth.gemm_operands(33, 31, 30, seed=3)
+    Cm = np.zeros((33, 31), np.float32)
+    assert c.gemm_raw(_host_gemm_args(A, B, Cm), 1e-2, stream=0) == (0, vid)   # nearest: 32^3
+    assert c.gemm_raw(_host_gemm_args(A, B, Cm), 1e-5, stream=0) == (0, vid)   # only host_f32
+    c.force_variant(fake)
+    assert c.gemm_raw(_host_gemm_args(A, B, Cm), 1e-2, stream=0) == (0, fake)
+    c.force_variant(-1)
+    c.set_flags(0)
+    assert c.gemm_raw(_host_gemm_args(A, B, Cm), 1e-2, stream=0)[0] == 0     # not logged
+    c.log_flush()
+    recs = [json.loads(l) for l in open(path).read().splitlines()]
+    assert [r["call"] for r in recs] == [1, 2, 3]
+    r0, r1, r2 = recs
+    assert (r0["M"], r0["N"], r0["K"], r0["tol"]) == (33, 31, 30, 1e-2)
+    assert r0["selector"] == "nn" and r0["variant"] == "host_f32" and r0["id"] == vid
+    assert r0["predicted_us"] == pytest.approx(250.0)
+    assert r0["measured_us"] > 0 and r0["residual"] is None and r0["fallbacks"] == 0
+    assert r1["selector"] == "only" and r1["predicted_us"] is None and r1["tol"] == 1e-5
+    assert r2["selector"] == "forced" and r2["variant"] == "fake_fast" and r2["measured_us"] >= 0
+    # a new sink: later records go there, the old file is left as it was
+    path2 = str(tmp_path / "more.jsonl")
+    c.set_log_file(path2)
+    c.set_flags(pa.CMP_FLAG_LOG)
+    c.gemm_raw(_host_gemm_args(A, B, Cm), 1e-2, stream=0)
+    c.close()                                     # terminate writes what is pending
+    assert len(open(path).read().splitlines()) == 3
+    assert [json.loads(l)["call"] for l in open(path2).read().splitlines()] == [4]
+    d = host_ctx()
+    assert d.L.cmp_set_log_file(d.ctx, str(tmp_path / "no" / "such" / "dir.jsonl").encode()) == pa.CMP_EINVAL
+    d.close()
+
+
+def test_call_log_from_environment(tmp_path):
+    path = str(tmp_path / "env.jsonl")
+    code = r"""
+import numpy as np, paper_2311_03543_amd as pa, synth
+c = pa.Compar(-1)
+vid = c.register_builtin("host_f32")
+A, B = synth.gemm_operands(8, 8, 8, seed=0)
+Cm = np.zeros((8, 8), np.float32)
+a = pa.cmp_gemm_args(8, 8, 8, 8, 8, 8, 1.0, 0.0, A.ctypes.data, B.ctypes.data, Cm.ctypes.data)
+print(c.gemm_raw(a, 1e-3, stream=0))
+c.close()
+"""
+    env = dict(os.environ, COMPAR_LOG=path, PYTHONPATH=ROOT)
+    subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, check=True)
+    import json
+    recs = [json.loads(l) for l in open(path).read().splitlines()]
+    assert len(recs) == 1 and recs[0]["variant"] == "host_f32" and recs[0]["M"] == 8
