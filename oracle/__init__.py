@@ -20,7 +20,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# COMPAR_SANITIZED=1: the AddressSanitizer/UBSan build (oracle/build.py, sanitize=True)
+_LIB_PATH = os.path.join(_HERE, "liboracle_san.so" if os.environ.get("COMPAR_SANITIZED") == "1"
+                         else "liboracle.so")
 _lib = None
 
 _f32p = np.ctypeslib.ndpointer(dtype=np.float32, flags="C_CONTIGUOUS")
@@ -38,7 +40,7 @@ def lib():
         return _lib
     if not os.path.exists(_LIB_PATH):
         from . import build as _b
-        _b.build()
+        _b.build(sanitize=os.environ.get("COMPAR_SANITIZED") == "1")
     L = C.CDLL(_LIB_PATH)
     gemm_args = [_i64, _i64, _i64, C.c_float, _f32p, _i64, _f32p, _i64, C.c_float,
                  C.c_void_p, _i64, _f64p, _i64]

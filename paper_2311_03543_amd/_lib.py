@@ -10,7 +10,8 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libcompar.so")
+# COMPAR_SANITIZED=1 loads the host-sanitized build (build.py, sanitize=True) instead
+LIB_PATH = os.path.join(HERE, "libcompar_san.so" if os.environ.get("COMPAR_SANITIZED") == "1" else "libcompar.so")
 
 # status codes (cmp_status)
 CMP_OK = 0

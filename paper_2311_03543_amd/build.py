@@ -1,4 +1,11 @@
-"""Build libcompar.so (the C-ABI library: host runtime + gfx950 HIP kernels) in-tree with hipcc."""
+"""Build libcompar.so (the C-ABI library: host runtime + gfx950 HIP kernels) in-tree with hipcc.
+
+`build(sanitize=True)` builds libcompar_san.so instead: the same sources with AddressSanitizer
+and UndefinedBehaviorSanitizer on the host code only (every -fsanitize= behind -Xarch_host;
+the gfx950 device code is built as usual).  It needs clang's ASan runtime loaded first
+(LD_PRELOAD=`sanitizer_runtime()`); the binding loads it when COMPAR_SANITIZED=1
+(tests/run_sanitized.py runs the CPU test suite that way).
+"""
 from __future__ import annotations
 
 import concurrent.futures as cf
@@ -11,6 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcompar.so")
+LIB_SAN = os.path.join(HERE, "libcompar_san.so")
 SOURCES = ["runtime.cpp", "gemm_f32_simt.hip", "gemm_mfma.hip", "prepass.hip", "mx6.hip", "freivalds.hip",
            "mlp.hip", "host_gemm.cpp"]
 ARCH = "gfx950"
@@ -31,8 +39,29 @@ def common_flags() -> list[str]:
             "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-Wall", "-Wno-unused-result"]
 
 
-def _compile(src: str, out: str) -> tuple[str, str]:
+SAN_HOST = ["address", "undefined"]
+
+
+def sanitize_flags() -> list[str]:
+    """Host-only sanitizer flags for hipcc: each -fsanitize= directly after -Xarch_host."""
+    f = []
+    for s in SAN_HOST:
+        f += ["-Xarch_host", f"-fsanitize={s}"]
+    return f + ["-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer",
+                "-Xarch_host", "-g"]
+
+
+def sanitizer_runtime() -> str:
+    """Path of clang's shared ASan runtime (to preload into an uninstrumented python)."""
+    r = subprocess.run([hipcc(), "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True,
+                       check=True)
+    return r.stdout.strip()
+
+
+def _compile(src: str, out: str, sanitize: bool = False) -> tuple[str, str]:
     cmd = [hipcc(), "-x", "hip", "-c", os.path.join(CSRC, src), "-o", out] + common_flags()
+    if sanitize:
+        cmd += sanitize_flags()
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
@@ -40,25 +69,28 @@ def _compile(src: str, out: str) -> tuple[str, str]:
     return src, warn
 
 
-def build(verbose: bool = False, jobs: int = 6) -> str:
+def build(verbose: bool = False, jobs: int = 6, sanitize: bool = False) -> str:
+    lib = LIB_SAN if sanitize else LIB
     tmp = tempfile.mkdtemp(prefix="compar_build_")
     try:
         objs = [os.path.join(tmp, s + ".o") for s in SOURCES]
         with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-            for src, warn in ex.map(_compile, SOURCES, objs):
+            for src, warn in ex.map(lambda so: _compile(so[0], so[1], sanitize), zip(SOURCES, objs)):
                 if verbose:
                     print(f"compiled {src}")
                 if warn and verbose:
                     print(warn)
-        out = LIB + ".tmp"
+        out = lib + ".tmp"
         cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", out] + objs
+        if sanitize:
+            cmd += ["-Xarch_host", "-shared-libsan"] + sanitize_flags()
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"link failed:\n{r.stderr}")
-        os.replace(out, LIB)
+        os.replace(out, lib)
     finally:
         shutil.rmtree(tmp, ignore_errors=True)
-    return LIB
+    return lib
 
 
 if __name__ == "__main__":

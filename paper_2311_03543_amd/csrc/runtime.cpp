@@ -1433,6 +1433,7 @@ CMP_API int cmp_gemm(cmp_ctx* c, const cmp_gemm_args* a, double tol, void* strea
     const bool logging = (c->flags & CMP_FLAG_LOG) != 0;
     hipEvent_t ev_a = nullptr, ev_b = nullptr;
     double host_us = NAN;
+    bool capturing = false;
     const int fallbacks0 = c->fallbacks;
     struct EvGuard {   // events not handed to a log record go back to the pool
         cmp_ctx* c;
@@ -1446,9 +1447,10 @@ CMP_API int cmp_gemm(cmp_ctx* c, const cmp_gemm_args* a, double tol, void* strea
     auto timed_run = [&](int vid) -> int {
         const bool hip_v = f->variants[vid].target == CMP_TARGET_HIP && c->gpu;
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-        if (logging && hip_v && hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone) {
-            if (!ev_a) ev_a = kev_get(c);
-            if (ev_a) (void)hipEventRecord(ev_a, s);
+        if (logging && hip_v && hipStreamIsCapturing(s, &cs) == hipSuccess) {
+            capturing = cs != hipStreamCaptureStatusNone;
+            if (!capturing && !ev_a) ev_a = kev_get(c);
+            if (!capturing && ev_a) (void)hipEventRecord(ev_a, s);
         }
         const auto t0 = std::chrono::steady_clock::now();
         const int rst = run_variant(c, *f, vid, a, stream);
@@ -1476,7 +1478,7 @@ CMP_API int cmp_gemm(cmp_ctx* c, const cmp_gemm_args* a, double tol, void* strea
                                                  f->variants[vid].name, pred, residual,
                                                  c->fallbacks - fallbacks0, ev_a, ev_b, host_us});
         ev_a = ev_b = nullptr;
-        log_drain(c, false);
+        if (!capturing) log_drain(c, false);   // no event queries inside a capture
     };
     float* c0 = nullptr;
     double* xdev = nullptr;

@@ -265,3 +265,48 @@ def test_mlp_selector_uses_network(cx):
     cx.mlp_set_norm(np.zeros(4), np.ones(4), np.zeros(4), np.ones(4))
     cx.selector_set(pa.CMP_SEL_MLP)
     assert cx.select_batch([(100, 200, 300, 1e-2), (100, 200, 300, 1e-3), (5000, 5000, 64, 1e-5)]) == [3, 2, 1]
+
+
+def test_call_log_gpu(cx, tmp_path):
+    """CMP_FLAG_LOG on the GPU: measured time from the call's HIP event pair, the selector's
+    predicted time from the history, the verify-mode residual, and no measurement for a call
+    made during stream capture."""
+    import json
+    import torch
+    import paper_2311_03543_amd as pa
+    M, N, K = 320, 256, 384
+    A, B = synth.gemm_operands(M, N, K, seed=5)
+    dA, dB = dev(A), dev(B)
+    dC = torch.zeros((M, N), device="cuda")
+    for vid in range(4):
+        med, mn, mean = cx.time_variant(vid, dA, dB, dC, warmup=1, reps=3)
+        cx.history_add(M, N, K, vid, 3, med, mn, mean)
+    path = str(tmp_path / "gpu_calls.jsonl")
+    cx.set_log_file(path)
+    cx.set_flags(pa.CMP_FLAG_LOG)
+    say("  logged cmp_gemm x3 (plain, verify)")
+    for tol in (1e-2, 1e-5):
+        cx.gemm(dA, dB, dC, tol=tol)
+    cx.set_flags(pa.CMP_FLAG_LOG | pa.CMP_FLAG_VERIFY)
+    vchosen = cx.gemm(dA, dB, dC, tol=1e-3)
+    cx.set_flags(pa.CMP_FLAG_LOG)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        cx.gemm(dA, dB, dC, tol=1e-2)          # warm: the capture only enqueues kernels
+        s.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            cx.gemm(dA, dB, dC, tol=1e-2)
+    g.replay()
+    torch.cuda.synchronize()
+    cx.log_flush()
+    recs = [json.loads(l) for l in open(path).read().splitlines()]
+    assert [r["call"] for r in recs] == [1, 2, 3, 4, 5]
+    T = {r[3]: r[5] for r in cx.history()}
+    for r in recs[:4]:
+        assert r["selector"] == "nn" and r["measured_us"] > 0 and (r["M"], r["N"], r["K"]) == (M, N, K)
+        assert r["predicted_us"] == pytest.approx(1e3 * T[r["id"]], rel=1e-6)
+    assert recs[0]["residual"] is None and recs[1]["residual"] is None
+    assert recs[2]["id"] == vchosen and 0 <= recs[2]["residual"] <= 1e-3
+    assert recs[4]["measured_us"] is None and recs[4]["variant"] == recs[3]["variant"]
+    assert oracle.relfro(host(dC), oracle.gemm(A, B)) <= 1e-2
