@@ -36,6 +36,15 @@
  * variants whose bound is <= tol (the "context match" step of OpenMP's
  * declare variant, which COMPAR extends, Sec. 2.1), and among those the
  * selector picks the one with the lowest measured or predicted time.
+ * The built-in bounds are the errors the variants meet on operands with
+ * independent entries (normal, uniform, and normal(0,1) * 2^u with u drawn per
+ * entry in [-20, 20]) up to K = 8192, NOT worst-case bounds: correlated
+ * operands keep the rounding errors from averaging out.  Constant operands
+ * A = B = c give fp8r 3.78e-3 (c = 1.033203125), bf16x3 2.94e-5
+ * (c = 1.0039134), and K = 8192 equal products summed in one FP32 accumulator
+ * drift by up to ~1e-4 (every variant accumulates in FP32).  A caller that
+ * needs the tolerance guaranteed sets CMP_FLAG_VERIFY: the FP64 probe then
+ * checks every result against tol and falls back to a tighter variant.
  *
  * Conventions for every function:
  *   - Returns a cmp_status; CMP_OK is 0 and every error is negative.  No C++
@@ -53,7 +62,16 @@
  *     GPU variants only enqueue kernels and stream/event waits, so they can be
  *     captured into a graph (stream capture) and replayed; verify mode and the
  *     host variant synchronise and cannot.
- *   - A cmp_ctx is not thread-safe: use one context per host thread.
+ *   - A cmp_ctx is not thread-safe: use one context per host thread.  It also
+ *     serves one stream at a time: all image variants of a context share one
+ *     device workspace (their pre-pass images), so calls on two streams of
+ *     one context must be ordered by the caller (e.g. an event wait).
+ *   - The workspace grows on demand: a call that needs more than the current
+ *     size synchronises the device, frees the old buffer and allocates a
+ *     larger one.  A graph captured earlier still refers to the old buffer,
+ *     so growth invalidates captured graphs: call cmp_reserve for the largest
+ *     shape before capturing; a reservation pins the workspace, and a later
+ *     call that would need more fails with CMP_ENOMEM instead of moving it.
  *   - Name strings are copied on registration.
  */
 #ifndef COMPAR_H
@@ -239,6 +257,13 @@ int cmp_log_flush(cmp_ctx *ctx);
  * shape, so the workspace grows by splits x M x N floats (CMP_ENOMEM if that
  * allocation fails). */
 int cmp_set_split_k(cmp_ctx *ctx, int splits);
+/* Size the shared device workspace for every enabled built-in GPU variant of
+ * "gemm" on an M x N x K product (pre-pass images plus the split-K partial sums
+ * of the current split setting) and pin it: later calls never reallocate it,
+ * and a call that would need more fails with CMP_ENOMEM (so graphs captured
+ * after the reservation stay valid).  M = N = K = 0 releases the pin (the
+ * buffer is kept).  Synchronises the device when the buffer grows. */
+int cmp_reserve(cmp_ctx *ctx, int64_t M, int64_t N, int64_t K);
 /* Register an optional built-in variant of "gemm" by name: "fp6x3" (GPU
  * contexts only) or "host_f32" (CMP_TARGET_HOST).  It takes the next free id
  * (*id, may be NULL).  CMP_EDUP if already registered, CMP_ENOTFOUND for an

@@ -163,6 +163,9 @@ class Compar:
     def log_flush(self):
         self._check(self.L.cmp_log_flush(self.ctx))
 
+    def reserve(self, M: int, N: int, K: int):
+        self._check(self.L.cmp_reserve(self.ctx, M, N, K))
+
     def register_builtin(self, name: str) -> int:
         """Register an optional built-in variant ("fp6x3" or "host_f32"); returns its id."""
         vid = C.c_int(-1)

@@ -90,6 +90,7 @@ SIGNATURES = {
     "cmp_selector_set": (_I, [_P, _I]),
     "cmp_set_flags": (_I, [_P, C.c_uint32]),
     "cmp_set_log_file": (_I, [_P, C.c_char_p]),
+    "cmp_reserve": (_I, [_P, C.c_int64, C.c_int64, C.c_int64]),
     "cmp_log_flush": (_I, [_P]),
     "cmp_set_split_k": (_I, [_P, _I]),
     "cmp_register_builtin": (_I, [_P, _S, _IP]),

@@ -144,6 +144,7 @@ struct cmp_ctx {
     // device memory owned by the library
     void* ws = nullptr;
     size_t ws_bytes = 0;
+    bool ws_pinned = false;  // cmp_reserve: never reallocate the workspace
     void* vws = nullptr;     // verify-mode workspace (C0 copy, probe vector, partial sums)
     void* hbuf = nullptr;    // pinned host staging of the host variant (A | B | C)
     size_t hbuf_bytes = 0;
@@ -1000,6 +1001,9 @@ int do_select_batch(cmp_ctx* c, Interface* f, int n, const cmp_context* q, int* 
 
 int ensure_ws(cmp_ctx* c, size_t need) {
     if (need <= c->ws_bytes) return CMP_OK;
+    if (c->ws_pinned)
+        return fail(c, CMP_ENOMEM, "call needs %zu workspace bytes, %zu are reserved (cmp_reserve)", need,
+                    c->ws_bytes);
     // in-flight work on any stream may still read the old buffer
     HIP_TRY(c, hipDeviceSynchronize());
     if (c->ws) HIP_TRY(c, hipFree(c->ws));
@@ -1351,6 +1355,33 @@ CMP_API int cmp_set_split_k(cmp_ctx* c, int splits) {
     if (splits < 0 || splits > kMaxForcedSplits)
         return fail(c, CMP_EINVAL, "split count must be 0 (automatic) or 1..%d", kMaxForcedSplits);
     c->split_k = splits;
+    return CMP_OK;
+}
+
+CMP_API int cmp_reserve(cmp_ctx* c, int64_t M, int64_t N, int64_t K) {
+    if (!c) return CMP_EINVAL;
+    if (M < 0 || N < 0 || K < 0) return fail(c, CMP_EINVAL, "negative dimension");
+    if (!c->gpu) return fail(c, CMP_EUNSUPPORTED, "cmp_reserve needs a GPU context");
+    if (M == 0 && N == 0 && K == 0) {
+        c->ws_pinned = false;
+        return CMP_OK;
+    }
+    Interface* f = find_iface(c, kGemm);
+    cmp_gemm_args a{};
+    a.M = std::max<int64_t>(M, 1);
+    a.N = std::max<int64_t>(N, 1);
+    a.K = std::max<int64_t>(K, 1);
+    a.lda = a.K;
+    a.ldb = a.ldc = a.N;
+    size_t need = 0;
+    for (size_t i = 0; i < f->variants.size(); ++i) {
+        const Variant& v = f->variants[i];
+        if ((f->mask >> i & 1) && v.target == CMP_TARGET_HIP && v.ws) need = std::max(need, v.ws(&a, v.user));
+    }
+    c->ws_pinned = false;
+    const int st = need ? ensure_ws(c, need) : CMP_OK;
+    if (st) return st;
+    c->ws_pinned = true;
     return CMP_OK;
 }
 

@@ -328,6 +328,10 @@ def test_split_k_and_optional_builtin_argument_checks():
     assert L.cmp_register_builtin(ctx, b"fp4", C.byref(vid)) == pa.CMP_ENOTFOUND
     assert L.cmp_register_builtin(ctx, None, C.byref(vid)) == pa.CMP_EINVAL
     assert L.cmp_register_builtin(None, b"fp6x3", C.byref(vid)) == pa.CMP_EINVAL
+    # workspace reservation needs a GPU context; negative sizes are refused
+    assert L.cmp_reserve(ctx, 64, 64, 64) == pa.CMP_EUNSUPPORTED
+    assert L.cmp_reserve(ctx, -1, 64, 64) == pa.CMP_EINVAL
+    assert L.cmp_reserve(None, 1, 1, 1) == pa.CMP_EINVAL
     # the MX FP6 quantisation entry needs a GPU context
     assert L.cmp_quant_mx6(ctx, 4, 4, None, 4, 0, None, None, None, None, None) == pa.CMP_EUNSUPPORTED
     c.close()

@@ -53,3 +53,45 @@ def test_captured_gemm_replays(name, M, N, K):
         del g
     finally:
         cx.close()
+
+
+def test_reserved_workspace_keeps_captured_graph_valid():
+    """cmp_reserve pins the shared workspace: a later eager call that would need more fails
+    with CMP_ENOMEM instead of freeing the buffer a captured graph replays into; releasing
+    the pin lets the workspace grow again."""
+    import torch
+    import paper_2311_03543_amd as pa
+    cx = pa.Compar(0)
+    try:
+        M, N, K = 512, 384, 640
+        cx.force_variant(cx.variant_find("bf16x3"))
+        cx.reserve(M, N, K)
+        A0, B0 = synth.gemm_operands(M, N, K, seed=77)
+        dA, dB = torch.from_numpy(A0).cuda(), torch.from_numpy(B0).cuda()
+        dC = torch.zeros((M, N), device="cuda")
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            say("  reserved workspace: eager warm-up and capture of bf16x3 512x384x640")
+            cx.gemm(dA, dB, dC, tol=1e-5, stream=s)
+            s.synchronize()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=s):
+                cx.gemm(dA, dB, dC, tol=1e-5, stream=s)
+        torch.cuda.synchronize()
+        big = [torch.zeros((2048, 2048), device="cuda") for _ in range(3)]
+        with pytest.raises(pa.ComparError) as e:
+            cx.gemm(big[0], big[1], big[2], tol=1e-5)
+        assert e.value.status == pa.CMP_ENOMEM
+        dA.mul_(0.5)
+        dC.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        err = oracle.relfro(host(dC), oracle.gemm(host(dA), B0))
+        assert err <= 1e-5
+        cx.reserve(0, 0, 0)                       # pin released: the workspace may grow again
+        cx.gemm(big[0], big[1], big[2], tol=1e-5)
+        torch.cuda.synchronize()
+        del g
+    finally:
+        cx.close()
