@@ -6,7 +6,8 @@ Bars:
   * random operands: relative Frobenius error within the variant's stated bound,
     and every entry within the rigorous a-priori rounding bound of its arithmetic
     (gamma_n times the absolute product of the operands the variant multiplies,
-    which the oracle computes from its own encodings of A and B);
+    which the oracle computes from its own encodings of A and B; for fp8r also the
+    truncation of products inside the scaled FP8 MFMA, fp8_mfma_truncation);
   * BLAS edge cases (beta == 0 ignores C, alpha == 0 ignores A and B, empty
     and ragged shapes, padded and misaligned leading dimensions);
   * bitwise repeatability of each variant.
@@ -82,6 +83,43 @@ def test_integer_exact(cx, name, M, N, K):
 
 # ---- random operands: stated bound and entrywise rounding bound ----------------
 
+def e4m3_place(codes, scale_bytes):
+    """Exponent of the leading binary place of each E4M3 code's dequantised value (normal
+    codes: field - 7; subnormal codes: -6, the place of 0.m; zero: -inf), plus its 128 x 128
+    tile's scale exponent (E8M0 byte - 127)."""
+    field = (codes >> 3) & 15
+    e = np.where(field == 0, -6.0, field.astype(np.float64) - 7.0)
+    e = np.where((codes & 0x7f) == 0, -np.inf, e)
+    s = np.repeat(np.repeat(scale_bytes.astype(np.float64) - 127.0, 128, 0), 128, 1)
+    return e + s[:codes.shape[0], :codes.shape[1]]
+
+
+def fp8_mfma_truncation(ca, sa, xa, cb, sb, xb):
+    """Bound on what the scaled FP8 MFMA loses on X_a X_b (codes ca / cb, scale bytes sa / sb,
+    dequantised values xa (M x K) and xb (K x N)).  Measured on gfx950 with in-bounds probes of
+    v_mfma_scale_f32_32x32x64_f8f6f4: a single product plus the accumulator is rounded once,
+    but within one instruction every product is truncated toward zero to a multiple of
+    2^(E - 13), E the largest sum of the two operands' leading-place exponents among its 64
+    products (exact cancellation of the large products still leaves the small ones
+    truncated).  Per 64-value K block each entry therefore loses at most
+    min(sum |products|, 64 * 2^(Ea + Eb - 12)), with Ea, Eb the row's and the column's largest
+    leading-place exponents in the block (twice the measured grid, as a margin)."""
+    M, K = xa.shape
+    N = xb.shape[1]
+    ea, eb = e4m3_place(ca, sa), e4m3_place(cb, sb)
+    out = np.zeros((M, N))
+    for k0 in range(0, K, 64):
+        k1 = min(k0 + 64, K)
+        emax_a = ea[:, k0:k1].max(axis=1)
+        emax_b = eb[k0:k1, :].max(axis=0)
+        with np.errstate(invalid="ignore"):
+            grid = np.exp2(emax_a[:, None] + emax_b[None, :] - 12.0)
+        grid = np.nan_to_num(grid, nan=0.0, posinf=0.0)
+        absblk = np.abs(xa[:, k0:k1]).astype(np.float64) @ np.abs(xb[k0:k1, :]).astype(np.float64)
+        out += np.minimum(absblk, (k1 - k0) * grid)
+    return out
+
+
 def variant_reference(name, A, B):
     """(product of the operands the variant multiplies, entrywise rounding bound)."""
     M, K = A.shape
@@ -108,7 +146,13 @@ def variant_reference(name, A, B):
         assert all(np.array_equal(x.astype(np.float64), y) for x, y in zip(f, (a1, a2, b1, b2)))
         prod = sum(oracle.gemm(x, y) for x in f[:2] for y in f[2:])
         mag = sum(oracle.absgemm(x, y) for x in f[:2] for y in f[2:])
-        return prod, gamma(4 * K) * mag
+        # FP32 roundings: at most one per 16 K values of each of the four products, plus the
+        # split-K reduction; and the scaled FP8 MFMA's own truncation (fp8_mfma_truncation)
+        nkb = -(-K // 64)
+        trunc = sum(fp8_mfma_truncation(ca, sa, xa, cb, sb, xb)
+                    for ca, sa, xa in ((qa["q"], qa["qscale"], f[0]), (qa["rq"], qa["rscale"], f[1]))
+                    for cb, sb, xb in ((qb["q"], qb["qscale"], f[2]), (qb["rq"], qb["rscale"], f[3])))
+        return prod, gamma(16 * nkb + 8) * mag + trunc
     if name == "fp6x3":
         qa, qb = oracle.quant_mx6(A), oracle.quant_mx6(np.ascontiguousarray(B.T))
         ah = oracle.dequant_mx6(qa["q"], qa["qscale"])
