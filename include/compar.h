@@ -71,7 +71,9 @@
  *     larger one.  A graph captured earlier still refers to the old buffer,
  *     so growth invalidates captured graphs: call cmp_reserve for the largest
  *     shape before capturing; a reservation pins the workspace, and a later
- *     call that would need more fails with CMP_ENOMEM instead of moving it.
+ *     variant that would need more fails with CMP_ENOMEM instead of moving it
+ *     (cmp_gemm then falls back to another admissible variant, see
+ *     cmp_reserve).
  *   - Name strings are copied on registration.
  */
 #ifndef COMPAR_H
@@ -259,10 +261,13 @@ int cmp_log_flush(cmp_ctx *ctx);
 int cmp_set_split_k(cmp_ctx *ctx, int splits);
 /* Size the shared device workspace for every enabled built-in GPU variant of
  * "gemm" on an M x N x K product (pre-pass images plus the split-K partial sums
- * of the current split setting) and pin it: later calls never reallocate it,
- * and a call that would need more fails with CMP_ENOMEM (so graphs captured
- * after the reservation stay valid).  M = N = K = 0 releases the pin (the
- * buffer is kept).  Synchronises the device when the buffer grows. */
+ * of the current split setting) and pin it: later calls never reallocate it
+ * (so graphs captured after the reservation stay valid).  A variant that would
+ * need more fails with CMP_ENOMEM: cmp_gemm_variant returns that status, while
+ * cmp_gemm treats it like any failing variant and falls back once to the best
+ * other admissible variant (f32_simt needs no workspace), failing with
+ * CMP_ENOMEM only if that one does not fit either.  M = N = K = 0 releases the
+ * pin (the buffer is kept).  Synchronises the device when the buffer grows. */
 int cmp_reserve(cmp_ctx *ctx, int64_t M, int64_t N, int64_t K);
 /* Register an optional built-in variant of "gemm" by name: "fp6x3" (GPU
  * contexts only) or "host_f32" (CMP_TARGET_HOST).  It takes the next free id
@@ -367,7 +372,8 @@ int cmp_mlp_fit_history(cmp_ctx *ctx, int steps, float lr, uint64_t seed, float 
 int cmp_freivalds(cmp_ctx *ctx, const cmp_gemm_args *args, const float *c0, const double *probe,
                   void *stream, double *estimate);
 /* Probe estimate of the last cmp_gemm in verify mode, and the number of
- * fallbacks verify mode has taken on this context. */
+ * fallbacks cmp_gemm has taken on this context (re-runs after a failing
+ * variant and after a failed verify-mode probe). */
 int cmp_last_verify(cmp_ctx *ctx, double *estimate, int *fallbacks);
 
 /* ---- operand pre-pass (exposed for bit-exact checking) ------------------ */

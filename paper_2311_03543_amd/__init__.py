@@ -11,7 +11,7 @@ import ctypes as C
 from typing import Callable, Sequence
 
 from . import _lib
-from ._lib import (CMP_EDUP, CMP_EHIP, CMP_EINVAL, CMP_ENODATA, CMP_ENOTFOUND,  # noqa: F401
+from ._lib import (CMP_EDUP, CMP_EHIP, CMP_EINVAL, CMP_ENODATA, CMP_ENOMEM, CMP_ENOTFOUND,  # noqa: F401
                    CMP_ENOVARIANT, CMP_ESIG, CMP_EUNSUPPORTED, CMP_ECHECK, CMP_OK, CMP_F32,
                    CMP_F64, CMP_I32, CMP_I64, CMP_BF16, CMP_F8E4M3, CMP_READ, CMP_WRITE,
                    CMP_READWRITE, CMP_SEL_MLP, CMP_SEL_NN, CMP_SEL_STATIC, CMP_TARGET_HIP,

@@ -80,9 +80,15 @@ def test_reserved_workspace_keeps_captured_graph_valid():
                 cx.gemm(dA, dB, dC, tol=1e-5, stream=s)
         torch.cuda.synchronize()
         big = [torch.zeros((2048, 2048), device="cuda") for _ in range(3)]
+        bf16x3 = cx.variant_find("bf16x3")
         with pytest.raises(pa.ComparError) as e:
-            cx.gemm(big[0], big[1], big[2], tol=1e-5)
+            cx.gemm_variant(bf16x3, big[0], big[1], big[2])
         assert e.value.status == pa.CMP_ENOMEM
+        # the selected call falls back to the best other admissible variant, which needs no
+        # workspace (f32_simt at 1e-5), and still runs
+        fb0 = cx.last_verify()[1]
+        assert cx.gemm(big[0], big[1], big[2], tol=1e-5) == cx.variant_find("f32_simt")
+        assert cx.last_verify()[1] == fb0 + 1
         dA.mul_(0.5)
         dC.zero_()
         torch.cuda.synchronize()
@@ -90,7 +96,7 @@ def test_reserved_workspace_keeps_captured_graph_valid():
         err = oracle.relfro(host(dC), oracle.gemm(host(dA), B0))
         assert err <= 1e-5
         cx.reserve(0, 0, 0)                       # pin released: the workspace may grow again
-        cx.gemm(big[0], big[1], big[2], tol=1e-5)
+        assert cx.gemm(big[0], big[1], big[2], tol=1e-5) == bf16x3
         torch.cuda.synchronize()
         del g
     finally:
