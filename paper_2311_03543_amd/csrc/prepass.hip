@@ -10,8 +10,10 @@
 //                 Scale bytes are E8M0 exponents 127 - e, the dequantisation
 //                 factor the scaled MFMA applies.
 //
-// All kernels are HBM-bound (4 bytes read, 2 or 4 written per element); the
-// B operand is transposed through LDS so that the written image is N x K.
+// All kernels are HBM-bound (4 bytes read, 2 or 4 written per element).  The
+// written B images are N x K: the bf16 split transposes B through LDS, the
+// E4M3 quantisation in registers (each lane loads the K values of its own
+// output rows).
 #include "common.h"
 #include "kernels.h"
 
@@ -183,73 +185,95 @@ __device__ __forceinline__ float e4m3_sat(float s) {
     if (__builtin_isinf(s)) return __builtin_nanf("");
     return fabsf(s) > 448.f ? copysignf(448.f, s) : s;
 }
-// Four floats -> four E4M3 bytes (v_cvt_pk_fp8_f32, round to nearest even).
+// Four floats -> four E4M3 bytes, byte j = value j (v_cvt_pk_fp8_f32, round
+// to nearest even; the inputs are already within the finite range or NaN).
 __device__ __forceinline__ uint32_t e4m3x4(float a, float b, float c, float d) {
-    int w = __builtin_amdgcn_cvt_pk_fp8_f32(e4m3_sat(a), e4m3_sat(b), 0, false);
-    w = __builtin_amdgcn_cvt_pk_fp8_f32(e4m3_sat(c), e4m3_sat(d), w, true);
+    int w = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
+    w = __builtin_amdgcn_cvt_pk_fp8_f32(c, d, w, true);
     return (uint32_t)w;
 }
-__device__ __forceinline__ float e4m3_byte_val(uint32_t word, int byte) {
-    switch (byte) {
-        case 0: return __builtin_amdgcn_cvt_f32_fp8((int)word, 0);
-        case 1: return __builtin_amdgcn_cvt_f32_fp8((int)word, 1);
-        case 2: return __builtin_amdgcn_cvt_f32_fp8((int)word, 2);
-        default: return __builtin_amdgcn_cvt_f32_fp8((int)word, 3);
-    }
-}
 
-__device__ __forceinline__ float block_max(float v, float* red, bool& any_nan_inout) {
-    // NaN propagates: any NaN in the block makes the result NaN.
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    int nan_flag = any_nan_inout ? 1 : 0;
+// Workgroup maximum of a 32-bit key; `slot` holds 4 words of LDS used by this
+// call site only, so consecutive calls need no barrier between them.
+__device__ __forceinline__ uint32_t block_umax(uint32_t v, uint32_t* slot) {
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        v = fmaxf(v, __shfl_xor(v, off));
-        nan_flag |= __shfl_xor(nan_flag, off);
-    }
+    for (int off = 32; off > 0; off >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, off));
+    if ((threadIdx.x & 63) == 0) slot[threadIdx.x >> 6] = v;
     __syncthreads();
-    if (lane == 0) {
-        red[wave] = v;
-        red[4 + wave] = nan_flag ? 1.f : 0.f;
+    return max(max(slot[0], slot[1]), max(slot[2], slot[3]));
+}
+__device__ __forceinline__ uint32_t mag_bits(float x) { return __builtin_bit_cast(uint32_t, x) & 0x7fffffffu; }
+
+// First level of one output row's 16 values: q codes (4 words) and the
+// residuals x - q 2^-e (rounded once, by the fused multiply-add), which
+// replace the values.  SPECIAL: the tile holds an infinity or NaN (then
+// e = 0): out-of-range values saturate, non-finite ones encode as NaN and
+// leave a zero residual.  Returns the row's largest residual magnitude bits.
+template <bool SPECIAL>
+__device__ __forceinline__ uint32_t level1(float (&v)[16], uint32_t (&qw)[4], int e, float inv) {
+    uint32_t rmax = 0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        float s[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            s[j] = ldexpf(v[4 * m + j], e);
+            if (SPECIAL) s[j] = e4m3_sat(s[j]);
+        }
+        qw[m] = e4m3x4(s[0], s[1], s[2], s[3]);
+        const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)qw[m], false);
+        const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)qw[m], true);
+        const float qv[4] = {lo[0], lo[1], hi[0], hi[1]};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const float x = v[4 * m + j];
+            float r = __builtin_fmaf(-qv[j], inv, x);
+            if (SPECIAL && !__builtin_isfinite(x)) r = 0.f;
+            v[4 * m + j] = r;
+            rmax = max(rmax, mag_bits(r));
+        }
     }
-    __syncthreads();
-    float m = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
-    const bool nan_any = (red[4] + red[5] + red[6] + red[7]) > 0.f;
-    any_nan_inout = nan_any;
-    return nan_any ? __builtin_nanf("") : m;
+    return rmax;
 }
 
-// One 128 x 128 output tile per workgroup of 256 lanes.  Lane t holds rows
-// 8 i + t/32 (i = 0..15) and columns 4 (t % 32) .. +3 of the X tile.  The
-// code images are row-major out_rows x out_cols (TILED false) or panel images
-// with out_cols bytes of K per row (TILED true).
+// One 128 x 128 tile per workgroup of 256 lanes; each lane ends up holding 16
+// consecutive K values of 4 output rows, so every image write is one 16-byte
+// store per row and level, in the image's final order (no LDS staging):
+//   TRANS false (X = A, rows x cols = M x K): lane t takes output rows
+//     t/8 + 32 i (i = 0..3), K values 16 (t % 8) .. +15 of each (four float4
+//     loads per row);
+//   TRANS true (X = B, rows x cols = K x N; output row = column of X): lane t
+//     takes X rows 16 (t % 8) .. +15 (its K values) of X columns 4 (t / 8)
+//     .. +3 (one float4 load per X row); eight consecutive lanes cover the
+//     128 K values of one output row.
+// The tile exponents come from integer maxima of the magnitudes' bit patterns:
+// non-negative floats order like their bits, and infinities and NaN sit above
+// every finite value, so the same maximum tells a non-finite tile (then
+// scale_exp gives e = 0, as for a NaN or infinite amax).  In a finite tile
+// |x 2^e| <= 448, so the encoder needs no saturation; x 2^e is exact whenever
+// its code is non-zero, and the residual x - q 2^-e is one FMA rounded once
+// (for a zero code it is x itself, and -0 - (-0) gives +0 as the definition
+// does).  The code images are row-major out_rows x out_cols (TILED false) or
+// panel images with out_cols bytes of K per row (TILED true).
 template <bool VEC, bool TRANS, bool TILED>
-__global__ __launch_bounds__(256) void quant_fp8_kernel(
-    int64_t rows, int64_t cols, const float* __restrict__ X, int64_t ldx, int64_t out_cols,
-    uint8_t* __restrict__ q, uint8_t* __restrict__ qscale, uint8_t* __restrict__ rq,
-    uint8_t* __restrict__ rscale) {
-    __shared__ float red[8];
-    __shared__ uint32_t tq[128][33];   // transposed staging: [col][row/4] words
-    __shared__ uint32_t tr[128][33];
+__device__ __forceinline__ void quant_tile(int64_t rows, int64_t cols, const float* __restrict__ X,
+                                           int64_t ldx, int64_t out_cols, uint8_t* __restrict__ q,
+                                           uint8_t* __restrict__ qscale, uint8_t* __restrict__ rq,
+                                           uint8_t* __restrict__ rscale, uint32_t* red) {
     const int t = threadIdx.x;
     const int64_t ot_cols = out_cols / 128;
     const int64_t nkb = out_cols / kPanelRowBytes;
-    auto out_off = [&](int64_t orow, int64_t ocol) -> int64_t {
-        return TILED ? panel_offset(orow, ocol, nkb) : orow * out_cols + ocol;
-    };
     const int64_t ot_r = blockIdx.x / ot_cols, ot_c = blockIdx.x % ot_cols;
     // tile origin in X coordinates
     const int64_t x_r0 = TRANS ? ot_c * 128 : ot_r * 128;
     const int64_t x_c0 = TRANS ? ot_r * 128 : ot_c * 128;
-    const int cl = (t & 31) * 4;
+    const int g = t & 7, h = t >> 3;
 
-    float v[16][4];
-    float amax = 0.f;
-    bool nan_seen = false;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int64_t r = x_r0 + 8 * i + (t >> 5);
-        const int64_t c = x_c0 + cl;
+    float v[4][16];                // [output row][K value]
+    // whole tile inside X with 16-byte aligned rows: unguarded float4 loads
+    const bool interior = VEC && x_r0 + 128 <= rows && x_c0 + 128 <= cols;
+    auto load4 = [&](const float* __restrict__ X, int64_t r, int64_t c, bool guard) -> float4 {
+        if (!guard) return *reinterpret_cast<const float4*>(X + r * ldx + c);
         float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
         if (r < rows) {
             const float* p = X + r * ldx + c;
@@ -262,90 +286,82 @@ __global__ __launch_bounds__(256) void quant_fp8_kernel(
                 if (c + 3 < cols) a.w = p[3];
             }
         }
-        v[i][0] = a.x; v[i][1] = a.y; v[i][2] = a.z; v[i][3] = a.w;
+        return a;
+    };
+    auto load_tile = [&](const float* __restrict__ X, bool guard) {
+        if (!TRANS) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const float m = fabsf(v[i][j]);
-            if (__builtin_isnan(m)) nan_seen = true;
-            else amax = fmaxf(amax, m);
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const float4 a = load4(X, x_r0 + h + 32 * i, x_c0 + 16 * g + 4 * u, guard);
+                    v[i][4 * u + 0] = a.x; v[i][4 * u + 1] = a.y;
+                    v[i][4 * u + 2] = a.z; v[i][4 * u + 3] = a.w;
+                }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const float4 a = load4(X, x_r0 + 16 * g + j, x_c0 + 4 * h, guard);
+                v[0][j] = a.x; v[1][j] = a.y; v[2][j] = a.z; v[3][j] = a.w;
+            }
         }
-    }
-    amax = block_max(amax, red, nan_seen);
-    const int e = scale_exp(amax);
+    };
+    if (interior) load_tile(X, false);
+    else load_tile(X, true);
+    uint32_t amax = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 16; ++j) amax = max(amax, mag_bits(v[i][j]));
+    amax = block_umax(amax, red);
+    const int e = scale_exp(__builtin_bit_cast(float, amax));
+    const float inv = ldexpf(1.f, -e);          // 2^-e, exact for e in [-127, 127]
 
-    // Residual r = x - q * 2^-e, rounded once to FP32.  In the scaled domain
-    // s - q is exact (s = x * 2^e is exact whenever q != 0), and scaling it
-    // back rounds once; this also avoids q * 2^-e overflowing FP32 when x is
-    // within rounding distance of FLT_MAX.  A zero code leaves r = x - (+-0),
-    // which is x except that -0 - (-0) = +0.
-    uint32_t qw[16];
-    float ramax = 0.f;
+    uint32_t qw[4][4], ramax = 0;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        float s[4];
+    for (int i = 0; i < 4; ++i) ramax = max(ramax, level1<false>(v[i], qw[i], e, inv));
+    if (amax >= 0x7f800000u) {                  // uniform: a tile with an infinity or NaN (rare)
+        // start again from x with the element-wise rules; the opaque copy of
+        // the base pointer keeps the compiler from holding the first pass's
+        // addresses live over the whole tile for this rare reload
+        const float* X2 = X;
+        asm volatile("" : "+s"(X2));
+        load_tile(X2, true);
+        ramax = 0;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) s[j] = ldexpf(v[i][j], e);
-        qw[i] = e4m3x4(s[0], s[1], s[2], s[3]);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const float qv = e4m3_byte_val(qw[i], j);
-            float r = 0.f;
-            if (__builtin_isfinite(v[i][j])) r = (qv == 0.f) ? v[i][j] - qv : ldexpf(s[j] - qv, -e);
-            v[i][j] = r;
-            ramax = fmaxf(ramax, fabsf(r));
-        }
+        for (int i = 0; i < 4; ++i) ramax = max(ramax, level1<true>(v[i], qw[i], e, inv));
     }
-    bool no_nan = false;
-    ramax = block_max(ramax, red, no_nan);
-    const int er = scale_exp(ramax);
-    uint32_t rw[16];
+    ramax = block_umax(ramax, red + 4);
+    const int er = scale_exp(__builtin_bit_cast(float, ramax));
+    uint32_t rw[4][4];
 #pragma unroll
-    for (int i = 0; i < 16; ++i)
-        rw[i] = e4m3x4(ldexpf(v[i][0], er), ldexpf(v[i][1], er), ldexpf(v[i][2], er),
-                       ldexpf(v[i][3], er));
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            rw[i][m] = e4m3x4(ldexpf(v[i][4 * m + 0], er), ldexpf(v[i][4 * m + 1], er),
+                              ldexpf(v[i][4 * m + 2], er), ldexpf(v[i][4 * m + 3], er));
 
     if (t == 0) {
         qscale[blockIdx.x] = (uint8_t)(127 - e);
         rscale[blockIdx.x] = (uint8_t)(127 - er);
     }
-    if (!TRANS) {
+    const int64_t ocol = ot_c * 128 + 16 * g;
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int64_t orow = ot_r * 128 + 8 * i + (t >> 5);
-            const int64_t ocol = ot_c * 128 + cl;
-            const int64_t o = out_off(orow, ocol);
-            *reinterpret_cast<uint32_t*>(q + o) = qw[i];
-            *reinterpret_cast<uint32_t*>(rq + o) = rw[i];
-        }
-    } else {
-        // out[x_col][x_row]: stage bytes by column, then write rows of 128 bytes
-        uint8_t* sq = reinterpret_cast<uint8_t*>(&tq[0][0]);
-        uint8_t* sr = reinterpret_cast<uint8_t*>(&tr[0][0]);
-        constexpr int stride = 33 * 4;
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int xr = 8 * i + (t >> 5);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                sq[(cl + j) * stride + xr] = (uint8_t)(qw[i] >> (8 * j));
-                sr[(cl + j) * stride + xr] = (uint8_t)(rw[i] >> (8 * j));
-            }
-        }
-        __syncthreads();
-        const int oc = t >> 1;            // output row within the tile (= X column)
-        const int half = (t & 1) * 64;    // 64 bytes of that row
-#pragma unroll
-        for (int w = 0; w < 4; ++w) {
-            uint4 a, b;
-            const uint32_t* srcq = &tq[oc][(half + 16 * w) / 4];
-            const uint32_t* srcr = &tr[oc][(half + 16 * w) / 4];
-            a.x = srcq[0]; a.y = srcq[1]; a.z = srcq[2]; a.w = srcq[3];
-            b.x = srcr[0]; b.y = srcr[1]; b.z = srcr[2]; b.w = srcr[3];
-            const int64_t o = out_off(ot_r * 128 + oc, ot_c * 128 + half + 16 * w);
-            *reinterpret_cast<uint4*>(q + o) = a;
-            *reinterpret_cast<uint4*>(rq + o) = b;
-        }
+    for (int i = 0; i < 4; ++i) {
+        const int64_t orow = ot_r * 128 + (TRANS ? 4 * h + i : h + 32 * i);
+        const int64_t o = TILED ? panel_offset(orow, ocol, nkb) : orow * out_cols + ocol;
+        *reinterpret_cast<uint4*>(q + o) = make_uint4(qw[i][0], qw[i][1], qw[i][2], qw[i][3]);
+        *reinterpret_cast<uint4*>(rq + o) = make_uint4(rw[i][0], rw[i][1], rw[i][2], rw[i][3]);
     }
+}
+
+template <bool VEC, bool TRANS, bool TILED>
+__global__ __launch_bounds__(256) void quant_fp8_kernel(
+    int64_t rows, int64_t cols, const float* __restrict__ X, int64_t ldx, int64_t out_cols,
+    uint8_t* __restrict__ q, uint8_t* __restrict__ qscale, uint8_t* __restrict__ rq,
+    uint8_t* __restrict__ rscale) {
+    __shared__ uint32_t red[8];    // the two reductions
+    quant_tile<VEC, TRANS, TILED>(rows, cols, X, ldx, out_cols, q, qscale, rq, rscale, red);
 }
 
 unsigned grid_for(int64_t work, int64_t per_block) {
