@@ -305,6 +305,27 @@ int cmp_gemm_variant(cmp_ctx *ctx, int id, const cmp_gemm_args *args, void *stre
 /* Run a host-target variant of any interface (synchronous), bypassing selection. */
 int cmp_call_host(cmp_ctx *ctx, const char *iface, int id, const void *args);
 
+/* For callers that cannot allocate device memory (code under their own graph
+ * capture, serving loops or harnesses that forbid hipMalloc): cmp_gemm_variant
+ * with the variant's workspace (pre-pass images, split-K partial sums) taken
+ * from a fixed array of CMP_STATIC_WS_BYTES in the library's device code
+ * instead of the context's workspace.  The call allocates nothing (no
+ * hipMalloc, hipFree or allocating library routine; per-kernel timing is
+ * suspended for it, since that creates events) and only enqueues kernels and
+ * event waits on `stream`.  The caller passes A, B, C as for cmp_gemm_variant.
+ * Each GPU holds its own copy of the array, created with the library's code
+ * on that device and kept until the process ends; every call on one GPU, from
+ * any context, shares it and it keeps the last call's contents, so calls that
+ * overlap in time on one GPU (two streams, two host threads) race: order them.
+ * Errors: CMP_ENOMEM (message names the bytes) when the variant needs more
+ * workspace for this shape than the array holds (e.g. bf16x3 and fp8r fit up
+ * to 4096^3, bf16 beyond); CMP_EUNSUPPORTED for a host context or a
+ * CMP_TARGET_HOST variant; CMP_EHIP if the array's device address could not be
+ * obtained at cmp_init; otherwise as cmp_gemm_variant.  Results are
+ * bit-identical to cmp_gemm_variant's (the same kernels). */
+#define CMP_STATIC_WS_BYTES ((size_t)128 << 20)
+int cmp_gemm_variant_static(cmp_ctx *ctx, int id, const cmp_gemm_args *args, void *stream);
+
 /* ---- timing and history (performance history, Sec. 3.2) --------------- */
 
 /* Time one variant: `warmup` untimed calls, then `reps` calls each bracketed

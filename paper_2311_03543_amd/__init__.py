@@ -213,6 +213,12 @@ class Compar:
         a = gemm_args(A, B, C_, alpha, beta)
         self._check(self.L.cmp_gemm_variant(self.ctx, vid, C.byref(a), _stream_ptr(stream)))
 
+    def gemm_variant_static(self, vid: int, A, B, C_, alpha=1.0, beta=0.0, stream=None):
+        """gemm_variant with the workspace taken from the library's fixed device array
+        (cmp_gemm_variant_static: no allocation)."""
+        a = gemm_args(A, B, C_, alpha, beta)
+        self._check(self.L.cmp_gemm_variant_static(self.ctx, vid, C.byref(a), _stream_ptr(stream)))
+
     def gemm_raw(self, args: cmp_gemm_args, tol: float, stream=None) -> tuple[int, int]:
         chosen = C.c_int(-1)
         st = self.L.cmp_gemm(self.ctx, C.byref(args), tol, _stream_ptr(stream), C.byref(chosen))

@@ -101,6 +101,7 @@ SIGNATURES = {
     "cmp_select_batch": (_I, [_P, _S, _I, C.POINTER(cmp_context), _IP]),
     "cmp_gemm": (_I, [_P, C.POINTER(cmp_gemm_args), _D, _P, _IP]),
     "cmp_gemm_variant": (_I, [_P, _I, C.POINTER(cmp_gemm_args), _P]),
+    "cmp_gemm_variant_static": (_I, [_P, _I, C.POINTER(cmp_gemm_args), _P]),
     "cmp_call_host": (_I, [_P, _S, _I, _P]),
     "cmp_time_variant": (_I, [_P, _I, C.POINTER(cmp_gemm_args), _I, _I, _P, _FP, _FP, _FP]),
     "cmp_calibrate": (_I, [_P, _I, C.POINTER(C.c_int64), _P, _P, _P, _I, _I, _P]),

@@ -16,6 +16,7 @@
 #include <fstream>
 #include <thread>
 #include <map>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <tuple>
@@ -120,6 +121,41 @@ inline double u01(uint64_t z) { return (double)(z >> 11) * (1.0 / 90071992547409
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Fixed device workspace of cmp_gemm_variant_static: one array in the device
+// code, which each GPU the library runs on holds until the process ends.  In
+// host code its name is only a stand-in, never a device address:
+// static_ws_address() asks the runtime, once per device and with that device
+// current, for the address of this device's copy, and callers pass that.
+namespace {
+constexpr size_t kStaticWsBytes = CMP_STATIC_WS_BYTES;
+__device__ __align__(256) uint8_t scratch[kStaticWsBytes];
+constexpr int kMaxDevices = 64;
+struct StaticWs {
+    std::once_flag once;
+    void* ptr = nullptr;
+    hipError_t err = hipSuccess;
+};
+StaticWs g_static_ws[kMaxDevices];
+
+// `device` must be the current device.
+void* static_ws_address(int device, hipError_t* err) {
+    if (device < 0 || device >= kMaxDevices) {
+        *err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    StaticWs& w = g_static_ws[device];
+    std::call_once(w.once, [&w]() {
+        void* p = nullptr;
+        w.err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        w.ptr = w.err == hipSuccess ? p : nullptr;
+        if (w.err != hipSuccess) (void)hipGetLastError();
+    });
+    *err = w.err;
+    return w.ptr;
+}
+}  // namespace
+
 struct cmp_ctx {
     int device = -1;
     bool gpu = false;
@@ -146,6 +182,8 @@ struct cmp_ctx {
     size_t ws_bytes = 0;
     bool ws_pinned = false;  // cmp_reserve: never reallocate the workspace
     void* vws = nullptr;     // verify-mode workspace (C0 copy, probe vector, partial sums)
+    void* static_ws = nullptr;              // this device's copy of the fixed array
+    hipError_t static_ws_err = hipSuccess;  // why static_ws is null
     void* hbuf = nullptr;    // pinned host staging of the host variant (A | B | C)
     size_t hbuf_bytes = 0;
     size_t vws_bytes = 0;
@@ -1182,6 +1220,7 @@ CMP_API int cmp_init(int device, cmp_ctx** out) {
             return CMP_EHIP;
         }
         c->gpu = true;
+        c->static_ws = static_ws_address(device, &c->static_ws_err);
     }
     read_env(c);
     register_builtins(c);
@@ -1436,6 +1475,40 @@ CMP_API int cmp_gemm_variant(cmp_ctx* c, int id, const cmp_gemm_args* a, void* s
     if (f->variants[id].target == CMP_TARGET_HIP && !c->gpu)
         return fail(c, CMP_EUNSUPPORTED, "HIP variant on a host-only context");
     return run_variant(c, *f, id, a, stream);
+}
+
+CMP_API int cmp_gemm_variant_static(cmp_ctx* c, int id, const cmp_gemm_args* a, void* stream) {
+    if (!c) return CMP_EINVAL;
+    if (!c->gpu) return fail(c, CMP_EUNSUPPORTED, "the fixed workspace needs a GPU context");
+    Interface* f = find_iface(c, kGemm);
+    int st = check_gemm_args(c, a);
+    if (st) return st;
+    if (id < 0 || id >= (int)f->variants.size()) return fail(c, CMP_EINVAL, "bad variant id %d", id);
+    Variant& v = f->variants[id];
+    if (v.target != CMP_TARGET_HIP)
+        return fail(c, CMP_EUNSUPPORTED, "variant %s does not run on the GPU", v.name.c_str());
+    if (!c->static_ws)
+        return fail(c, CMP_EHIP, "address of the fixed workspace unavailable: %s",
+                    hipGetErrorString(c->static_ws_err));
+    const size_t need = v.ws ? v.ws(a, v.user) : 0;
+    if (need > kStaticWsBytes)
+        return fail(c, CMP_ENOMEM, "variant %s needs %zu workspace bytes for %lld x %lld x %lld; the fixed "
+                    "workspace holds %zu", v.name.c_str(), need, (long long)a->M, (long long)a->N,
+                    (long long)a->K, kStaticWsBytes);
+    const bool ktime = c->ktime;   // per-kernel timing creates events: off for this call
+    c->ktime = false;
+    ++v.calls;
+    st = v.fn(a, need ? c->static_ws : nullptr, need, stream, v.user);
+    c->ktime = ktime;
+    if (st != CMP_OK) {
+        if (c->last_error.empty() || st == CMP_EHIP) {
+            hipError_t e = hipGetLastError();
+            return fail(c, st, "variant %s failed (%d): %s", v.name.c_str(), st,
+                        e != hipSuccess ? hipGetErrorString(e) : "");
+        }
+        return st;
+    }
+    return CMP_OK;
 }
 
 CMP_API int cmp_call_host(cmp_ctx* c, const char* iface, int id, const void* args) {
