@@ -32,33 +32,43 @@ __device__ __forceinline__ int mx6_scale_exp(float amax) {
     return e > 127 ? 127 : (e < -127 ? -127 : e);
 }
 
-// Round-to-nearest-even onto the E2M3 grid for |s| <= 7.5 (which the block
-// scale guarantees), without branches.  Below 1 the grid is k/8 (the
-// subnormal codes 0..7, and k = 8 is the code of 1.0): k = rint(8 |s|), and
-// v_rndne rounds halves to even.  From 1 up the grid keeps 3 fraction bits:
-// rounding |s|'s own bits at bit 20 to nearest even (add 0x7ffff plus the
-// kept last bit, clear the rest) gives the value, and its exponent and top
-// fraction bits are the code, (E - 126) << 3 | f.  Returns the 6-bit code;
-// `val` gets the value.
-__device__ __forceinline__ uint32_t e2m3_code(float s, float& val) {
-    const float a = fabsf(s);
-    const float k = __builtin_rintf(a * 8.f);
-    const uint32_t u = __builtin_bit_cast(uint32_t, a);
-    const uint32_t ur = (u + 0x7ffffu + ((u >> 20) & 1u)) & 0xfff00000u;
-    const bool sub = a < 1.f;
-    const uint32_t code = sub ? (uint32_t)k : (ur >> 20) - (126u << 3);
-    const float v = sub ? k * 0.125f : __builtin_bit_cast(float, ur);
-    val = __builtin_copysignf(v, s);
-    return ((__builtin_bit_cast(uint32_t, s) >> 31) << 5) | code;
+// Four E2M3 codes, packed 6 bits each at bits 0, 6, 12, 18, of values whose
+// scaled forms s_j = x_j 2^e satisfy |s_j| <= 7.5, given as t_j = s_j 2^-6.
+// They come from the E4M3 converter (v_cvt_pk_fp8_f32, round to nearest
+// even): on [0, 7.5 2^-6] the E4M3 grid is the E2M3 grid scaled by 2^-6 (the
+// E4M3 subnormals k 2^-9 are E2M3's k / 8 there, and from 2^-6 up both keep
+// three fraction bits), so rounding t_j onto one is rounding s_j onto the
+// other, and the E4M3 byte, whose exponent field is at most 3, holds the E2M3
+// code in its sign (bit 7 -> 5), the low two exponent bits and the fraction.
+// q8 receives the four E4M3 bytes: their values times 2^6 are the codes'
+// values s_j rounded.
+__device__ __forceinline__ uint32_t e2m3x4(float t0, float t1, float t2, float t3, uint32_t& q8) {
+    int w = __builtin_amdgcn_cvt_pk_fp8_f32(t0, t1, 0, false);
+    w = __builtin_amdgcn_cvt_pk_fp8_f32(t2, t3, w, true);
+    q8 = (uint32_t)w;
+    const uint32_t by = (q8 & 0x1f1f1f1fu) | ((q8 >> 2) & 0x20202020u);   // one code per byte
+    return (by & 0x3fu) | ((by >> 2) & 0xfc0u) | ((by >> 4) & 0x3f000u) | ((by >> 6) & 0xfc0000u);
 }
-
-// Residual of one value against its code value qv (scaled domain s = x 2^e):
-// s - qv is exact and scaling back rounds once; a zero code leaves x - qv
-// (s may have lost bits below the FP32 range).  Both are formed, one kept.
-__device__ __forceinline__ float mx6_resid(float x, float s, float qv, int e) {
-    const float scaled = __builtin_ldexpf(s - qv, -e);
-    const float direct = x - qv;
-    return qv == 0.f ? direct : scaled;
+// First level of four values x_j of a block with exponent e (inv = 2^-e):
+// their packed codes, and the residuals x - q 2^-e (one FMA, rounded once; a
+// zero code leaves x, and -0 - (-0) gives +0 as the definition does), which
+// replace the values.
+__device__ __forceinline__ uint32_t mx6_level1(float (&x)[4], int e, float inv) {
+    uint32_t q8;
+    const uint32_t code = e2m3x4(__builtin_ldexpf(x[0], e - 6), __builtin_ldexpf(x[1], e - 6),
+                                 __builtin_ldexpf(x[2], e - 6), __builtin_ldexpf(x[3], e - 6), q8);
+    const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)q8, false);
+    const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)q8, true);
+    const float qv[4] = {lo[0] * 64.f, lo[1] * 64.f, hi[0] * 64.f, hi[1] * 64.f};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) x[j] = __builtin_fmaf(-qv[j], inv, x[j]);
+    return code;
+}
+// Second level: the residuals' packed codes with their block exponent e.
+__device__ __forceinline__ uint32_t mx6_level2(const float (&r)[4], int e) {
+    uint32_t q8;
+    return e2m3x4(__builtin_ldexpf(r[0], e - 6), __builtin_ldexpf(r[1], e - 6),
+                  __builtin_ldexpf(r[2], e - 6), __builtin_ldexpf(r[3], e - 6), q8);
 }
 
 // ---------------------------------------------------------------------------
@@ -115,23 +125,12 @@ __global__ __launch_bounds__(256) void quant_mx6_rows_kernel(
         uint32_t w0 = 0, w1 = 0, sb0 = 0xffu, sb1 = 0xffu;
         if (!bad) {
             const int e0 = mx6_scale_exp(amax);
-            float res[4], ramax = 0.f;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const float s = __builtin_ldexpf(v[j], e0);
-                float qv;
-                w0 |= e2m3_code(s, qv) << (6 * j);
-                res[j] = mx6_resid(v[j], s, qv, e0);
-                ramax = fmaxf(ramax, fabsf(res[j]));
-            }
+            w0 = mx6_level1(v, e0, __builtin_ldexpf(1.f, -e0));
+            float ramax = fmaxf(fmaxf(fabsf(v[0]), fabsf(v[1])), fmaxf(fabsf(v[2]), fabsf(v[3])));
 #pragma unroll
             for (int off = 1; off < 8; off <<= 1) ramax = fmaxf(ramax, __shfl_xor(ramax, off));
             const int e1 = mx6_scale_exp(ramax);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                float qv;
-                w1 |= e2m3_code(__builtin_ldexpf(res[j], e1), qv) << (6 * j);
-            }
+            w1 = mx6_level2(v, e1);
             sb0 = (uint32_t)(127 - e0);
             sb1 = (uint32_t)(127 - e1);
         }
@@ -208,30 +207,34 @@ __global__ __launch_bounds__(256) void quant_mx6_cols_kernel(
                 if (!__builtin_isfinite(v[j])) bad = true;
                 else amax = fmaxf(amax, fabsf(v[j]));
             }
-            // codes packed as they are made: code j at bit 6 j of p0 / p1
+            // codes packed as they are made: code j at bit 6 j of p0 / p1, four
+            // codes (24 bits) at a time
             uint32_t p0[6] = {0, 0, 0, 0, 0, 0}, p1[6] = {0, 0, 0, 0, 0, 0};
-            auto put = [](uint32_t (&p)[6], int j, uint32_t c) {
-                const int bit = 6 * j, d = bit >> 5, sh = bit & 31;
+            auto put24 = [](uint32_t (&p)[6], int m, uint32_t c) {
+                const int bit = 24 * m, d = bit >> 5, sh = bit & 31;
                 p[d] |= c << sh;
-                if (sh > 26) p[d + 1] |= c >> (32 - sh);
+                if (sh > 8) p[d + 1] |= c >> (32 - sh);
             };
             uint32_t sb0 = 0xffu, sb1 = 0xffu;
             if (!bad) {
                 const int e0 = mx6_scale_exp(amax);
+                const float inv = __builtin_ldexpf(1.f, -e0);
                 float ramax = 0.f;
 #pragma unroll
-                for (int j = 0; j < 32; ++j) {
-                    const float s = __builtin_ldexpf(v[j], e0);
-                    float qv;
-                    put(p0, j, e2m3_code(s, qv));
-                    v[j] = mx6_resid(v[j], s, qv, e0);
-                    ramax = fmaxf(ramax, fabsf(v[j]));
+                for (int m = 0; m < 8; ++m) {
+                    float x4[4] = {v[4 * m], v[4 * m + 1], v[4 * m + 2], v[4 * m + 3]};
+                    put24(p0, m, mx6_level1(x4, e0, inv));
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        v[4 * m + j] = x4[j];
+                        ramax = fmaxf(ramax, fabsf(x4[j]));
+                    }
                 }
                 const int e1 = mx6_scale_exp(ramax);
 #pragma unroll
-                for (int j = 0; j < 32; ++j) {
-                    float qv;
-                    put(p1, j, e2m3_code(__builtin_ldexpf(v[j], e1), qv));
+                for (int m = 0; m < 8; ++m) {
+                    const float r4[4] = {v[4 * m], v[4 * m + 1], v[4 * m + 2], v[4 * m + 3]};
+                    put24(p1, m, mx6_level2(r4, e1));
                 }
                 sb0 = (uint32_t)(127 - e0);
                 sb1 = (uint32_t)(127 - e1);
