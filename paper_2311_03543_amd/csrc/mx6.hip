@@ -73,11 +73,13 @@ __device__ __forceinline__ uint32_t mx6_level2(const float (&r)[4], int e) {
 
 // ---------------------------------------------------------------------------
 // Rows of X (blocks along X's rows, K = cols): eight lanes per block, four
-// consecutive values each, so one wave reads 1 KiB of a row with each load.
-// The block's amax and NaN flag are reduced over the eight lanes; each lane
-// then holds 4 codes (24 bits) and lane i < 6 assembles dword i of the packed
-// 192 bits from the 24-bit words of two neighbours; lane 6 writes the block's
-// two scale bytes.
+// consecutive values each, so one wave reads 1 KiB of a row with each load;
+// a lane takes kMx6RowsPerLane rows at a time and issues all their loads
+// first.  The block's amax and NaN flag are reduced over the eight lanes; each
+// lane then holds 4 codes (24 bits) and lane i < 6 assembles dword i of the
+// packed 192 bits from the 24-bit words of two neighbours; lane 6 writes the
+// block's two scale bytes.
+constexpr int kMx6RowsPerLane = 4;
 template <bool VEC, bool TILED>
 __global__ __launch_bounds__(256) void quant_mx6_rows_kernel(
     int64_t rows, int64_t cols, const float* __restrict__ X, int64_t ldx, int64_t out_rows,
@@ -97,66 +99,79 @@ __global__ __launch_bounds__(256) void quant_mx6_rows_kernel(
     const int sh = li < 6 ? 8 * (li % 3) : 0;
     const int b = i >> 3;
     const int64_t k = (int64_t)b * 32 + 4 * li;
-    for (int64_t r = blockIdx.y; r < nrows; r += gridDim.y) {
-        float v[4] = {0.f, 0.f, 0.f, 0.f};
-        if (r < rows) {
-            const float* p = X + r * ldx + k;
-            if (VEC && k + 3 < cols) {
-                const float4 a = *reinterpret_cast<const float4*>(p);
-                v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    constexpr int RPL = kMx6RowsPerLane;
+    for (int64_t r0 = (int64_t)blockIdx.y * RPL; r0 < nrows; r0 += (int64_t)gridDim.y * RPL) {
+        float vr[RPL][4];
+#pragma unroll
+        for (int rr = 0; rr < RPL; ++rr) {
+            const int64_t r = r0 + rr;
+            float* v = vr[rr];
+            v[0] = v[1] = v[2] = v[3] = 0.f;
+            if (r < rows) {
+                const float* p = X + r * ldx + k;
+                if (VEC && k + 3 < cols) {
+                    const float4 a = *reinterpret_cast<const float4*>(p);
+                    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (k + j < cols) v[j] = p[j];
+                }
+            }
+        }
+#pragma unroll
+        for (int rr = 0; rr < RPL; ++rr) {
+            const int64_t r = r0 + rr;
+            if (r >= nrows) break;                  // uniform: r depends on the workgroup only
+            float (&v)[4] = vr[rr];
+            float amax = 0.f;
+            int bad = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (!__builtin_isfinite(v[j])) bad = 1;
+                else amax = fmaxf(amax, fabsf(v[j]));
+            }
+#pragma unroll
+            for (int off = 1; off < 8; off <<= 1) {
+                amax = fmaxf(amax, __shfl_xor(amax, off));
+                bad |= __shfl_xor(bad, off);
+            }
+            uint32_t w0 = 0, w1 = 0, sb0 = 0xffu, sb1 = 0xffu;
+            if (!bad) {
+                const int e0 = mx6_scale_exp(amax);
+                w0 = mx6_level1(v, e0, __builtin_ldexpf(1.f, -e0));
+                float ramax = fmaxf(fmaxf(fabsf(v[0]), fabsf(v[1])), fmaxf(fabsf(v[2]), fabsf(v[3])));
+#pragma unroll
+                for (int off = 1; off < 8; off <<= 1) ramax = fmaxf(ramax, __shfl_xor(ramax, off));
+                const int e1 = mx6_scale_exp(ramax);
+                w1 = mx6_level2(v, e1);
+                sb0 = (uint32_t)(127 - e0);
+                sb1 = (uint32_t)(127 - e1);
+            }
+            if (TILED) {
+                // dword li (< 6) of this block's 24 code bytes; the scales from lane 6
+                const uint32_t lo0 = __shfl(w0, src_lo), hi0 = __shfl(w0, src_hi);
+                const uint32_t lo1 = __shfl(w1, src_lo), hi1 = __shfl(w1, src_hi);
+                if (li < 6) {
+                    const int64_t o = mx6_code_offset(r, b >> 1, b & 1, 4 * li, nkb);
+                    *reinterpret_cast<uint32_t*>(q + o) = (lo0 >> sh) | (hi0 << (24 - sh));
+                    *reinterpret_cast<uint32_t*>(rq + o) = (lo1 >> sh) | (hi1 << (24 - sh));
+                } else if (li == 6) {
+                    *reinterpret_cast<uint16_t*>(qscale + mx6_scale_offset(r, b >> 1, b & 1, 0, nkb)) =
+                        (uint16_t)(sb0 | (sb1 << 8));
+                }
             } else {
+                // one code per byte, row-major rows x cols; the scales from lane 0
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
-                    if (k + j < cols) v[j] = p[j];
-            }
-        }
-        float amax = 0.f;
-        int bad = 0;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            if (!__builtin_isfinite(v[j])) bad = 1;
-            else amax = fmaxf(amax, fabsf(v[j]));
-        }
-#pragma unroll
-        for (int off = 1; off < 8; off <<= 1) {
-            amax = fmaxf(amax, __shfl_xor(amax, off));
-            bad |= __shfl_xor(bad, off);
-        }
-        uint32_t w0 = 0, w1 = 0, sb0 = 0xffu, sb1 = 0xffu;
-        if (!bad) {
-            const int e0 = mx6_scale_exp(amax);
-            w0 = mx6_level1(v, e0, __builtin_ldexpf(1.f, -e0));
-            float ramax = fmaxf(fmaxf(fabsf(v[0]), fabsf(v[1])), fmaxf(fabsf(v[2]), fabsf(v[3])));
-#pragma unroll
-            for (int off = 1; off < 8; off <<= 1) ramax = fmaxf(ramax, __shfl_xor(ramax, off));
-            const int e1 = mx6_scale_exp(ramax);
-            w1 = mx6_level2(v, e1);
-            sb0 = (uint32_t)(127 - e0);
-            sb1 = (uint32_t)(127 - e1);
-        }
-        if (TILED) {
-            // dword li (< 6) of this block's 24 code bytes; the scales from lane 6
-            const uint32_t lo0 = __shfl(w0, src_lo), hi0 = __shfl(w0, src_hi);
-            const uint32_t lo1 = __shfl(w1, src_lo), hi1 = __shfl(w1, src_hi);
-            if (li < 6) {
-                const int64_t o = mx6_code_offset(r, b >> 1, b & 1, 4 * li, nkb);
-                *reinterpret_cast<uint32_t*>(q + o) = (lo0 >> sh) | (hi0 << (24 - sh));
-                *reinterpret_cast<uint32_t*>(rq + o) = (lo1 >> sh) | (hi1 << (24 - sh));
-            } else if (li == 6) {
-                *reinterpret_cast<uint16_t*>(qscale + mx6_scale_offset(r, b >> 1, b & 1, 0, nkb)) =
-                    (uint16_t)(sb0 | (sb1 << 8));
-            }
-        } else {
-            // one code per byte, row-major rows x cols; the scales from lane 0
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if (k + j < cols) {
-                    q[r * cols + k + j] = (uint8_t)((w0 >> (6 * j)) & 63u);
-                    rq[r * cols + k + j] = (uint8_t)((w1 >> (6 * j)) & 63u);
+                    if (k + j < cols) {
+                        q[r * cols + k + j] = (uint8_t)((w0 >> (6 * j)) & 63u);
+                        rq[r * cols + k + j] = (uint8_t)((w1 >> (6 * j)) & 63u);
+                    }
+                if (li == 0) {
+                    qscale[r * nb + b] = (uint8_t)sb0;
+                    rscale[r * nb + b] = (uint8_t)sb1;
                 }
-            if (li == 0) {
-                qscale[r * nb + b] = (uint8_t)sb0;
-                rscale[r * nb + b] = (uint8_t)sb1;
             }
         }
     }
@@ -295,7 +310,8 @@ hipError_t launch_quant_mx6(int64_t rows, int64_t cols, const float* X, int64_t 
     if (!transpose) {
         const int64_t nb = tiled ? Kp / 32 : (cols + 31) / 32;
         if (nb * 8 >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
-        const dim3 g(cap((nb * 8 + 255) / 256, 1 << 30), cap(tiled ? out_rows : rows, 65535));
+        const int64_t nr = tiled ? out_rows : rows;
+        const dim3 g(cap((nb * 8 + 255) / 256, 1 << 30), cap((nr + kMx6RowsPerLane - 1) / kMx6RowsPerLane, 65535));
         const bool vec = (ldx % 4 == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
         auto go = [&](auto kernel) {
             hipLaunchKernelGGL(kernel, g, dim3(256), 0, stream, rows, cols, X, ldx, out_rows, Kp, q,
