@@ -167,6 +167,10 @@ struct cmp_ctx {
     int split_k = 0;                  // 0: cost model; n >= 1: forced slice count
     std::vector<HistRow> history;
     uint64_t hist_gen = 0;            // bumped on every change of `history`
+    // per-K-block workgroup time of each image kind on this device, derived
+    // from the history (0: none yet, the built-in constant applies)
+    mutable double step_ns[4] = {0, 0, 0, 0};
+    mutable uint64_t step_gen = ~0ull;
     // shape table of the history, rebuilt when hist_gen or the variant count moves
     mutable ShapeTable shape_cache;
     mutable uint64_t shape_cache_gen = ~0ull;
@@ -450,16 +454,59 @@ Images images_of(int kind, int64_t M, int64_t N, int64_t K) {
     I.total = o;
     return I;
 }
-// Split-K count of an image variant: K blocks of 64 bytes (bf16: 32 values,
-// FP8: 64 values, FP6: one 64-value block) priced at the variant's measured
-// time per K block.
-int image_splits(int kind, const cmp_gemm_args* a, const Images& I, const void* user) {
-    switch (kind) {
-        case kImgBf16: return gemm_splits(a, I.Kp * 2, cmp::kStepNsBf16, user);
-        case kImgBf16x3: return gemm_splits(a, I.Kp * 2, cmp::kStepNsBf16x3, user);
-        case kImgFp8r: return gemm_splits(a, I.Kp, cmp::kStepNsFp8r, user);
-        default: return gemm_splits(a, I.Kp, cmp::kStepNsFp6x3, user);
+int image_kind(const Variant& v);
+
+// Per-K-block time of one workgroup of an image variant on this device (ns),
+// the price the split-K cost model puts on a K block.  Boards of one product
+// differ by several percent in the clock their power limit allows, so it is
+// taken from this context's own history where possible: over the timed shapes
+// of the variant whose tiles fill every CU (no split) and whose K spans at
+// least 64 blocks, (median time - the operand pre-pass at 5 TB/s) / (tile
+// waves x K blocks), the median over those shapes, kept within [0.75, 1.33]
+// of the constant measured at 8192^3.  Without such a shape, the constant.
+double step_time(const cmp_ctx* c, int kind) {
+    static constexpr double kConst[4] = {cmp::kStepNsBf16, cmp::kStepNsBf16x3, cmp::kStepNsFp8r,
+                                         cmp::kStepNsFp6x3};
+    if (!c || kind < 0 || kind > 3) return kind >= 0 && kind <= 3 ? kConst[kind] : cmp::kStepNsBf16;
+    if (c->step_gen != c->hist_gen) {
+        const Interface* f = nullptr;
+        for (const auto& i : c->ifaces)
+            if (i.name == kGemm) f = &i;
+        const int cus = c->gpu && c->props.multiProcessorCount > 0 ? c->props.multiProcessorCount : 256;
+        std::vector<double> per[4];
+        for (const HistRow& r : c->history) {
+            if (!f || r.id < 0 || r.id >= (int)f->variants.size() || !(r.med > 0)) continue;
+            const int k = image_kind(f->variants[r.id]);
+            if (k < 0) continue;
+            const Images I = images_of(k, r.M, r.N, r.K);
+            const int64_t nkb = (k == kImgBf16 || k == kImgBf16x3 ? I.Kp * 2 : I.Kp) / cmp::kKBlockBytes;
+            const int64_t tiles = (I.Mp / cmp::kMfmaTileM) * (I.Np / cmp::kMfmaTileN);
+            if (tiles < cus || nkb < 64) continue;
+            const double waves = (double)((tiles + cus - 1) / cus);
+            const double prepass_ns = (4.0 * (double)(r.M * r.K + r.K * r.N) + (double)I.total) / 5000.0;
+            const double t = (double)r.med * 1e6 - prepass_ns;
+            if (t > 0) per[k].push_back(t / (waves * (double)nkb));
+        }
+        for (int k = 0; k < 4; ++k) {
+            double v = 0;
+            if (!per[k].empty()) {
+                std::sort(per[k].begin(), per[k].end());
+                v = per[k][per[k].size() / 2];
+                v = std::min(std::max(v, 0.75 * kConst[k]), 1.33 * kConst[k]);
+            }
+            c->step_ns[k] = v;
+        }
+        c->step_gen = c->hist_gen;
     }
+    return c->step_ns[kind] > 0 ? c->step_ns[kind] : kConst[kind];
+}
+
+// Split-K count of an image variant: K blocks of 64 bytes (bf16: 32 values,
+// FP8: 64 values, FP6: one 64-value block) priced at the variant's time per
+// K block on this device.
+int image_splits(int kind, const cmp_gemm_args* a, const Images& I, const void* user) {
+    const double step = step_time((const cmp_ctx*)user, kind);
+    return gemm_splits(a, kind == kImgBf16 || kind == kImgBf16x3 ? I.Kp * 2 : I.Kp, step, user);
 }
 size_t ws_images(int kind, const void* args, const void* user) {
     auto a = (const cmp_gemm_args*)args;

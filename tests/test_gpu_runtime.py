@@ -180,6 +180,30 @@ def test_mlp_selector_estimates_optional_variants_from_history():
         c.close()
 
 
+def test_split_k_prices_k_blocks_from_this_device_history(cx):
+    """The split-K cost model prices a K block at the per-block time the context's own history
+    implies (a timed shape whose tiles fill every CU), within [0.75, 1.33] of the built-in
+    constant: a slow record means more slices, a fast one fewer, no record the constant."""
+    vid = cx.variant_find("bf16")
+    shapes = [(m, m, k) for m in (256, 512, 768, 1024, 1536, 2048) for k in (2048, 4096, 8192, 16384)]
+    cx.history_clear()
+    s0 = [cx.split_k(vid, *s) for s in shapes]
+    cx.history_add(8192, 8192, 8192, vid, 1, 10.0)        # far slower than the constant implies
+    s1 = [cx.split_k(vid, *s) for s in shapes]
+    cx.history_clear()
+    cx.history_add(8192, 8192, 8192, vid, 1, 0.3)         # far faster
+    s2 = [cx.split_k(vid, *s) for s in shapes]
+    cx.history_clear()
+    assert [cx.split_k(vid, *s) for s in shapes] == s0
+    assert all(a >= b for a, b in zip(s1, s0)) and any(a > b for a, b in zip(s1, s0))
+    assert all(a <= b for a, b in zip(s2, s0)) and any(a < b for a, b in zip(s2, s0))
+    # shapes too small to fill the CUs, or with a short K, do not inform the price
+    cx.history_add(1024, 1024, 8192, vid, 1, 10.0)
+    cx.history_add(8192, 8192, 512, vid, 1, 10.0)
+    assert [cx.split_k(vid, *s) for s in shapes] == s0
+    cx.history_clear()
+
+
 def test_injected_failure_falls_back(monkeypatch):
     """COMPAR_FAULT=bf16:1 makes every bf16 call fail; cmp_gemm must fall back once to the
     best other admissible variant (fp8r by the recorded times) and still meet tol."""
