@@ -3,8 +3,12 @@
 // interface: every product and sum is an FP32 FMA on the vector ALUs.
 //
 // Two launch forms share the tile code of simt_tile.h:
-//   - one problem: a 128 x 128 x 16 tile per workgroup, tiles renumbered so
-//     each XCD works on a contiguous, L2-friendly block of C;
+//   - one problem: a tile per workgroup, tiles renumbered so each XCD works
+//     on a contiguous, L2-friendly block of C.  The tile is the largest of
+//     128 x 256, 128 x 128, 64 x 128 and 64 x 64 (K step 16) that still gives
+//     every CU two tiles (the smallest when none does): on MI355X a 128 x 256
+//     tile streams 91-93 TFLOP/s at 4096^2..8192^2 against 81-87 for
+//     128 x 128, and at 2048^2 64 x 128 tiles (512 of them) 58 against 42;
 //   - a group of problems of uneven shapes: one persistent launch whose
 //     workgroups stride over the concatenated tile list of all problems
 //     (problems sorted by decreasing work, so the tail is short), with the
@@ -16,15 +20,18 @@
 namespace cmp {
 namespace {
 
+using CfgL = SimtCfg<128, 256, 16, 8, 16>;
 using Cfg128 = SimtCfg<128, 128, 16, 8, 8>;
+using CfgM = SimtCfg<64, 128, 16, 4, 8>;
+using CfgS = SimtCfg<64, 64, 16, 4, 4>;
 
-template <bool VEC>
+template <typename Cfg, bool VEC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void gemm_f32_simt_kernel(
     SimtProblem p, int tiles_m, int tiles_n) {
-    __shared__ __attribute__((aligned(16))) float smem[Cfg128::SMEM_FLOATS];
+    __shared__ __attribute__((aligned(16))) float smem[Cfg::SMEM_FLOATS];
     int tm, tn;
     grouped_tile(xcd_remap(blockIdx.x, tiles_m * tiles_n), tiles_m, tiles_n, 8, tm, tn);
-    simt_tile<Cfg128, VEC>(p, (int64_t)tm * Cfg128::BM, (int64_t)tn * Cfg128::BN, smem);
+    simt_tile<Cfg, VEC>(p, (int64_t)tm * Cfg::BM, (int64_t)tn * Cfg::BN, smem);
 }
 
 // Persistent grouped kernel: workgroup b takes tiles b, b + grid, b + 2 grid, ...
@@ -81,6 +88,7 @@ hipError_t launch_grouped_cfg(const GroupedDesc* desc, int count, int total_tile
 const GroupedConfig kGroupedConfigs[kNumGroupedConfigs] = {
     {64, 64, 16}, {64, 64, 32}, {64, 128, 16}, {128, 64, 16},
     {128, 128, 16}, {128, 128, 32}, {256, 128, 16}, {128, 256, 16},
+    {64, 64, 64}, {64, 128, 64},
 };
 
 hipError_t launch_gemm_f32_grouped(int config, const GroupedDesc* desc, int count, int total_tiles,
@@ -95,6 +103,8 @@ hipError_t launch_gemm_f32_grouped(int config, const GroupedDesc* desc, int coun
         case 5: return launch_grouped_cfg<SimtCfg<128, 128, 32, 8, 8>>(desc, count, total_tiles, grid, stream);
         case 6: return launch_grouped_cfg<SimtCfg<256, 128, 16, 16, 8>>(desc, count, total_tiles, grid, stream);
         case 7: return launch_grouped_cfg<SimtCfg<128, 256, 16, 8, 16>>(desc, count, total_tiles, grid, stream);
+        case 8: return launch_grouped_cfg<SimtCfg<64, 64, 64, 4, 4>>(desc, count, total_tiles, grid, stream);
+        case 9: return launch_grouped_cfg<SimtCfg<64, 128, 64, 4, 8>>(desc, count, total_tiles, grid, stream);
         default: return hipErrorInvalidValue;
     }
 }
@@ -111,27 +121,44 @@ int grouped_blocks_per_cu(int config) {
         case 5: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gemm_f32_grouped_kernel<SimtCfg<128, 128, 32, 8, 8>>, 256, 0); break;
         case 6: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gemm_f32_grouped_kernel<SimtCfg<256, 128, 16, 16, 8>>, 256, 0); break;
         case 7: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gemm_f32_grouped_kernel<SimtCfg<128, 256, 16, 8, 16>>, 256, 0); break;
+        case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gemm_f32_grouped_kernel<SimtCfg<64, 64, 64, 4, 4>>, 256, 0); break;
+        case 9: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gemm_f32_grouped_kernel<SimtCfg<64, 128, 64, 4, 8>>, 256, 0); break;
         default: break;
     }
     return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
+template <typename Cfg>
+hipError_t launch_simt(const SimtProblem& p, bool vec, hipStream_t stream) {
+    const int tiles_m = (int)((p.M + Cfg::BM - 1) / Cfg::BM);
+    const int tiles_n = (int)((p.N + Cfg::BN - 1) / Cfg::BN);
+    const int nb = tiles_m * tiles_n;
+    if (nb == 0) return hipSuccess;
+    if (vec)
+        hipLaunchKernelGGL((gemm_f32_simt_kernel<Cfg, true>), dim3(nb), dim3(256), 0, stream, p, tiles_m, tiles_n);
+    else
+        hipLaunchKernelGGL((gemm_f32_simt_kernel<Cfg, false>), dim3(nb), dim3(256), 0, stream, p, tiles_m, tiles_n);
+    return hipGetLastError();
+}
+
+template <typename Cfg>
+int64_t simt_tiles(int64_t M, int64_t N) {
+    return ((M + Cfg::BM - 1) / Cfg::BM) * ((N + Cfg::BN - 1) / Cfg::BN);
+}
+
 hipError_t launch_gemm_f32_simt(int64_t M, int64_t N, int64_t K, float alpha, const float* A,
                                 int64_t lda, const float* B, int64_t ldb, float beta, float* C,
                                 int64_t ldc, hipStream_t stream) {
-    const int tiles_m = (int)((M + Cfg128::BM - 1) / Cfg128::BM);
-    const int tiles_n = (int)((N + Cfg128::BN - 1) / Cfg128::BN);
-    const int nb = tiles_m * tiles_n;
-    if (nb == 0) return hipSuccess;
+    if (M <= 0 || N <= 0) return hipSuccess;
     const bool vec = (lda % 4 == 0) && (ldb % 4 == 0) &&
                      ((reinterpret_cast<uintptr_t>(A) & 15) == 0) &&
                      ((reinterpret_cast<uintptr_t>(B) & 15) == 0);
     const SimtProblem p{M, N, K, lda, ldb, ldc, alpha, beta, A, B, C};
-    if (vec)
-        hipLaunchKernelGGL(gemm_f32_simt_kernel<true>, dim3(nb), dim3(256), 0, stream, p, tiles_m, tiles_n);
-    else
-        hipLaunchKernelGGL(gemm_f32_simt_kernel<false>, dim3(nb), dim3(256), 0, stream, p, tiles_m, tiles_n);
-    return hipGetLastError();
+    constexpr int64_t kWant = 2 * 256;   // two tiles for each of the 256 CUs
+    if (simt_tiles<CfgL>(M, N) >= kWant) return launch_simt<CfgL>(p, vec, stream);
+    if (simt_tiles<Cfg128>(M, N) >= kWant) return launch_simt<Cfg128>(p, vec, stream);
+    if (simt_tiles<CfgM>(M, N) >= kWant) return launch_simt<CfgM>(p, vec, stream);
+    return launch_simt<CfgS>(p, vec, stream);
 }
 
 hipError_t launch_scale_c(int64_t M, int64_t N, float beta, float* C, int64_t ldc,

@@ -36,7 +36,7 @@ struct GroupedDesc {
 struct GroupedConfig {
     int bm, bn, bk;
 };
-constexpr int kNumGroupedConfigs = 8;
+constexpr int kNumGroupedConfigs = 10;
 extern const GroupedConfig kGroupedConfigs[kNumGroupedConfigs];
 hipError_t launch_gemm_f32_grouped(int config, const GroupedDesc* desc, int count, int total_tiles,
                                    int grid, hipStream_t stream);
