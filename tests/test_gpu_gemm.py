@@ -67,7 +67,9 @@ INT_SHAPES = [(1, 1, 1), (7, 5, 3), (256, 256, 256), (300, 520, 200), (257, 255,
               (64, 64, 16384), (1, 4096, 1000), (4096, 1, 1000), (33, 65, 8200),
               # many 256 x 256 tiles in both M and N: the XCD renumbering and the
               # grouped tile walk of the MFMA kernels cover a 9 x 10 tile grid
-              (2304, 2560, 384)]
+              (2304, 2560, 384),
+              # the FP32 SIMT kernel's 128 x 128 tile (fewer than 512 tiles of 128 x 256)
+              (2048, 4096, 72)]
 
 
 @pytest.mark.parametrize("name", VARIANTS)
