@@ -382,6 +382,16 @@ int cmp_mlp_infer(cmp_ctx *ctx, int n, const float *Xs, float *Yout);
  * Kaiming-uniform from splitmix64(seed), train, and enable the network for
  * CMP_SEL_MLP.  *final_loss (may be NULL) receives the last loss. */
 int cmp_mlp_fit_history(cmp_ctx *ctx, int steps, float lr, uint64_t seed, float *final_loss);
+/* Persist / reload the network (parameters and the four standardisation
+ * vectors) as text, with the same header as the history (device signature,
+ * library version; values printed with 9 significant digits, so a reload is
+ * bit-exact).  Save: CMP_ENODATA when the network has no parameters.  Load:
+ * CMP_EINVAL for a file that is not a network file, is malformed, has the
+ * wrong parameter count or non-positive deviations, or was saved on a
+ * different device signature (unless `force` is non-zero); on success the
+ * network is enabled for CMP_SEL_MLP and the decision cache cleared. */
+int cmp_mlp_save(cmp_ctx *ctx, const char *path);
+int cmp_mlp_load(cmp_ctx *ctx, const char *path, int force);
 
 /* ---- verification (FP64 residual probe) -------------------------------- */
 

@@ -321,6 +321,12 @@ class Compar:
         self._check(self.L.cmp_mlp_infer(self.ctx, x.shape[0], px, out.ctypes.data_as(C.POINTER(C.c_float))))
         return out
 
+    def mlp_save(self, path: str):
+        self._check(self.L.cmp_mlp_save(self.ctx, str(path).encode()))
+
+    def mlp_load(self, path: str, force: bool = False):
+        self._check(self.L.cmp_mlp_load(self.ctx, str(path).encode(), 1 if force else 0))
+
     def mlp_fit_history(self, steps=5000, lr=1e-3, seed=0) -> float:
         loss = C.c_float()
         self._check(self.L.cmp_mlp_fit_history(self.ctx, steps, lr, seed, C.byref(loss)))

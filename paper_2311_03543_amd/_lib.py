@@ -120,6 +120,8 @@ SIGNATURES = {
     "cmp_mlp_grad": (_I, [_P, _I, _FP, _FP, _FP, _FP]),
     "cmp_mlp_infer": (_I, [_P, _I, _FP, _FP]),
     "cmp_mlp_fit_history": (_I, [_P, _I, _F, _U64, _FP]),
+    "cmp_mlp_save": (_I, [_P, C.c_char_p]),
+    "cmp_mlp_load": (_I, [_P, C.c_char_p, _I]),
     "cmp_freivalds": (_I, [_P, C.POINTER(cmp_gemm_args), _P, _DP, _P, _DP]),
     "cmp_last_verify": (_I, [_P, _DP, _IP]),
     "cmp_split_bf16": (_I, [_P, _I64, _I64, _P, _I64, _P, _P, _P]),

@@ -2143,6 +2143,82 @@ CMP_API int cmp_mlp_fit_history(cmp_ctx* c, int steps, float lr, uint64_t seed, 
     return CMP_OK;
 }
 
+CMP_API int cmp_mlp_save(cmp_ctx* c, const char* path) {
+    if (!c || !path) return CMP_EINVAL;
+    if (c->mlp_params.size() != (size_t)kMlpP) return fail(c, CMP_ENODATA, "network has no parameters");
+    std::ofstream o(path);
+    if (!o) return fail(c, CMP_EINVAL, "cannot open %s", path);
+    o << "# compar-mlp v1\n";
+    o << "# device " << device_signature(c) << "\n";
+    o << "# lib " << kVersion << "\n";
+    char buf[32];
+    auto row = [&](const char* name, const float* v, int n) {
+        o << name;
+        for (int i = 0; i < n; ++i) {
+            std::snprintf(buf, sizeof buf, " %.9g", v[i]);
+            o << buf;
+        }
+        o << "\n";
+    };
+    row("mu_x", c->mu_x, 4);
+    row("sd_x", c->sd_x, 4);
+    row("mu_y", c->mu_y, 4);
+    row("sd_y", c->sd_y, 4);
+    row("params", c->mlp_params.data(), kMlpP);
+    if (!o) return fail(c, CMP_EINVAL, "write to %s failed", path);
+    return CMP_OK;
+}
+
+CMP_API int cmp_mlp_load(cmp_ctx* c, const char* path, int force) {
+    if (!c || !path) return CMP_EINVAL;
+    std::ifstream in(path);
+    if (!in) return fail(c, CMP_EINVAL, "cannot open %s", path);
+    std::string line;
+    bool header = false;
+    std::map<std::string, std::vector<float>> rows;
+    while (std::getline(in, line)) {
+        if (line.empty()) continue;
+        if (line[0] == '#') {
+            if (line.rfind("# compar-mlp v1", 0) == 0) header = true;
+            if (line.rfind("# device ", 0) == 0 && !force) {
+                const std::string sig = line.substr(9);
+                if (sig != device_signature(c))
+                    return fail(c, CMP_EINVAL, "network saved on '%s', this device is '%s'", sig.c_str(),
+                                device_signature(c).c_str());
+            }
+            continue;
+        }
+        std::istringstream ss(line);
+        std::string name;
+        ss >> name;
+        std::vector<float> v;
+        std::string tok;
+        while (ss >> tok) {
+            char* end = nullptr;
+            const float x = std::strtof(tok.c_str(), &end);
+            if (!end || *end) return fail(c, CMP_EINVAL, "malformed value '%s' in %s", tok.c_str(), path);
+            v.push_back(x);
+        }
+        rows[name] = std::move(v);
+    }
+    if (!header) return fail(c, CMP_EINVAL, "%s is not a compar network file", path);
+    for (const char* k : {"mu_x", "sd_x", "mu_y", "sd_y"})
+        if (rows[k].size() != 4) return fail(c, CMP_EINVAL, "%s: %s needs 4 values", path, k);
+    if (rows["params"].size() != (size_t)kMlpP)
+        return fail(c, CMP_EINVAL, "%s holds %zu parameters, the network has %d", path, rows["params"].size(), kMlpP);
+    for (int j = 0; j < 4; ++j)
+        if (!(rows["sd_x"][j] > 0) || !(rows["sd_y"][j] > 0))
+            return fail(c, CMP_EINVAL, "%s: deviations must be > 0", path);
+    std::copy(rows["mu_x"].begin(), rows["mu_x"].end(), c->mu_x);
+    std::copy(rows["sd_x"].begin(), rows["sd_x"].end(), c->sd_x);
+    std::copy(rows["mu_y"].begin(), rows["mu_y"].end(), c->mu_y);
+    std::copy(rows["sd_y"].begin(), rows["sd_y"].end(), c->sd_y);
+    c->mlp_params = rows["params"];
+    c->mlp_ready = true;
+    c->cache.clear();
+    return CMP_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Verification and pre-pass entry points
 

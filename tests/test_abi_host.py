@@ -289,6 +289,59 @@ def test_history_roundtrip_and_signature(tmp_path):
     assert e.history_load(q) == pa.CMP_EINVAL
 
 
+def test_mlp_checkpoint_roundtrip_and_errors(tmp_path):
+    """The selector network and its normalisation statistics survive a save and a load bit for
+    bit (Section 3.2 trains the network once and reuses it); a file from another device, a
+    malformed file or one with the wrong parameter count is refused and changes nothing."""
+    rng = np.random.default_rng(7)
+    c = host_ctx()
+    p = str(tmp_path / "net.txt")
+    with pytest.raises(pa.ComparError) as e:
+        c.mlp_save(p)                                   # nothing trained or set yet
+    assert e.value.status == pa.CMP_ENODATA
+    n = _lib.load().cmp_mlp_param_count()
+    params = (rng.standard_normal(n) * 10.0 ** rng.integers(-8, 8, n)).astype(np.float32)
+    params[:3] = [np.float32(1) / 3, -0.0, np.finfo(np.float32).tiny]
+    norm = [rng.standard_normal(4).astype(np.float32), rng.uniform(0.1, 9, 4).astype(np.float32),
+            rng.standard_normal(4).astype(np.float32), rng.uniform(0.1, 9, 4).astype(np.float32)]
+    c.mlp_set_params(params)
+    c.mlp_set_norm(*norm)
+    c.mlp_save(p)
+
+    d = host_ctx()
+    d.mlp_load(p)
+    assert d.mlp_get_params().tobytes() == params.tobytes()
+    for got, want in zip(d.mlp_get_norm(), norm):
+        assert got.tobytes() == want.tobytes()
+
+    text = open(p).read()
+    q = str(tmp_path / "other.txt")
+    open(q, "w").write(re.sub(r"(?m)^# device .*$", "# device arch=gfx950 cus=256", text))
+    e = host_ctx()
+    with pytest.raises(pa.ComparError) as err:
+        e.mlp_load(q)                                   # saved on another device
+    assert err.value.status == pa.CMP_EINVAL
+    e.mlp_load(q, force=True)
+    assert e.mlp_get_params().tobytes() == params.tobytes()
+
+    bad = {
+        "short": re.sub(r"(?m)^(params(?: \S+){%d}).*$" % (n - 1), r"\1", text),
+        "value": text.replace("sd_x ", "sd_x x", 1),
+        "sd": re.sub(r"(?m)^sd_y \S+", "sd_y 0", text),
+        "header": "\n".join(l for l in text.splitlines() if not l.startswith("# compar-mlp")),
+        "garbage": "garbage\n",
+    }
+    for name, body in bad.items():
+        f = str(tmp_path / f"bad_{name}.txt")
+        open(f, "w").write(body)
+        g = host_ctx()
+        g.mlp_set_params(np.zeros(n, np.float32))
+        with pytest.raises(pa.ComparError) as err:
+            g.mlp_load(f, force=True)
+        assert err.value.status == pa.CMP_EINVAL, name
+        assert not g.mlp_get_params().any(), name      # a refused file leaves the network alone
+
+
 def test_env_restriction_in_subprocess():
     code = r"""
 import paper_2311_03543_amd as pa

@@ -291,6 +291,35 @@ def test_mlp_selector_uses_network(cx):
     assert cx.select_batch([(100, 200, 300, 1e-2), (100, 200, 300, 1e-3), (5000, 5000, 64, 1e-5)]) == [3, 2, 1]
 
 
+def test_mlp_checkpoint_restores_selection(tmp_path):
+    """A network trained on this device, saved and loaded into a fresh context, infers the same
+    ln-times bit for bit and makes the same choices over a batch of shapes."""
+    import paper_2311_03543_amd as pa
+    X, Y = _mlp_data(400, 36)
+    a = pa.Compar(0)
+    b = pa.Compar(0)
+    try:
+        mx, sx, my, sy = X.mean(0), X.std(0), Y.mean(0), Y.std(0)
+        a.mlp_set_params(synth.mlp_init(10))
+        a.mlp_set_norm(mx, sx, my, sy)
+        a.mlp_train(((X - mx) / sx).astype(np.float32), ((Y - my) / sy).astype(np.float32), 200, 1e-2)
+        p = str(tmp_path / "net.txt")
+        a.mlp_save(p)
+        b.mlp_load(p)
+        Xs = ((X[:64] - mx) / sx).astype(np.float32)
+        assert a.mlp_infer(Xs).tobytes() == b.mlp_infer(Xs).tobytes()
+        a.selector_set(pa.CMP_SEL_MLP)
+        b.selector_set(pa.CMP_SEL_MLP)
+        rng = np.random.default_rng(11)
+        qs = [(int(m), int(n), int(k), t) for (m, n, k), t in
+              zip(rng.integers(16, 9000, (60, 3)), rng.choice([1e-5, 1e-3, 1e-2], 60))]
+        say("  mlp checkpoint: 60 selections")
+        assert a.select_batch(qs) == b.select_batch(qs)
+    finally:
+        a.close()
+        b.close()
+
+
 def test_call_log_gpu(cx, tmp_path):
     """CMP_FLAG_LOG on the GPU: measured time from the call's HIP event pair, the selector's
     predicted time from the history, the verify-mode residual, and no measurement for a call
