@@ -479,8 +479,12 @@ int cmp_prepass_images(cmp_ctx *ctx, int id, const cmp_gemm_args *args, void *ou
 /* A plan runs `count` independent gemm problems (FP32 SIMT arithmetic, each
  * problem's own alpha, beta and leading dimensions; device pointers owned by
  * the caller and fixed for the plan's lifetime) as ONE persistent kernel whose
- * workgroups stride over the concatenated tile list, problems ordered by
- * decreasing work.  The tile shape is one of cmp_grouped_config_count()
+ * workgroups take tiles of the concatenated tile list from a device counter
+ * as they finish their previous one, problems ordered by decreasing K (the
+ * longest tiles first).  A launch zeroes the plan's counter first (a one-lane
+ * kernel on the same stream, no memset, so the pair can be captured), and two
+ * launches of one plan must not run at the same time (they would share the
+ * counter and the problems' C).  The tile shape is one of cmp_grouped_config_count()
  * configurations; config < 0 runs the autotuner, which times every
  * configuration `reps` times on this group and keeps the fastest (it runs the
  * products, so C is overwritten: with beta != 0, re-initialise C afterwards).

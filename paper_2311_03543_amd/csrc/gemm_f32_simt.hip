@@ -10,9 +10,10 @@
 //     tile streams 91-93 TFLOP/s at 4096^2..8192^2 against 81-87 for
 //     128 x 128, and at 2048^2 64 x 128 tiles (512 of them) 58 against 42;
 //   - a group of problems of uneven shapes: one persistent launch whose
-//     workgroups stride over the concatenated tile list of all problems
-//     (problems sorted by decreasing work, so the tail is short), with the
-//     tile shape picked per group by the autotuner from kGroupedConfigs.
+//     workgroups claim tiles of the concatenated tile list of all problems
+//     from a counter as they go (problems sorted by decreasing K, so the
+//     longest tiles go first and the tail is short), with the tile shape
+//     picked per group by the autotuner from kGroupedConfigs.
 #include "common.h"
 #include "kernels.h"
 #include "simt_tile.h"
@@ -34,13 +35,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
     simt_tile<Cfg, VEC>(p, (int64_t)tm * Cfg::BM, (int64_t)tn * Cfg::BN, smem);
 }
 
-// Persistent grouped kernel: workgroup b takes tiles b, b + grid, b + 2 grid, ...
-// of the concatenated list; tile_start[p] is the first tile of problem p.
+// Persistent grouped kernel over the concatenated tile list (tile_start[p] is
+// the first tile of problem p; problems come in decreasing order of per-tile
+// work).  Workgroup b starts with tile b; each workgroup that finishes a tile
+// takes the next unclaimed one from the counter (tile grid + ticket), so the
+// list is served greedily in order, longest tiles first.  Every workgroup
+// leaves once a claim passes the end of the list.  The counter must be zero
+// at launch (grouped_reset_kernel runs right before on the same stream).
+__global__ void grouped_reset_kernel(unsigned* counter) {
+    if (threadIdx.x == 0) *counter = 0u;
+}
+
 template <typename Cfg>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void gemm_f32_grouped_kernel(
-    const GroupedDesc* __restrict__ desc, int count, int total_tiles) {
+    const GroupedDesc* __restrict__ desc, int count, int total_tiles, unsigned* __restrict__ counter) {
     __shared__ __attribute__((aligned(16))) float smem[Cfg::SMEM_FLOATS];
-    for (int tile = blockIdx.x; tile < total_tiles; tile += gridDim.x) {
+    __shared__ int next_tile;
+    for (int tile = blockIdx.x; tile < total_tiles;) {
         // last problem whose first tile is <= tile (binary search, wave-uniform)
         typedef const __attribute__((address_space(1))) GroupedDesc* gdesc;
         const gdesc dg = (gdesc)desc;
@@ -60,7 +71,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
             simt_tile<Cfg, true>(p, (int64_t)tm * Cfg::BM, (int64_t)tn * Cfg::BN, smem);
         else
             simt_tile<Cfg, false>(p, (int64_t)tm * Cfg::BM, (int64_t)tn * Cfg::BN, smem);
-        __syncthreads();  // LDS is reused by the next tile
+        __syncthreads();  // LDS is reused by the next tile; next_tile read by every lane
+        if (threadIdx.x == 0) {
+            const unsigned ticket = atomicAdd(counter, 1u);
+            const unsigned left = (unsigned)total_tiles - gridDim.x;   // grid <= total_tiles
+            next_tile = ticket < left ? (int)(gridDim.x + ticket) : total_tiles;
+        }
+        __syncthreads();
+        tile = next_tile;
     }
 }
 
@@ -77,9 +95,10 @@ __global__ void scale_c_kernel(int64_t M, int64_t N, float beta, float* __restri
 
 template <typename Cfg>
 hipError_t launch_grouped_cfg(const GroupedDesc* desc, int count, int total_tiles, int grid,
-                              hipStream_t stream) {
+                              unsigned* counter, hipStream_t stream) {
+    hipLaunchKernelGGL(grouped_reset_kernel, dim3(1), dim3(64), 0, stream, counter);
     hipLaunchKernelGGL(gemm_f32_grouped_kernel<Cfg>, dim3(grid), dim3(256), 0, stream, desc, count,
-                       total_tiles);
+                       total_tiles, counter);
     return hipGetLastError();
 }
 
@@ -92,19 +111,20 @@ const GroupedConfig kGroupedConfigs[kNumGroupedConfigs] = {
 };
 
 hipError_t launch_gemm_f32_grouped(int config, const GroupedDesc* desc, int count, int total_tiles,
-                                   int grid, hipStream_t stream) {
+                                   int grid, unsigned* counter, hipStream_t stream) {
     if (total_tiles <= 0) return hipSuccess;
+    if (grid < 1 || grid > total_tiles || !counter) return hipErrorInvalidValue;
     switch (config) {
-        case 0: return launch_grouped_cfg<SimtCfg<64, 64, 16, 4, 4>>(desc, count, total_tiles, grid, stream);
-        case 1: return launch_grouped_cfg<SimtCfg<64, 64, 32, 4, 4>>(desc, count, total_tiles, grid, stream);
-        case 2: return launch_grouped_cfg<SimtCfg<64, 128, 16, 4, 8>>(desc, count, total_tiles, grid, stream);
-        case 3: return launch_grouped_cfg<SimtCfg<128, 64, 16, 8, 4>>(desc, count, total_tiles, grid, stream);
-        case 4: return launch_grouped_cfg<SimtCfg<128, 128, 16, 8, 8>>(desc, count, total_tiles, grid, stream);
-        case 5: return launch_grouped_cfg<SimtCfg<128, 128, 32, 8, 8>>(desc, count, total_tiles, grid, stream);
-        case 6: return launch_grouped_cfg<SimtCfg<256, 128, 16, 16, 8>>(desc, count, total_tiles, grid, stream);
-        case 7: return launch_grouped_cfg<SimtCfg<128, 256, 16, 8, 16>>(desc, count, total_tiles, grid, stream);
-        case 8: return launch_grouped_cfg<SimtCfg<64, 64, 64, 4, 4>>(desc, count, total_tiles, grid, stream);
-        case 9: return launch_grouped_cfg<SimtCfg<64, 128, 64, 4, 8>>(desc, count, total_tiles, grid, stream);
+        case 0: return launch_grouped_cfg<SimtCfg<64, 64, 16, 4, 4>>(desc, count, total_tiles, grid, counter, stream);
+        case 1: return launch_grouped_cfg<SimtCfg<64, 64, 32, 4, 4>>(desc, count, total_tiles, grid, counter, stream);
+        case 2: return launch_grouped_cfg<SimtCfg<64, 128, 16, 4, 8>>(desc, count, total_tiles, grid, counter, stream);
+        case 3: return launch_grouped_cfg<SimtCfg<128, 64, 16, 8, 4>>(desc, count, total_tiles, grid, counter, stream);
+        case 4: return launch_grouped_cfg<SimtCfg<128, 128, 16, 8, 8>>(desc, count, total_tiles, grid, counter, stream);
+        case 5: return launch_grouped_cfg<SimtCfg<128, 128, 32, 8, 8>>(desc, count, total_tiles, grid, counter, stream);
+        case 6: return launch_grouped_cfg<SimtCfg<256, 128, 16, 16, 8>>(desc, count, total_tiles, grid, counter, stream);
+        case 7: return launch_grouped_cfg<SimtCfg<128, 256, 16, 8, 16>>(desc, count, total_tiles, grid, counter, stream);
+        case 8: return launch_grouped_cfg<SimtCfg<64, 64, 64, 4, 4>>(desc, count, total_tiles, grid, counter, stream);
+        case 9: return launch_grouped_cfg<SimtCfg<64, 128, 64, 4, 8>>(desc, count, total_tiles, grid, counter, stream);
         default: return hipErrorInvalidValue;
     }
 }

@@ -38,8 +38,12 @@ struct GroupedConfig {
 };
 constexpr int kNumGroupedConfigs = 10;
 extern const GroupedConfig kGroupedConfigs[kNumGroupedConfigs];
+// One persistent launch over the problems of `desc` (tile list in desc order,
+// 1 <= grid <= total_tiles workgroups), preceded by a one-lane kernel that
+// zeroes `counter` (device, 4 bytes), the tile queue the workgroups claim from;
+// launches of one counter must not overlap.
 hipError_t launch_gemm_f32_grouped(int config, const GroupedDesc* desc, int count, int total_tiles,
-                                   int grid, hipStream_t stream);
+                                   int grid, unsigned* counter, hipStream_t stream);
 // Resident workgroups per CU of the grouped kernel for a configuration.
 int grouped_blocks_per_cu(int config);
 

@@ -2393,7 +2393,8 @@ struct cmp_grouped_plan {
     int config = -1;
     int total_tiles = 0;
     int grid = 0;
-    cmp::GroupedDesc* desc = nullptr;     // device
+    cmp::GroupedDesc* desc = nullptr;     // device: the descriptors, then the tile-queue counter
+    unsigned* counter = nullptr;          // device, inside the descriptor allocation
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<float> config_ms;         // autotuner medians per configuration (NaN: not tried)
@@ -2401,7 +2402,10 @@ struct cmp_grouped_plan {
 
 namespace {
 
-// Descriptors for one tile configuration, problems in decreasing order of work.
+// Descriptors for one tile configuration.  A tile's time grows with its
+// problem's K, so problems go in decreasing order of K (then of M x N): the
+// kernel hands tiles out greedily in list order, and serving the longest
+// tiles first keeps the finishing times of the workgroups close together.
 int build_descs(cmp_ctx* c, const std::vector<cmp_gemm_args>& probs, int config,
                 std::vector<cmp::GroupedDesc>* out, int* total) {
     const int bm = cmp::kGroupedConfigs[config].bm, bn = cmp::kGroupedConfigs[config].bn;
@@ -2409,8 +2413,8 @@ int build_descs(cmp_ctx* c, const std::vector<cmp_gemm_args>& probs, int config,
     for (int i = 0; i < (int)probs.size(); ++i)
         if (probs[i].M > 0 && probs[i].N > 0) order.push_back(i);
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-        return (double)probs[x].M * probs[x].N * std::max<int64_t>(probs[x].K, 1) >
-               (double)probs[y].M * probs[y].N * std::max<int64_t>(probs[y].K, 1);
+        if (probs[x].K != probs[y].K) return probs[x].K > probs[y].K;
+        return (double)probs[x].M * probs[x].N > (double)probs[y].M * probs[y].N;
     });
     out->clear();
     int64_t start = 0;
@@ -2438,8 +2442,10 @@ int upload_descs(cmp_ctx* c, cmp_grouped_plan* pl, const std::vector<cmp::Groupe
                  hipStream_t s) {
     if (pl->desc) HIP_TRY(c, hipFree(pl->desc));
     pl->desc = nullptr;
-    const size_t bytes = std::max<size_t>(d.size(), 1) * sizeof(cmp::GroupedDesc);
-    HIP_TRY(c, hipMalloc(&pl->desc, bytes));
+    pl->counter = nullptr;
+    const size_t dbytes = (size_t)round_up((int64_t)(std::max<size_t>(d.size(), 1) * sizeof(cmp::GroupedDesc)), 256);
+    HIP_TRY(c, hipMalloc(&pl->desc, dbytes + 256));
+    pl->counter = reinterpret_cast<unsigned*>(reinterpret_cast<uint8_t*>(pl->desc) + dbytes);
     if (!d.empty())
         HIP_TRY(c, hipMemcpyAsync(pl->desc, d.data(), d.size() * sizeof(cmp::GroupedDesc),
                                   hipMemcpyHostToDevice, s));
@@ -2501,10 +2507,10 @@ CMP_API int cmp_grouped_plan_create(cmp_ctx* c, int count, const cmp_gemm_args* 
             if ((st = upload_descs(c, pl, d, s))) return cleanup(st);
             const int grid = grouped_grid(c, cfg, total);
             std::vector<float> t(reps);
-            hipError_t he = cmp::launch_gemm_f32_grouped(cfg, pl->desc, (int)d.size(), total, grid, s);
+            hipError_t he = cmp::launch_gemm_f32_grouped(cfg, pl->desc, (int)d.size(), total, grid, pl->counter, s);
             for (int r = 0; r < reps && he == hipSuccess; ++r) {
                 (void)hipEventRecord(e0, s);
-                he = cmp::launch_gemm_f32_grouped(cfg, pl->desc, (int)d.size(), total, grid, s);
+                he = cmp::launch_gemm_f32_grouped(cfg, pl->desc, (int)d.size(), total, grid, pl->counter, s);
                 (void)hipEventRecord(e1, s);
                 if (he == hipSuccess) he = hipEventSynchronize(e1);
                 if (he == hipSuccess) he = hipEventElapsedTime(&t[r], e0, e1);
@@ -2537,7 +2543,7 @@ CMP_API int cmp_grouped_plan_create(cmp_ctx* c, int count, const cmp_gemm_args* 
     if (he == hipSuccess) he = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (he == hipSuccess) {
         hipError_t le = cmp::launch_gemm_f32_grouped(pl->config, pl->desc, pl->count, pl->total_tiles,
-                                                     pl->grid, cap);
+                                                     pl->grid, pl->counter, cap);
         he = hipStreamEndCapture(cap, &pl->graph);
         if (he == hipSuccess) he = le;
     }
@@ -2568,7 +2574,7 @@ CMP_API int cmp_grouped_launch(cmp_grouped_plan* pl, void* stream) {
     if (!pl) return CMP_EINVAL;
     cmp_ctx* c = pl->ctx;
     HIP_TRY(c, cmp::launch_gemm_f32_grouped(pl->config, pl->desc, pl->count, pl->total_tiles, pl->grid,
-                                            (hipStream_t)stream));
+                                            pl->counter, (hipStream_t)stream));
     return CMP_OK;
 }
 
