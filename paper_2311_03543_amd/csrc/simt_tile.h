@@ -7,9 +7,10 @@
 // k-major so a lane's TM row values are two TM/2-wide LDS reads), double
 // buffered: the next step's global loads are in flight in registers while the
 // current step computes.  Lane (tx, ty) owns rows ty*TM/2 + [0, TM/2) and
-// BM/2 + ty*TM/2 + [0, TM/2), columns likewise with tx and TN: the lanes of a
-// wave that share ty read one broadcast address, and the B reads of a wave
-// are contiguous, so LDS reads are conflict-free.
+// BM/2 + ty*TM/2 + [0, TM/2), and the TN columns g*BN*4/TN + tx*4 + [0, 4)
+// for g < TN/4: the lanes of a wave that share ty read one broadcast address
+// of A, and each 16-byte B read of the 16 lanes that share ty covers 256
+// contiguous bytes, so LDS reads are conflict-free.
 //
 // Every output entry is one lane's chain of FP32 FMAs over k in increasing
 // order, whatever the tile shape, so all configurations give bit-identical C.
@@ -144,7 +145,12 @@ template <typename Cfg, bool VEC>
 __device__ __forceinline__ void simt_tile(const SimtProblem& p, int64_t m0, int64_t n0,
                                           float* smem) {
     constexpr int BK = Cfg::BK, TM = Cfg::TM, TN = Cfg::TN;
-    constexpr int HM = TM / 2, HN = TN / 2;
+    constexpr int HM = TM / 2;
+    // A lane's TN columns are NG groups of 4, GS columns apart: one 16-byte
+    // LDS read per group, and the 16 lanes of a wave that share ty read 256
+    // contiguous bytes (all 64 banks once).
+    constexpr int NG = TN / 4, GS = Cfg::BN / NG;
+    static_assert(TN % 4 == 0 && GS == 4 * Cfg::TX, "column groups of four");
     // buffer b of A at smem + b * ASZ, of B at smem + 2 * ASZ + b * BSZ (plain
     // offsets keep the pointers in the LDS address space: ds_read, not flat)
     constexpr int ASZ = BK * Cfg::APITCH, BSZ = BK * Cfg::BN;
@@ -175,8 +181,8 @@ __device__ __forceinline__ void simt_tile(const SimtProblem& p, int64_t m0, int6
             float av[TM], bv[TN];
             lds_vec<HM>(a_s + k * Cfg::APITCH + ty * HM, av);
             lds_vec<HM>(a_s + k * Cfg::APITCH + Cfg::BM / 2 + ty * HM, av + HM);
-            lds_vec<HN>(b_s + k * Cfg::BN + tx * HN, bv);
-            lds_vec<HN>(b_s + k * Cfg::BN + Cfg::BN / 2 + tx * HN, bv + HN);
+#pragma unroll
+            for (int g = 0; g < NG; ++g) lds_vec<4>(b_s + k * Cfg::BN + g * GS + tx * 4, bv + 4 * g);
 #pragma unroll
             for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -187,36 +193,31 @@ __device__ __forceinline__ void simt_tile(const SimtProblem& p, int64_t m0, int6
     }
 
     // Epilogue: C = alpha * acc + beta * C (C not read when beta == 0).
-    const bool cvec = ((p.ldc & 3) == 0) && ((reinterpret_cast<uintptr_t>(p.C) & 15) == 0) &&
-                      (HN % 4 == 0);
+    const bool cvec = ((p.ldc & 3) == 0) && ((reinterpret_cast<uintptr_t>(p.C) & 15) == 0);
 #pragma unroll
     for (int i = 0; i < TM; ++i) {
         const int64_t row = m0 + (i < HM ? ty * HM + i : Cfg::BM / 2 + ty * HM + (i - HM));
         if (row >= p.M) continue;
         gfloat crow = (gfloat)p.C + row * p.ldc;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int64_t col = n0 + h * (Cfg::BN / 2) + tx * HN;
-            float v[HN];
+        for (int h = 0; h < NG; ++h) {
+            const int64_t col = n0 + h * GS + tx * 4;
+            float v[4];
 #pragma unroll
-            for (int j = 0; j < HN; ++j) v[j] = p.alpha * acc[i][h * HN + j];
-            if (cvec && col + HN - 1 < p.N) {
-#pragma unroll
-                for (int q4 = 0; q4 < HN / 4; ++q4) {
-                    gf32x4 q = (gf32x4)(crow + col + 4 * q4);
-                    float* w = v + 4 * q4;
-                    if (p.beta != 0.f) {
-                        const f32x4 o = *q;
-                        w[0] = __builtin_fmaf(p.beta, o.x, w[0]);
-                        w[1] = __builtin_fmaf(p.beta, o.y, w[1]);
-                        w[2] = __builtin_fmaf(p.beta, o.z, w[2]);
-                        w[3] = __builtin_fmaf(p.beta, o.w, w[3]);
-                    }
-                    *q = f32x4{w[0], w[1], w[2], w[3]};
+            for (int j = 0; j < 4; ++j) v[j] = p.alpha * acc[i][4 * h + j];
+            if (cvec && col + 3 < p.N) {
+                gf32x4 q = (gf32x4)(crow + col);
+                if (p.beta != 0.f) {
+                    const f32x4 o = *q;
+                    v[0] = __builtin_fmaf(p.beta, o.x, v[0]);
+                    v[1] = __builtin_fmaf(p.beta, o.y, v[1]);
+                    v[2] = __builtin_fmaf(p.beta, o.z, v[2]);
+                    v[3] = __builtin_fmaf(p.beta, o.w, v[3]);
                 }
+                *q = f32x4{v[0], v[1], v[2], v[3]};
             } else {
 #pragma unroll
-                for (int j = 0; j < HN; ++j) {
+                for (int j = 0; j < 4; ++j) {
                     if (col + j < p.N) {
                         float o = v[j];
                         if (p.beta != 0.f) o = __builtin_fmaf(p.beta, crow[col + j], o);
