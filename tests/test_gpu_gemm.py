@@ -403,6 +403,25 @@ def test_square_8192_sampled(cx, name):
     assert err <= BOUND[name], err
 
 
+@pytest.mark.parametrize("name", VARIANTS)
+@pytest.mark.parametrize("M,N,K", [(8192, 8192, 8192), (8191, 8189, 8190)])
+def test_full_size_integer_sampled_exact(cx, name, M, N, K):
+    """At the measured size (and one short of it in every dimension: ragged last tiles, a
+    ragged last K block) small-integer operands make every variant exact.  The expected
+    entries are int64 dot products of the sampled rows and columns; the sample holds the
+    four corners and the last row and column of every tile edge it can reach."""
+    A = synth.int_matrix(M, K, 8001 + M)
+    B = synth.int_matrix(K, N, 8002 + N)
+    C = run(cx, name, A, B)
+    ij = synth.sample_entries(M, N, 4096, 8003)
+    edge = np.array([(0, 0), (0, N - 1), (M - 1, 0), (M - 1, N - 1), (255, 256), (256, 255),
+                     (M - 1, N // 2), (M // 2, N - 1)], np.int64)
+    ij = np.concatenate([ij, edge])
+    want = np.einsum("ik,ki->i", A[ij[:, 0]].astype(np.int64), B[:, ij[:, 1]].astype(np.int64))
+    got = C[ij[:, 0], ij[:, 1]].astype(np.float64)
+    assert np.array_equal(got, want.astype(np.float64)), (name, int(np.sum(got != want)))
+
+
 # ---- operands whose magnitude changes from tile to tile ----------------------------
 # Tile (i, j) of 128 x 128 entries of A and of B^T is scaled by 2^((3 i + 5 j) mod 23 - 11):
 # every FP8 tile scale and MX block scale differs from its neighbours, so a swapped or
