@@ -558,7 +558,8 @@ def grouped_experiment(cx, pa, torch, args):
 
 def stream_experiment(pa, torch, args):
     """10000 requests over 50 shapes (M, N, K log-uniform in [64, 4096]), Zipf(1.1) ranks,
-    tolerance per request, 20% ill-conditioned operands served in verify mode."""
+    tolerance per request, 20% ill-conditioned operands served in verify mode; each request
+    completes before the next is submitted."""
     from paper_2311_03543_amd import stream as st
     req = st.make_stream(nshapes=50, nreq=args.stream_requests, lo=64, hi=4096, s=1.1, ill_frac=0.2, seed=5)
     pool = st.build_pool(req["shapes"], seed=9, device_gen=True)
@@ -577,21 +578,30 @@ def stream_experiment(pa, torch, args):
             a, b = pool[sh]["well"][0]
             cx.gemm(a, b, pool[sh]["C"], tol=t)
     torch.cuda.synchronize()
+    # served by the library's executor (cmp_gemm_stream), then once more one cmp_gemm per
+    # request from Python, for the host overhead of the binding
     t0 = time.perf_counter()
-    lat, chosen, fallbacks = st.run_stream(cx, req, pool, verify_ill=True)
+    lat, chosen, fallbacks = st.run_stream_native(cx, req, pool, verify_ill=True)
     wall = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    lat_py, _, _ = st.run_stream(cx, req, pool, verify_ill=True)
+    wall_py = time.perf_counter() - t0
     cx.close()
     flops = sum(2.0 * shapes[r - 1][0] * shapes[r - 1][1] * shapes[r - 1][2] for r in req["ranks"])
     mix = {pa.BUILTIN_VARIANTS[v]: int((chosen == v).sum()) for v in range(4)}
     ill = req["ill"]
-    res = dict(requests=len(lat), wall_s=wall, req_per_s=len(lat) / wall, tflops=flops / wall / 1e12,
+    res = dict(requests=len(lat), executor="cmp_gemm_stream", wall_s=wall, req_per_s=len(lat) / wall,
+               tflops=flops / wall / 1e12,
                p50_us=float(np.percentile(lat, 50)), p99_us=float(np.percentile(lat, 99)),
                p50_us_well=float(np.percentile(lat[~ill], 50)), p99_us_well=float(np.percentile(lat[~ill], 99)),
                p50_us_ill_verify=float(np.percentile(lat[ill], 50)),
                p99_us_ill_verify=float(np.percentile(lat[ill], 99)),
-               variant_mix=mix, verify_fallbacks=int(fallbacks))
+               variant_mix=mix, verify_fallbacks=int(fallbacks),
+               per_call_python=dict(req_per_s=len(lat_py) / wall_py, p50_us=float(np.percentile(lat_py, 50)),
+                                    p99_us=float(np.percentile(lat_py, 99))))
     log(f"stream: {res['req_per_s']:.0f} req/s, p50 {res['p50_us']:.0f} us, p99 {res['p99_us']:.0f} us, "
-        f"mix {mix}, fallbacks {fallbacks}")
+        f"mix {mix}, fallbacks {fallbacks}; one cmp_gemm per request from Python "
+        f"{res['per_call_python']['req_per_s']:.0f} req/s, p50 {res['per_call_python']['p50_us']:.0f} us")
     del pool
     torch.cuda.empty_cache()
     return res

@@ -300,6 +300,21 @@ int cmp_select_batch(cmp_ctx *ctx, const char *iface, int n, const cmp_context *
  * on `stream` (except in verify mode, which synchronises the stream to read
  * the probe).  *chosen (may be NULL) receives the variant id that ran. */
 int cmp_gemm(cmp_ctx *ctx, const cmp_gemm_args *args, double tol, void *stream, int *chosen);
+/* Serve a stream of `n` "gemm" requests in order, each as one cmp_gemm: its
+ * own context (shape, tols[i]) selects its variant (Sec. 2.2.2: one task per
+ * request, the codelet chosen at run time).  flags[i] & CMP_FLAG_VERIFY
+ * switches verify mode on for request i (flags may be NULL: the context's
+ * flags apply to every request; the context's flags are the same afterwards).
+ * sync != 0: each request is complete before the next is submitted, and
+ * lat_us[i] receives its latency in microseconds, host submission to
+ * completion on `stream`; sync == 0: the requests are only enqueued (lat_us
+ * unused).  chosen[i] receives the variant id that ran.  chosen and lat_us
+ * may be NULL.  Requests may share operands and C: they run in stream order.
+ * Stops at the first request that fails and returns its status; *done (may
+ * be NULL) receives the number of requests served before it. */
+int cmp_gemm_stream(cmp_ctx *ctx, int n, const cmp_gemm_args *reqs, const double *tols,
+                    const uint32_t *flags, int sync, void *stream, int *chosen, double *lat_us,
+                    int *done);
 /* Run one named variant of "gemm" by id, bypassing selection. */
 int cmp_gemm_variant(cmp_ctx *ctx, int id, const cmp_gemm_args *args, void *stream);
 /* Run a host-target variant of any interface (synchronous), bypassing selection. */

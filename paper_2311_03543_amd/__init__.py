@@ -224,6 +224,39 @@ class Compar:
         st = self.L.cmp_gemm(self.ctx, C.byref(args), tol, _stream_ptr(stream), C.byref(chosen))
         return st, chosen.value
 
+    def gemm_stream_raw(self, args, tols, verify=None, sync=True, stream=None):
+        """cmp_gemm_stream over a list of cmp_gemm_args: returns (status, requests served,
+        chosen ids, latencies in us or None)."""
+        import numpy as np
+        n = len(args)
+        arr = (cmp_gemm_args * max(n, 1))(*args)
+        t = np.ascontiguousarray(tols, dtype=np.float64)
+        if t.shape != (n,):
+            raise ValueError("one tolerance per request")
+        fl = None
+        if verify is not None:
+            fl = np.where(np.asarray(verify, dtype=bool), CMP_FLAG_VERIFY, 0).astype(np.uint32)
+            if fl.shape != (n,):
+                raise ValueError("one verify flag per request")
+        chosen = np.full(max(n, 1), -1, np.int32)
+        lat = np.zeros(max(n, 1), np.float64)
+        done = C.c_int(0)
+        st = self.L.cmp_gemm_stream(self.ctx, n, arr, t.ctypes.data_as(C.POINTER(C.c_double)),
+                                    None if fl is None else fl.ctypes.data_as(C.POINTER(C.c_uint32)),
+                                    1 if sync else 0, _stream_ptr(stream),
+                                    chosen.ctypes.data_as(C.POINTER(C.c_int)),
+                                    lat.ctypes.data_as(C.POINTER(C.c_double)), C.byref(done))
+        return st, done.value, chosen[:n].astype(np.int64), (lat[:n] if sync else None)
+
+    def gemm_stream(self, requests, tols, verify=None, sync=True, stream=None):
+        """Serve [(A, B, C[, alpha, beta]), ...] in order in the library (cmp_gemm_stream), each
+        request selected by its own tolerance; verify: per-request booleans (None: the
+        context's flags).  Returns (chosen ids, latencies in us, or None when sync is False)."""
+        st, _, chosen, lat = self.gemm_stream_raw([gemm_args(*r) for r in requests], tols, verify,
+                                                  sync, stream)
+        self._check(st)
+        return chosen, lat
+
     def call_host(self, iface: str, vid: int, args_ptr) -> int:
         return self.L.cmp_call_host(self.ctx, iface.encode(), vid, args_ptr)
 

@@ -100,6 +100,8 @@ SIGNATURES = {
     "cmp_select": (_I, [_P, _S, C.POINTER(cmp_context), _IP]),
     "cmp_select_batch": (_I, [_P, _S, _I, C.POINTER(cmp_context), _IP]),
     "cmp_gemm": (_I, [_P, C.POINTER(cmp_gemm_args), _D, _P, _IP]),
+    "cmp_gemm_stream": (_I, [_P, _I, C.POINTER(cmp_gemm_args), _DP, C.POINTER(C.c_uint32), _I, _P, _IP,
+                             _DP, _IP]),
     "cmp_gemm_variant": (_I, [_P, _I, C.POINTER(cmp_gemm_args), _P]),
     "cmp_gemm_variant_static": (_I, [_P, _I, C.POINTER(cmp_gemm_args), _P]),
     "cmp_call_host": (_I, [_P, _S, _I, _P]),

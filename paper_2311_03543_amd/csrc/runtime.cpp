@@ -1702,6 +1702,34 @@ CMP_API int cmp_gemm(cmp_ctx* c, const cmp_gemm_args* a, double tol, void* strea
     return CMP_OK;
 }
 
+CMP_API int cmp_gemm_stream(cmp_ctx* c, int n, const cmp_gemm_args* reqs, const double* tols,
+                            const uint32_t* flags, int sync, void* stream, int* chosen, double* lat_us,
+                            int* done) {
+    if (done) *done = 0;
+    if (!c) return CMP_EINVAL;
+    if (n < 0 || (n > 0 && (!reqs || !tols))) return fail(c, CMP_EINVAL, "bad request list");
+    const uint32_t saved = c->flags;
+    auto s = (hipStream_t)stream;
+    int st = CMP_OK;
+    for (int i = 0; i < n; ++i) {
+        if (flags) c->flags = (saved & ~(uint32_t)CMP_FLAG_VERIFY) | (flags[i] & (uint32_t)CMP_FLAG_VERIFY);
+        const auto t0 = std::chrono::steady_clock::now();
+        int id = -1;
+        st = cmp_gemm(c, &reqs[i], tols[i], stream, &id);
+        if (st == CMP_OK && sync && c->gpu) {
+            const hipError_t e = hipStreamSynchronize(s);
+            if (e != hipSuccess) st = hip_fail(c, e, "request stream");
+        }
+        if (st != CMP_OK) break;
+        if (sync && lat_us)
+            lat_us[i] = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+        if (chosen) chosen[i] = id;
+        if (done) *done = i + 1;
+    }
+    c->flags = saved;
+    return st;
+}
+
 CMP_API int cmp_time_variant(cmp_ctx* c, int id, const cmp_gemm_args* a, int warmup, int reps,
                              void* stream, float* med, float* mn, float* mean) {
     if (!c) return CMP_EINVAL;

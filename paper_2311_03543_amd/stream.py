@@ -1,6 +1,8 @@
 """Request-stream driver: many gemm requests of recurring shapes, each with its own tolerance,
-served one by one through cmp_gemm (selection by context, then execution), with the FP64
-residual probe switched on for requests whose operands are ill-conditioned.
+served one by one (selection by context, then execution), with the FP64 residual probe
+switched on for requests whose operands are ill-conditioned.  `run_stream_native` hands the
+whole list to the library's executor (cmp_gemm_stream: the loop, the selection, the waits and
+the latency clock are native); `run_stream` calls cmp_gemm once per request from Python.
 
 The stream: `nshapes` shapes with M, N, K log-uniform in [lo, hi] (rank = draw order);
 `nreq` requests whose shape rank follows a finite Zipf(s) law; tolerance uniform over the
@@ -61,6 +63,29 @@ def build_pool(shapes, seed=9, host_arrays=False, device_gen=False):
         ent["C"] = torch.zeros((M, N), dtype=torch.float32, device="cuda")
         pool.append(ent)
     return pool
+
+
+def requests_of(stream, pool, outputs=None):
+    """(A, B, C) per request in stream order; C is the shape's shared output unless
+    `outputs` gives one tensor per request."""
+    reqs = []
+    for i in range(len(stream["ranks"])):
+        sh = int(stream["ranks"][i]) - 1
+        kind = "ill" if stream["ill"][i] else "well"
+        A, B = pool[sh][kind][i % 2]
+        reqs.append((A, B, pool[sh]["C"] if outputs is None else outputs[i]))
+    return reqs
+
+
+def run_stream_native(cx, stream, pool, verify_ill=True, outputs=None):
+    """Serve every request through cmp_gemm_stream, each complete before the next; returns
+    per-request latency (us, host submit to completion, measured by the library), chosen
+    variant ids and the context's verify-mode fallback count."""
+    reqs = requests_of(stream, pool, outputs)
+    verify = np.asarray(stream["ill"], dtype=bool) & bool(verify_ill)
+    chosen, lat = cx.gemm_stream(reqs, np.asarray(stream["tols"], dtype=np.float64), verify=verify,
+                                 sync=True)
+    return lat, chosen, cx.last_verify()[1]
 
 
 def run_stream(cx, stream, pool, verify_ill=True, on_result=None):

@@ -236,6 +236,49 @@ def test_gemm_dispatch_to_host_variants_and_fallback():
     assert st == 0 and chosen == 0
 
 
+def test_request_stream_selects_per_request_and_stops_at_a_failure():
+    """cmp_gemm_stream serves requests in order, each selected by its own tolerance exactly as
+    cmp_select chooses it; a request no variant admits ends the stream with its status and the
+    count of requests served before it."""
+    c = host_ctx()
+    ran = []
+
+    def matmul(i):
+        def fn(args, ws, wsb, stream, user):
+            a = pa.cmp_gemm_args.from_address(args)
+            ran.append(i)
+            A = np.ctypeslib.as_array(C.cast(a.A, C.POINTER(C.c_float)), (a.M, a.lda))
+            B = np.ctypeslib.as_array(C.cast(a.B, C.POINTER(C.c_float)), (a.K, a.ldb))
+            Cm = np.ctypeslib.as_array(C.cast(a.C, C.POINTER(C.c_float)), (a.M, a.ldc))
+            Cm[:, :a.N] = a.alpha * (A[:, :a.K] @ B[:, :a.N]) + (a.beta * Cm[:, :a.N] if a.beta else 0)
+            return 0
+        return fn
+    assert c.variant_register("gemm", "exact", pa.CMP_TARGET_HOST, matmul(0), 1e-5)[:2] == (0, 0)
+    assert c.variant_register("gemm", "quick", pa.CMP_TARGET_HOST, matmul(1), 1e-2)[:2] == (0, 1)
+    c.history_add(16, 24, 8, 0, 1, 5.0)
+    c.history_add(16, 24, 8, 1, 1, 1.0)
+    tols = [1e-5, 1e-2, 1e-3, 1e-2, 1e-5, 0.5]
+    ops = [synth.gemm_operands(16, 24, 8, seed=40 + i) for i in range(len(tols))]
+    outs = [np.zeros((16, 24), np.float32) for _ in tols]
+    args = [_host_gemm_args(A, B, Cm) for (A, B), Cm in zip(ops, outs)]
+    st, done, chosen, lat = c.gemm_stream_raw(args, tols, sync=True, stream=0)
+    assert st == 0 and done == len(tols)
+    assert list(chosen) == [c.select(16, 24, 8, t) for t in tols] == [0, 1, 0, 1, 0, 1]
+    assert ran == list(chosen)
+    assert np.all(lat >= 0)
+    for (A, B), Cm in zip(ops, outs):
+        assert np.allclose(Cm, A @ B, rtol=1e-5, atol=1e-5)
+    # the third request asks for 1e-9, which no variant meets
+    ran.clear()
+    st, done, chosen, _ = c.gemm_stream_raw(args[:5], [1e-2, 1e-5, 1e-9, 1e-2, 1e-2], sync=False, stream=0)
+    assert st == pa.CMP_ENOVARIANT and done == 2 and ran == [1, 0]
+    assert list(chosen[:2]) == [1, 0]
+    st, done, _, _ = c.gemm_stream_raw([], [], stream=0)
+    assert st == 0 and done == 0
+    with pytest.raises(ValueError):
+        c.gemm_stream_raw(args[:2], [1e-2], stream=0)
+
+
 def test_gemm_argument_validation():
     c = host_ctx()
     register_fakes(c)

@@ -41,3 +41,40 @@ def test_request_stream_outputs_within_tolerance():
     bad = [(i, e, t) for i, e, t in errors if not e <= t]
     assert not bad, bad[:5]
     assert np.all(lat > 0)
+
+
+def test_native_request_stream_outputs_within_tolerance():
+    """The same kind of stream served by the library's executor (cmp_gemm_stream) in one call,
+    every request with an output of its own so that all of them can be checked afterwards;
+    the ids chosen for requests outside verify mode equal those of one cmp_select per request
+    (a verify-mode request may fall back to a tighter variant)."""
+    import torch
+    import paper_2311_03543_amd as pa
+    from paper_2311_03543_amd import stream as st
+    req = st.make_stream(nshapes=10, nreq=200, lo=64, hi=768, seed=23)
+    pool = st.build_pool(req["shapes"], seed=4, host_arrays=True)
+    cx = pa.Compar(0)
+    try:
+        A = torch.randn(768 * 768, device="cuda")
+        B = torch.randn(768 * 768, device="cuda")
+        C = torch.zeros(768 * 768, device="cuda")
+        shapes = [tuple(map(int, s)) for s in req["shapes"]]
+        cx.calibrate(shapes, A, B, C, warmup=1, reps=3)
+        outs = []
+        for r in req["ranks"]:
+            M, N, _ = shapes[int(r) - 1]
+            outs.append(torch.zeros((M, N), device="cuda"))
+        say("  serving 200 requests natively")
+        lat, chosen, _ = st.run_stream_native(cx, req, pool, verify_ill=True, outputs=outs)
+        want = [cx.select(*shapes[int(r) - 1], float(t)) for r, t in zip(req["ranks"], req["tols"])]
+    finally:
+        cx.close()
+    assert all(c == w for c, w, ill in zip(chosen, want, req["ill"]) if not ill)
+    assert np.all(lat > 0)
+    for i in range(len(chosen)):
+        assert BOUNDS[chosen[i]] <= req["tols"][i]
+        sh = int(req["ranks"][i]) - 1
+        kind = "ill" if req["ill"][i] else "well"
+        Ah, Bh = pool[sh]["host"][kind][i % 2]
+        err = oracle.relfro(host(outs[i]), oracle.gemm(Ah, Bh))
+        assert err <= req["tols"][i], (i, err, req["tols"][i])
