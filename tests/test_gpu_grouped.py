@@ -113,3 +113,30 @@ def test_degenerate_problems_in_a_group(cx):
         assert oracle.relfro(host(c4), oracle.gemm(A, B, -1.5, 0.25, C0)) <= 1e-5
     finally:
         plan.destroy()
+
+
+@pytest.mark.parametrize("cfg", [0, 4, 7])
+def test_tile_queue_with_many_more_tiles_than_workgroups(cx, cfg):
+    """A group with several times more tiles than resident workgroups, so that most tiles are
+    claimed from the plan's counter: every problem bit-identical to its own f32_simt launch, on
+    an eager launch, a second eager launch (the counter is zeroed again) and a graph replay."""
+    import torch
+    probs = _problems(300, 7, 192, 1024)
+    dprobs = [(dev(A), dev(B)) for A, B in probs]
+    ref = _run_separate(cx, dprobs)
+    outs = [torch.zeros((A.shape[0], B.shape[1]), device="cuda") for A, B in probs]
+    plan = cx.grouped_plan([(a, b, o) for (a, b), o in zip(dprobs, outs)], config=cfg)
+    try:
+        info = plan.info()
+        say(f"  grouped config {cfg}: {info['tiles']} tiles on {info['grid']} workgroups")
+        assert info["tiles"] >= 3 * info["grid"]
+        for how in ("launch", "launch", "graph"):
+            for o in outs:
+                o.fill_(float("nan"))
+            torch.cuda.synchronize()
+            plan.launch() if how == "launch" else plan.graph_launch()
+            got = [host(o) for o in outs]
+            for g_, r in zip(got, ref):
+                assert np.array_equal(g_.view(np.uint32), r.view(np.uint32)), how
+    finally:
+        plan.destroy()

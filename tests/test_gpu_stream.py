@@ -67,6 +67,20 @@ def test_native_request_stream_outputs_within_tolerance():
         say("  serving 200 requests natively")
         lat, chosen, _ = st.run_stream_native(cx, req, pool, verify_ill=True, outputs=outs)
         want = [cx.select(*shapes[int(r) - 1], float(t)) for r, t in zip(req["ranks"], req["tols"])]
+        first = [host(o) for o in outs]
+        # the same stream only enqueued (sync = 0, no verify mode): the requests that ran
+        # without verify mode before get the same variants and the same bits
+        for o in outs:
+            o.zero_()
+        say("  serving 200 requests natively, enqueue only")
+        chosen2, lat2 = cx.gemm_stream(st.requests_of(req, pool, outs), np.asarray(req["tols"], np.float64),
+                                       verify=np.zeros(len(outs), bool), sync=False)
+        torch.cuda.synchronize()
+        assert lat2 is None
+        for i, o in enumerate(outs):
+            if not req["ill"][i]:
+                assert chosen2[i] == chosen[i]
+                assert np.array_equal(first[i].view(np.uint32), host(o).view(np.uint32))
     finally:
         cx.close()
     assert all(c == w for c, w, ill in zip(chosen, want, req["ill"]) if not ill)
