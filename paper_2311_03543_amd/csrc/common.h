@@ -71,4 +71,32 @@ __host__ __device__ __forceinline__ int64_t mx6_scale_offset(int64_t row, int64_
     return (((row >> 8) * nkb + kb) << 10) + (row & 255) * 4 + 2 * h + level;
 }
 
+// Workgroup `blk` of a launch that runs ta workgroups of one kind and tb of
+// another (the operand pre-passes of A and B in one launch), spread evenly:
+// the second kind sits at the blocks where floor(blk * tb / (ta + tb)) steps,
+// so both kinds stream side by side in proportion for the whole launch.
+// *index is the workgroup's number within its kind.
+__device__ __forceinline__ bool second_kind(int64_t blk, int64_t ta, int64_t tb, int64_t* index) {
+    const int64_t total = ta + tb;
+    const int64_t before = blk * tb / total, upto = (blk + 1) * tb / total;
+    *index = upto > before ? before : blk - before;
+    return upto > before;
+}
+
+// The same over groups of eight consecutive workgroups, which the hardware
+// hands to the eight XCDs in turn: every XCD gets its share of both kinds
+// (a plain A, B, A, B order would put all of A on four XCDs).  A launch of
+// paired_blocks(ta, tb) workgroups; returns 0 (first kind), 1 (second kind)
+// or -1 for the few workgroups past the end of a kind's last group.
+__host__ __device__ __forceinline__ int64_t paired_blocks(int64_t ta, int64_t tb) {
+    return 8 * ((ta + 7) / 8 + (tb + 7) / 8);
+}
+__device__ __forceinline__ int paired_kind(int64_t blk, int64_t ta, int64_t tb, int64_t* index) {
+    int64_t g;
+    const bool second = second_kind(blk >> 3, (ta + 7) / 8, (tb + 7) / 8, &g);
+    *index = 8 * g + (blk & 7);
+    if (*index >= (second ? tb : ta)) return -1;
+    return second ? 1 : 0;
+}
+
 }  // namespace cmp

@@ -80,6 +80,14 @@ hipError_t launch_quant_fp8(int64_t rows, int64_t cols, const float* X, int64_t 
                             uint8_t* q, uint8_t* qscale, uint8_t* rq, uint8_t* rscale,
                             hipStream_t stream);
 
+// Both operands' tiled FP8 images in one launch, as launch_quant_fp8 with
+// tiled = true gives them: A (M x K, lda) into Mp x Kp codes, B (K x N, ldb)
+// transposed into Np x Kp codes, with their scale arrays.
+hipError_t launch_quant_fp8_pair(int64_t M, int64_t N, int64_t K, const float* A, int64_t lda,
+                                const float* B, int64_t ldb, int64_t Mp, int64_t Np, int64_t Kp,
+                                uint8_t* aq, uint8_t* aqs, uint8_t* ar, uint8_t* ars, uint8_t* bq,
+                                uint8_t* bqs, uint8_t* br, uint8_t* brs, hipStream_t stream);
+
 // MX E2M3 quantisation with one residual level, one E8M0 scale per 32 K values.
 //   transpose = false: X is rows x cols, blocks along its rows (K = cols), one
 //                      output row per row of X.
@@ -91,6 +99,13 @@ hipError_t launch_quant_fp8(int64_t rows, int64_t cols, const float* X, int64_t 
 //                  multiple of 64); rscale unused.
 //   tiled = false: one code per byte, row-major (output rows x K), scale
 //                  bytes output rows x ceil(K / 32); out_rows, Kp unused.
+// Both operands' tiled MX FP6 images in one launch, as launch_quant_mx6 with
+// tiled = true gives them: A (M x K, lda) into Mp rows (codes aq / ar, scales
+// as), B (K x N, ldb) transposed into Np rows (bq / br / bs), Kp K values.
+hipError_t launch_quant_mx6_pair(int64_t M, int64_t N, int64_t K, const float* A, int64_t lda,
+                                const float* B, int64_t ldb, int64_t Mp, int64_t Np, int64_t Kp,
+                                uint8_t* aq, uint8_t* ar, uint8_t* as, uint8_t* bq, uint8_t* br,
+                                uint8_t* bs, hipStream_t stream);
 hipError_t launch_quant_mx6(int64_t rows, int64_t cols, const float* X, int64_t ldx,
                             bool transpose, bool tiled, int64_t out_rows, int64_t Kp, uint8_t* q,
                             uint8_t* qscale, uint8_t* rq, uint8_t* rscale, hipStream_t stream);

@@ -80,16 +80,17 @@ __device__ __forceinline__ uint32_t mx6_level2(const float (&r)[4], int e) {
 // packed 192 bits from the 24-bit words of two neighbours; lane 6 writes the
 // block's two scale bytes.
 constexpr int kMx6RowsPerLane = 4;
+// Workgroup (bx, by) of a grid whose y extent is gy.
 template <bool VEC, bool TILED>
-__global__ __launch_bounds__(256) void quant_mx6_rows_kernel(
-    int64_t rows, int64_t cols, const float* __restrict__ X, int64_t ldx, int64_t out_rows,
-    int64_t Kp, uint8_t* __restrict__ q, uint8_t* __restrict__ qscale, uint8_t* __restrict__ rq,
-    uint8_t* __restrict__ rscale) {
+__device__ __forceinline__ void quant_mx6_rows(
+    int bx, int64_t by, int64_t gy, int64_t rows, int64_t cols, const float* __restrict__ X, int64_t ldx,
+    int64_t out_rows, int64_t Kp, uint8_t* __restrict__ q, uint8_t* __restrict__ qscale,
+    uint8_t* __restrict__ rq, uint8_t* __restrict__ rscale) {
     // grid: x over the 8 nb lanes of one output row (nb * 8 < 2^31), y over rows
     const int nb = (int)(TILED ? Kp / 32 : (cols + 31) / 32);   // blocks per output row
     const int64_t nrows = TILED ? out_rows : rows;
     const int64_t nkb = Kp / 64;
-    const int i = (int)blockIdx.x * 256 + (int)threadIdx.x;    // lane of the row: block i / 8
+    const int i = bx * 256 + (int)threadIdx.x;                  // lane of the row: block i / 8
     if ((i >> 3) >= nb) return;                                 // whole 8-lane groups only
     const int lane = threadIdx.x & 63;
     const int li = lane & 7, gbase = lane & ~7;
@@ -100,7 +101,7 @@ __global__ __launch_bounds__(256) void quant_mx6_rows_kernel(
     const int b = i >> 3;
     const int64_t k = (int64_t)b * 32 + 4 * li;
     constexpr int RPL = kMx6RowsPerLane;
-    for (int64_t r0 = (int64_t)blockIdx.y * RPL; r0 < nrows; r0 += (int64_t)gridDim.y * RPL) {
+    for (int64_t r0 = by * RPL; r0 < nrows; r0 += gy * RPL) {
         float vr[RPL][4];
 #pragma unroll
         for (int rr = 0; rr < RPL; ++rr) {
@@ -177,30 +178,40 @@ __global__ __launch_bounds__(256) void quant_mx6_rows_kernel(
     }
 }
 
+template <bool VEC, bool TILED>
+__global__ __launch_bounds__(256) void quant_mx6_rows_kernel(
+    int64_t rows, int64_t cols, const float* __restrict__ X, int64_t ldx, int64_t out_rows,
+    int64_t Kp, uint8_t* __restrict__ q, uint8_t* __restrict__ qscale, uint8_t* __restrict__ rq,
+    uint8_t* __restrict__ rscale) {
+    quant_mx6_rows<VEC, TILED>((int)blockIdx.x, blockIdx.y, gridDim.y, rows, cols, X, ldx, out_rows, Kp,
+                               q, qscale, rq, rscale);
+}
+
 // ---------------------------------------------------------------------------
 // Columns of X (X is K x N; output row n = column n of X, blocks along K):
 // one lane per pair of blocks (64 K values, one 48-byte image row and its 4
 // scale bytes), consecutive lanes on consecutive columns, so each load of a
 // lane is one coalesced row segment of X and a wave's stores fill contiguous
 // 3 KiB of each code image.  The lane packs its 32 codes per block itself.
+// Workgroup (bx, by) of a grid whose y extent is gy; stage_h / stage_l are the
+// LDS staging blocks (kMx6Block bytes each when TILED).
 template <bool TILED>
-__global__ __launch_bounds__(256) void quant_mx6_cols_kernel(
-    int64_t K, int64_t N, const float* __restrict__ X, int64_t ldx, int64_t out_rows, int64_t Kp,
-    uint8_t* __restrict__ q, uint8_t* __restrict__ qscale, uint8_t* __restrict__ rq,
-    uint8_t* __restrict__ rscale) {
+__device__ __forceinline__ void quant_mx6_cols(
+    int64_t bx, int64_t by, int64_t gy, int64_t K, int64_t N, const float* __restrict__ X, int64_t ldx,
+    int64_t out_rows, int64_t Kp, uint8_t* __restrict__ q, uint8_t* __restrict__ qscale,
+    uint8_t* __restrict__ rq, uint8_t* __restrict__ rscale, uint4* stage_h, uint4* stage_l) {
     // grid: x over output rows (columns of X), y over pairs of blocks.  Tiled:
     // a workgroup's 256 rows are one 256-row image block, staged in LDS so that
     // its two 12 KiB code blocks leave as whole coalesced lines.
     static_assert(kMx6Block % (16 * 256) == 0, "a staged block is whole 16-byte stores per lane");
-    __shared__ uint4 stage_h[TILED ? kMx6Block / 16 : 1], stage_l[TILED ? kMx6Block / 16 : 1];
     const int64_t nb = TILED ? Kp / 32 : (K + 31) / 32;
     const int64_t npairs = (nb + 1) / 2;
     const int64_t nrows = TILED ? out_rows : N;
     const int64_t nkb = Kp / 64;
     const int t = threadIdx.x;
-    const int64_t n = (int64_t)blockIdx.x * 256 + t;
+    const int64_t n = bx * 256 + t;
     if (!TILED && n >= nrows) return;        // tiled: out_rows % 256 == 0, every lane has a row
-    for (int64_t pr = blockIdx.y; pr < npairs; pr += gridDim.y) {
+    for (int64_t pr = by; pr < npairs; pr += gy) {
         uint32_t scales = 0;                    // (h0 hi, h0 lo, h1 hi, h1 lo) of this row segment
 #pragma unroll 1
         for (int h = 0; h < 2; ++h) {
@@ -281,7 +292,7 @@ __global__ __launch_bounds__(256) void quant_mx6_cols_kernel(
         if (TILED) {
             *reinterpret_cast<uint32_t*>(qscale + mx6_scale_offset(n, pr, 0, 0, nkb)) = scales;
             __syncthreads();
-            const int64_t base = ((int64_t)blockIdx.x * nkb + pr) * kMx6Block;
+            const int64_t base = (bx * nkb + pr) * kMx6Block;
 #pragma unroll
             for (int c = 0; c < kMx6Block / 16 / 256; ++c) {
                 reinterpret_cast<uint4*>(q + base)[t + 256 * c] = stage_h[t + 256 * c];
@@ -292,9 +303,63 @@ __global__ __launch_bounds__(256) void quant_mx6_cols_kernel(
     }
 }
 
+template <bool TILED>
+__global__ __launch_bounds__(256) void quant_mx6_cols_kernel(
+    int64_t K, int64_t N, const float* __restrict__ X, int64_t ldx, int64_t out_rows, int64_t Kp,
+    uint8_t* __restrict__ q, uint8_t* __restrict__ qscale, uint8_t* __restrict__ rq,
+    uint8_t* __restrict__ rscale) {
+    __shared__ uint4 stage_h[TILED ? kMx6Block / 16 : 1], stage_l[TILED ? kMx6Block / 16 : 1];
+    quant_mx6_cols<TILED>(blockIdx.x, blockIdx.y, gridDim.y, K, N, X, ldx, out_rows, Kp, q, qscale, rq,
+                          rscale, stage_h, stage_l);
+}
+
+// Both operands' MX FP6 images in one launch: A by rows (a.gx x a.gy
+// workgroups of quant_mx6_rows) and B by columns (b.gx x b.gy workgroups of
+// quant_mx6_cols), interleaved by paired_kind.
+struct Mx6Operand {
+    int64_t rows, cols, ldx, out_rows, Kp, gx, gy;
+    const float* X;
+    uint8_t *q, *qscale, *rq;
+};
+template <bool VA>
+__global__ __launch_bounds__(256) void quant_mx6_pair_kernel(Mx6Operand a, Mx6Operand b) {
+    __shared__ uint4 stage_h[kMx6Block / 16], stage_l[kMx6Block / 16];
+    int64_t w;
+    const int kind = paired_kind(blockIdx.x, a.gx * a.gy, b.gx * b.gy, &w);
+    if (kind < 0) return;
+    if (kind == 1)
+        quant_mx6_cols<true>(w % b.gx, w / b.gx, b.gy, b.rows, b.cols, b.X, b.ldx, b.out_rows, b.Kp, b.q,
+                             b.qscale, b.rq, nullptr, stage_h, stage_l);
+    else
+        quant_mx6_rows<VA, true>((int)(w % a.gx), w / a.gx, a.gy, a.rows, a.cols, a.X, a.ldx, a.out_rows,
+                                 a.Kp, a.q, a.qscale, a.rq, nullptr);
+}
+
 unsigned cap(int64_t v, int64_t m) { return (unsigned)(v < 1 ? 1 : (v > m ? m : v)); }
 
 }  // namespace
+
+hipError_t launch_quant_mx6_pair(int64_t M, int64_t N, int64_t K, const float* A, int64_t lda,
+                                const float* B, int64_t ldb, int64_t Mp, int64_t Np, int64_t Kp,
+                                uint8_t* aq, uint8_t* ar, uint8_t* as, uint8_t* bq, uint8_t* br,
+                                uint8_t* bs, hipStream_t stream) {
+    if (M <= 0 || N <= 0 || K <= 0 || !A || !B || !aq || !ar || !as || !bq || !br || !bs ||
+        Mp % kPanelRows || Np % kPanelRows || Mp < M || Np < N || Kp % 64 || Kp < K)
+        return hipErrorInvalidValue;
+    const int64_t nb = Kp / 32;
+    if (nb * 8 >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+    Mx6Operand a{M, K, lda, Mp, Kp, (int64_t)cap((nb * 8 + 255) / 256, 1 << 30),
+                 (int64_t)cap((Mp + kMx6RowsPerLane - 1) / kMx6RowsPerLane, 65535), A, aq, as, ar};
+    Mx6Operand b{K, N, ldb, Np, Kp, Np / 256, (int64_t)cap((nb + 1) / 2, 65535), B, bq, bs, br};
+    const int64_t blocks = paired_blocks(a.gx * a.gy, b.gx * b.gy);
+    if (blocks >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+    const bool va = (lda % 4 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
+    if (va)
+        hipLaunchKernelGGL(quant_mx6_pair_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, stream, a, b);
+    else
+        hipLaunchKernelGGL(quant_mx6_pair_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, stream, a, b);
+    return hipGetLastError();
+}
 
 hipError_t launch_quant_mx6(int64_t rows, int64_t cols, const float* X, int64_t ldx,
                             bool transpose, bool tiled, int64_t out_rows, int64_t Kp, uint8_t* q,

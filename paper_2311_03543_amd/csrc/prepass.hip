@@ -256,14 +256,15 @@ __device__ __forceinline__ uint32_t level1(float (&v)[16], uint32_t (&qw)[4], in
 // does).  The code images are row-major out_rows x out_cols (TILED false) or
 // panel images with out_cols bytes of K per row (TILED true).
 template <bool VEC, bool TRANS, bool TILED>
-__device__ __forceinline__ void quant_tile(int64_t rows, int64_t cols, const float* __restrict__ X,
-                                           int64_t ldx, int64_t out_cols, uint8_t* __restrict__ q,
-                                           uint8_t* __restrict__ qscale, uint8_t* __restrict__ rq,
-                                           uint8_t* __restrict__ rscale, uint32_t* red) {
+__device__ __forceinline__ void quant_tile(int64_t tile, int64_t rows, int64_t cols,
+                                           const float* __restrict__ X, int64_t ldx, int64_t out_cols,
+                                           uint8_t* __restrict__ q, uint8_t* __restrict__ qscale,
+                                           uint8_t* __restrict__ rq, uint8_t* __restrict__ rscale,
+                                           uint32_t* red) {
     const int t = threadIdx.x;
     const int64_t ot_cols = out_cols / 128;
     const int64_t nkb = out_cols / kPanelRowBytes;
-    const int64_t ot_r = blockIdx.x / ot_cols, ot_c = blockIdx.x % ot_cols;
+    const int64_t ot_r = tile / ot_cols, ot_c = tile % ot_cols;
     // tile origin in X coordinates
     const int64_t x_r0 = TRANS ? ot_c * 128 : ot_r * 128;
     const int64_t x_c0 = TRANS ? ot_r * 128 : ot_c * 128;
@@ -342,8 +343,8 @@ __device__ __forceinline__ void quant_tile(int64_t rows, int64_t cols, const flo
                               ldexpf(v[i][4 * m + 2], er), ldexpf(v[i][4 * m + 3], er));
 
     if (t == 0) {
-        qscale[blockIdx.x] = (uint8_t)(127 - e);
-        rscale[blockIdx.x] = (uint8_t)(127 - er);
+        qscale[tile] = (uint8_t)(127 - e);
+        rscale[tile] = (uint8_t)(127 - er);
     }
     const int64_t ocol = ot_c * 128 + 16 * g;
 #pragma unroll
@@ -361,7 +362,31 @@ __global__ __launch_bounds__(256) void quant_fp8_kernel(
     uint8_t* __restrict__ q, uint8_t* __restrict__ qscale, uint8_t* __restrict__ rq,
     uint8_t* __restrict__ rscale) {
     __shared__ uint32_t red[8];    // the two reductions
-    quant_tile<VEC, TRANS, TILED>(rows, cols, X, ldx, out_cols, q, qscale, rq, rscale, red);
+    quant_tile<VEC, TRANS, TILED>(blockIdx.x, rows, cols, X, ldx, out_cols, q, qscale, rq, rscale, red);
+}
+
+// The images of both operands of a GEMM in one launch: A (M x K, a.tiles
+// tiles) and B (K x N, transposed into its N x K image, b.tiles tiles), the
+// tiles of the two interleaved by paired_kind, so the two halves stream from
+// HBM side by side and one launch replaces two kernels on two streams with
+// their event fork and join.
+struct QuantOperand {
+    int64_t rows, cols, ldx, out_cols, tiles;
+    const float* X;
+    uint8_t *q, *qscale, *rq, *rscale;
+};
+template <bool VA, bool VB>
+__global__ __launch_bounds__(256) void quant_fp8_pair_kernel(QuantOperand a, QuantOperand b) {
+    __shared__ uint32_t red[8];
+    int64_t tile;
+    const int kind = paired_kind(blockIdx.x, a.tiles, b.tiles, &tile);
+    if (kind < 0) return;
+    if (kind == 1)
+        quant_tile<VB, true, true>(tile, b.rows, b.cols, b.X, b.ldx, b.out_cols, b.q, b.qscale, b.rq,
+                                   b.rscale, red);
+    else
+        quant_tile<VA, false, true>(tile, a.rows, a.cols, a.X, a.ldx, a.out_cols, a.q, a.qscale, a.rq,
+                                    a.rscale, red);
 }
 
 unsigned grid_for(int64_t work, int64_t per_block) {
@@ -372,6 +397,26 @@ unsigned grid_for(int64_t work, int64_t per_block) {
 }
 
 }  // namespace
+
+hipError_t launch_quant_fp8_pair(int64_t M, int64_t N, int64_t K, const float* A, int64_t lda,
+                                const float* B, int64_t ldb, int64_t Mp, int64_t Np, int64_t Kp,
+                                uint8_t* aq, uint8_t* aqs, uint8_t* ar, uint8_t* ars, uint8_t* bq,
+                                uint8_t* bqs, uint8_t* br, uint8_t* brs, hipStream_t stream) {
+    if (M <= 0 || N <= 0 || K <= 0 || Kp % 128 || Mp % kPanelRows || Np % kPanelRows || Mp < M ||
+        Np < N || Kp < K)
+        return hipErrorInvalidValue;
+    const QuantOperand a{M, K, lda, Kp, (Mp / 128) * (Kp / 128), A, aq, aqs, ar, ars};
+    const QuantOperand b{K, N, ldb, Kp, (Np / 128) * (Kp / 128), B, bq, bqs, br, brs};
+    const bool va = (lda % 4 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
+    const bool vb = (ldb % 4 == 0) && ((reinterpret_cast<uintptr_t>(B) & 15) == 0);
+    const dim3 g((unsigned)paired_blocks(a.tiles, b.tiles));
+    auto go = [&](auto kernel) { hipLaunchKernelGGL(kernel, g, dim3(256), 0, stream, a, b); };
+    if (va && vb) go(quant_fp8_pair_kernel<true, true>);
+    else if (va) go(quant_fp8_pair_kernel<true, false>);
+    else if (vb) go(quant_fp8_pair_kernel<false, true>);
+    else go(quant_fp8_pair_kernel<false, false>);
+    return hipGetLastError();
+}
 
 hipError_t launch_split_a_bf16(int64_t M, int64_t K, const float* A, int64_t lda, int64_t Mp,
                                int64_t Kp, uint16_t* hi, uint16_t* lo, hipStream_t stream) {

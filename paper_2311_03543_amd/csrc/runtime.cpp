@@ -193,10 +193,6 @@ struct cmp_ctx {
     size_t vws_bytes = 0;
     float* mlp_dev = nullptr;  // params | m | v | X | Y | loss | grad | infer io
     hipStream_t side = nullptr;
-    // the B-operand pre-pass runs on `aux`, beside the A pre-pass on the
-    // caller's stream: fork/join through two events
-    hipStream_t aux = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // verify mode and fault injection
     double last_verify = -1.0;
     int fallbacks = 0;
@@ -544,25 +540,6 @@ int v_f32_simt(const void* args, void*, size_t, void* stream, void* user) {
                : CMP_EHIP;
 }
 
-// The A and B FP8 pre-passes are independent HBM-bound kernels whose phases
-// (load, reduce, convert, store) leave bandwidth unused when each runs alone
-// (about 45 % of the HBM rate); the B pre-pass runs on the context's
-// auxiliary stream beside the A pre-pass.  (The bf16 splits stream at 55-70 %
-// and gain nothing from running side by side, so they stay on s.)
-// fork: `aux` waits for everything already queued on s (so the workspace is
-// no longer read by an earlier call); join: s waits for the B pre-pass.
-// Recording and waiting on events is legal inside a stream capture, so the
-// pair also works when the caller captures the call into a graph.
-hipError_t fork_aux(cmp_ctx* c, hipStream_t s) {
-    hipError_t e = hipEventRecord(c->ev_fork, s);
-    if (e == hipSuccess) e = hipStreamWaitEvent(c->aux, c->ev_fork, 0);
-    return e;
-}
-hipError_t join_aux(cmp_ctx* c, hipStream_t s) {
-    hipError_t e = hipEventRecord(c->ev_join, c->aux);
-    if (e == hipSuccess) e = hipStreamWaitEvent(s, c->ev_join, 0);
-    return e;
-}
 
 // Sum of the split-K partials into C (nothing to do without a split).
 int finish_split(cmp_ctx* c, const cmp_gemm_args* a, int splits, const float* partial,
@@ -576,8 +553,11 @@ int finish_split(cmp_ctx* c, const cmp_gemm_args* a, int splits, const float* pa
 }
 
 // The pre-pass of an image variant: the kernels that turn A and B into the
-// variant's images at `base` (laid out by images_of).  The FP8 and FP6
-// quantisations of B run on the auxiliary stream beside those of A.
+// variant's images at `base` (laid out by images_of), all on the caller's
+// stream.  The bf16 splits of A and B run one after the other (side by side
+// they streamed no faster); the FP8 and FP6 quantisations of A and B share
+// one launch whose workgroups interleave the two operands, because each alone
+// leaves HBM bandwidth unused (its phases load, reduce, convert and store).
 int prepass(cmp_ctx* c, int kind, const cmp_gemm_args* a, const Images& I, void* base,
             hipStream_t s) {
     if (kind == kImgBf16 || kind == kImgBf16x3) {
@@ -596,31 +576,22 @@ int prepass(cmp_ctx* c, int kind, const cmp_gemm_args* a, const Images& I, void*
             return CMP_EHIP;
         return CMP_OK;
     }
-    if (fork_aux(c, s) != hipSuccess) return CMP_EHIP;
+    // FP8 and FP6: both operands in one launch, their workgroups interleaved
     if (kind == kImgFp8r) {
-        {
-            KTimer kt(c, c->aux, "quant_fp8_bt");
-            if (cmp::launch_quant_fp8(a->K, a->N, a->B, a->ldb, true, true, I.Np, I.Kp, I.at(base, 2),
-                                      I.at(base, 6), I.at(base, 3), I.at(base, 7), c->aux) != hipSuccess)
-                return CMP_EHIP;
-        }
-        KTimer kt(c, s, "quant_fp8_a");
-        if (cmp::launch_quant_fp8(a->M, a->K, a->A, a->lda, false, true, I.Mp, I.Kp, I.at(base, 0),
-                                  I.at(base, 4), I.at(base, 1), I.at(base, 5), s) != hipSuccess)
-            return CMP_EHIP;
-    } else {
-        {
-            KTimer kt(c, c->aux, "quant_mx6_bt");
-            if (cmp::launch_quant_mx6(a->K, a->N, a->B, a->ldb, true, true, I.Np, I.Kp, I.at(base, 2),
-                                      I.at(base, 5), I.at(base, 3), nullptr, c->aux) != hipSuccess)
-                return CMP_EHIP;
-        }
-        KTimer kt(c, s, "quant_mx6_a");
-        if (cmp::launch_quant_mx6(a->M, a->K, a->A, a->lda, false, true, I.Mp, I.Kp, I.at(base, 0),
-                                  I.at(base, 4), I.at(base, 1), nullptr, s) != hipSuccess)
-            return CMP_EHIP;
+        KTimer kt(c, s, "quant_fp8_ab");
+        return cmp::launch_quant_fp8_pair(a->M, a->N, a->K, a->A, a->lda, a->B, a->ldb, I.Mp, I.Np, I.Kp,
+                                          I.at(base, 0), I.at(base, 4), I.at(base, 1), I.at(base, 5),
+                                          I.at(base, 2), I.at(base, 6), I.at(base, 3), I.at(base, 7),
+                                          s) == hipSuccess
+                   ? CMP_OK
+                   : CMP_EHIP;
     }
-    return join_aux(c, s) == hipSuccess ? CMP_OK : CMP_EHIP;
+    KTimer kt(c, s, "quant_mx6_ab");
+    return cmp::launch_quant_mx6_pair(a->M, a->N, a->K, a->A, a->lda, a->B, a->ldb, I.Mp, I.Np, I.Kp,
+                                      I.at(base, 0), I.at(base, 1), I.at(base, 4), I.at(base, 2),
+                                      I.at(base, 3), I.at(base, 5), s) == hipSuccess
+               ? CMP_OK
+               : CMP_EHIP;
 }
 
 // An image variant: pre-pass, then its GEMM kernel over the images (with
@@ -1255,14 +1226,7 @@ CMP_API int cmp_init(int device, cmp_ctx** out) {
             delete c;
             return CMP_EHIP;
         }
-        if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
-            hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
-            if (c->side) (void)hipStreamDestroy(c->side);
-            if (c->aux) (void)hipStreamDestroy(c->aux);
-            if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
-            if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+        if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) {
             delete c;
             return CMP_EHIP;
         }
@@ -1283,7 +1247,6 @@ CMP_API int cmp_terminate(cmp_ctx* c) {
     if (c->gpu) {
         (void)hipSetDevice(c->device);
         if (c->side) (void)hipStreamSynchronize(c->side);
-        if (c->aux) (void)hipStreamSynchronize(c->aux);
         (void)hipDeviceSynchronize();
         if (c->ws) (void)hipFree(c->ws);
         if (c->vws) (void)hipFree(c->vws);
@@ -1295,9 +1258,6 @@ CMP_API int cmp_terminate(cmp_ctx* c) {
         }
         for (auto e : c->kpool) (void)hipEventDestroy(e);
         if (c->side) (void)hipStreamDestroy(c->side);
-        if (c->aux) (void)hipStreamDestroy(c->aux);
-        if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
-        if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     }
     delete c;
     return CMP_OK;
