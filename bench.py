@@ -72,7 +72,11 @@ def kernel_roofline(name: str, M: int, N: int, K: int):
         return "hbm", 4.0 * M * K + 2.0 * M * Kp128, PEAK["hbm_gbs"], "GB/s"
     if name == "quant_fp8_bt":
         return "hbm", 4.0 * K * N + 2.0 * N * Kp128, PEAK["hbm_gbs"], "GB/s"
-    if name == "quant_fp8_ab":        # both operands in one launch
+    if name == "split_bf16_ab":       # both operands in one launch
+        return "hbm", 4.0 * (M * K + K * N) + 2.0 * (M + N) * Kp64, PEAK["hbm_gbs"], "GB/s"
+    if name == "split_bf16_hilo_ab":
+        return "hbm", 4.0 * (M * K + K * N) + 4.0 * (M + N) * Kp64, PEAK["hbm_gbs"], "GB/s"
+    if name == "quant_fp8_ab":
         return "hbm", 4.0 * (M * K + K * N) + 2.0 * (M + N) * Kp128, PEAK["hbm_gbs"], "GB/s"
     # MX fp6 images: 3/4 byte per K value and level, plus 4 scale bytes per 64 K values
     if name == "quant_mx6_ab":

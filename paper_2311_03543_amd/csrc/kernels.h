@@ -63,6 +63,12 @@ hipError_t launch_split_a_bf16(int64_t M, int64_t K, const float* A, int64_t lda
 hipError_t launch_split_bt_bf16(int64_t K, int64_t N, const float* B, int64_t ldb,
                                 int64_t Np, int64_t Kp, uint16_t* hi, uint16_t* lo,
                                 hipStream_t stream);
+// Both operands' bf16 images in one launch, as launch_split_a_bf16 and
+// launch_split_bt_bf16 give them (al and bl both null: hi images only).
+hipError_t launch_split_bf16_pair(int64_t M, int64_t N, int64_t K, const float* A, int64_t lda,
+                                 const float* B, int64_t ldb, int64_t Mp, int64_t Np, int64_t Kp,
+                                 uint16_t* ah, uint16_t* al, uint16_t* bh, uint16_t* bl,
+                                 hipStream_t stream);
 // Plain bf16 split of a row-major matrix, tight output (bit-exact checking).
 hipError_t launch_split_bf16_plain(int64_t rows, int64_t cols, const float* X, int64_t ldx,
                                    uint16_t* hi, uint16_t* lo, hipStream_t stream);

@@ -37,14 +37,14 @@ __device__ __forceinline__ void split1(float x, uint16_t& hi, uint16_t& lo) {
 // A (M x K, lda) -> hi/lo panel images (Mp rows, Kp bf16 per row).  One lane
 // per 16-byte image chunk (8 consecutive k), lanes in image order: the writes
 // are contiguous and each group of 4 lanes reads 32 consecutive floats of a row.
+// Workgroup bx of gx (256 lanes each, grid-stride over the chunks).
 template <bool VEC>
-__global__ void split_a_kernel(int64_t M, int64_t K, const float* __restrict__ A, int64_t lda,
-                               int64_t Mp, int64_t Kp, uint16_t* __restrict__ hi,
-                               uint16_t* __restrict__ lo) {
+__device__ __forceinline__ void split_a(int64_t bx, int64_t gx, int64_t M, int64_t K,
+                                        const float* __restrict__ A, int64_t lda, int64_t Mp, int64_t Kp,
+                                        uint16_t* __restrict__ hi, uint16_t* __restrict__ lo) {
     const int64_t nkb = Kp * 2 / kPanelRowBytes;
     const int64_t total = Mp * (Kp / 8);
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t e = bx * 256 + threadIdx.x; e < total; e += gx * 256) {
         const int64_t blk = e >> 10;            // 1024 chunks per 16 KiB block
         const int w = (int)(e & 1023), rr = w >> 2, pos = w & 3;
         const int64_t rb = blk / nkb, kb = blk - rb * nkb;
@@ -79,18 +79,23 @@ __global__ void split_a_kernel(int64_t M, int64_t K, const float* __restrict__ A
     }
 }
 
-// B (K x N, ldb) -> hi/lo transposed panel images (Np rows, Kp bf16 per row);
-// one 64 x 64 tile per workgroup.
 template <bool VEC>
-__global__ __launch_bounds__(256) void split_bt_kernel(int64_t K, int64_t N,
-                                                       const float* __restrict__ B, int64_t ldb,
-                                                       int64_t Kp, uint16_t* __restrict__ hi,
-                                                       uint16_t* __restrict__ lo) {
-    __shared__ float T[64][65];
+__global__ __launch_bounds__(256) void split_a_kernel(int64_t M, int64_t K, const float* __restrict__ A,
+                                                      int64_t lda, int64_t Mp, int64_t Kp,
+                                                      uint16_t* __restrict__ hi, uint16_t* __restrict__ lo) {
+    split_a<VEC>(blockIdx.x, gridDim.x, M, K, A, lda, Mp, Kp, hi, lo);
+}
+
+// B (K x N, ldb) -> hi/lo transposed panel images (Np rows, Kp bf16 per row);
+// one 64 x 64 tile per workgroup (tile `tile`), transposed through T.
+template <bool VEC>
+__device__ __forceinline__ void split_bt(int64_t tile, int64_t K, int64_t N, const float* __restrict__ B,
+                                         int64_t ldb, int64_t Kp, uint16_t* __restrict__ hi,
+                                         uint16_t* __restrict__ lo, float (*T)[65]) {
     const int t = threadIdx.x;
     const int64_t tiles_k = Kp / 64;
-    const int64_t k0 = (blockIdx.x % tiles_k) * 64;
-    const int64_t n0 = (blockIdx.x / tiles_k) * 64;
+    const int64_t k0 = (tile % tiles_k) * 64;
+    const int64_t n0 = (tile / tiles_k) * 64;
     // load: rows k0 + t/16 + 16 i, columns n0 + 4 (t % 16) .. +3
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -147,6 +152,31 @@ __global__ __launch_bounds__(256) void split_bt_kernel(int64_t K, int64_t N,
             *reinterpret_cast<uint4*>(pl + (q ? o1 : o0)) = lv;
         }
     }
+}
+
+template <bool VEC>
+__global__ __launch_bounds__(256) void split_bt_kernel(int64_t K, int64_t N, const float* __restrict__ B,
+                                                       int64_t ldb, int64_t Kp, uint16_t* __restrict__ hi,
+                                                       uint16_t* __restrict__ lo) {
+    __shared__ float T[64][65];
+    split_bt<VEC>(blockIdx.x, K, N, B, ldb, Kp, hi, lo, T);
+}
+
+// Both operands' bf16 images in one launch: ga grid-stride workgroups of
+// split_a and gb tiles of split_bt, interleaved by paired_kind.
+struct SplitPair {
+    int64_t M, N, K, lda, ldb, Mp, Kp, ga, gb;
+    const float* A;
+    const float* B;
+    uint16_t *ah, *al, *bh, *bl;
+};
+template <bool VA, bool VB>
+__global__ __launch_bounds__(256) void split_pair_kernel(SplitPair p) {
+    __shared__ float T[64][65];
+    int64_t w;
+    const int kind = paired_kind(blockIdx.x, p.ga, p.gb, &w);
+    if (kind == 0) split_a<VA>(w, p.ga, p.M, p.K, p.A, p.lda, p.Mp, p.Kp, p.ah, p.al);
+    else if (kind == 1) split_bt<VB>(w, p.K, p.N, p.B, p.ldb, p.Kp, p.bh, p.bl, T);
 }
 
 __global__ void split_plain_kernel(int64_t rows, int64_t cols, const float* __restrict__ X,
@@ -415,6 +445,27 @@ hipError_t launch_quant_fp8_pair(int64_t M, int64_t N, int64_t K, const float* A
     else if (va) go(quant_fp8_pair_kernel<true, false>);
     else if (vb) go(quant_fp8_pair_kernel<false, true>);
     else go(quant_fp8_pair_kernel<false, false>);
+    return hipGetLastError();
+}
+
+hipError_t launch_split_bf16_pair(int64_t M, int64_t N, int64_t K, const float* A, int64_t lda,
+                                 const float* B, int64_t ldb, int64_t Mp, int64_t Np, int64_t Kp,
+                                 uint16_t* ah, uint16_t* al, uint16_t* bh, uint16_t* bl,
+                                 hipStream_t stream) {
+    if (M <= 0 || N <= 0 || K <= 0 || !ah || !bh || (!al) != (!bl) || Mp % kPanelRows ||
+        Np % kPanelRows || Mp < M || Np < N || Kp % 64 || Kp < K)
+        return hipErrorInvalidValue;
+    const SplitPair p{M, N, K, lda, ldb, Mp, Kp, grid_for(Mp * (Kp / 8), 256), (Np / 64) * (Kp / 64),
+                      A, B, ah, al, bh, bl};
+    const int64_t blocks = paired_blocks(p.ga, p.gb);
+    if (blocks >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+    const bool va = (lda % 4 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
+    const bool vb = (ldb % 4 == 0) && ((reinterpret_cast<uintptr_t>(B) & 15) == 0);
+    auto go = [&](auto kernel) { hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(256), 0, stream, p); };
+    if (va && vb) go(split_pair_kernel<true, true>);
+    else if (va) go(split_pair_kernel<true, false>);
+    else if (vb) go(split_pair_kernel<false, true>);
+    else go(split_pair_kernel<false, false>);
     return hipGetLastError();
 }
 

@@ -552,31 +552,23 @@ int finish_split(cmp_ctx* c, const cmp_gemm_args* a, int splits, const float* pa
                : CMP_EHIP;
 }
 
-// The pre-pass of an image variant: the kernels that turn A and B into the
-// variant's images at `base` (laid out by images_of), all on the caller's
-// stream.  The bf16 splits of A and B run one after the other (side by side
-// they streamed no faster); the FP8 and FP6 quantisations of A and B share
-// one launch whose workgroups interleave the two operands, because each alone
-// leaves HBM bandwidth unused (its phases load, reduce, convert and store).
+// The pre-pass of an image variant: one kernel on the caller's stream that
+// turns A and B into the variant's images at `base` (laid out by images_of),
+// its workgroups interleaving the two operands (each alone leaves HBM
+// bandwidth unused, and one launch saves a kernel boundary).
 int prepass(cmp_ctx* c, int kind, const cmp_gemm_args* a, const Images& I, void* base,
             hipStream_t s) {
+    // every pre-pass handles both operands in one launch, their workgroups interleaved
     if (kind == kImgBf16 || kind == kImgBf16x3) {
         const bool lo = kind == kImgBf16x3;
-        auto* Ah = (uint16_t*)I.at(base, 0);
-        auto* Bh = (uint16_t*)I.at(base, 1);
-        auto* Al = lo ? (uint16_t*)I.at(base, 2) : nullptr;
-        auto* Bl = lo ? (uint16_t*)I.at(base, 3) : nullptr;
-        {
-            KTimer kt(c, s, lo ? "split_a_bf16_hilo" : "split_a_bf16");
-            if (cmp::launch_split_a_bf16(a->M, a->K, a->A, a->lda, I.Mp, I.Kp, Ah, Al, s) != hipSuccess)
-                return CMP_EHIP;
-        }
-        KTimer kt(c, s, lo ? "split_bt_bf16_hilo" : "split_bt_bf16");
-        if (cmp::launch_split_bt_bf16(a->K, a->N, a->B, a->ldb, I.Np, I.Kp, Bh, Bl, s) != hipSuccess)
-            return CMP_EHIP;
-        return CMP_OK;
+        KTimer kt(c, s, lo ? "split_bf16_hilo_ab" : "split_bf16_ab");
+        return cmp::launch_split_bf16_pair(a->M, a->N, a->K, a->A, a->lda, a->B, a->ldb, I.Mp, I.Np, I.Kp,
+                                           (uint16_t*)I.at(base, 0), lo ? (uint16_t*)I.at(base, 2) : nullptr,
+                                           (uint16_t*)I.at(base, 1), lo ? (uint16_t*)I.at(base, 3) : nullptr,
+                                           s) == hipSuccess
+                   ? CMP_OK
+                   : CMP_EHIP;
     }
-    // FP8 and FP6: both operands in one launch, their workgroups interleaved
     if (kind == kImgFp8r) {
         KTimer kt(c, s, "quant_fp8_ab");
         return cmp::launch_quant_fp8_pair(a->M, a->N, a->K, a->A, a->lda, a->B, a->ldb, I.Mp, I.Np, I.Kp,

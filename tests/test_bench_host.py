@@ -40,7 +40,8 @@ def test_traffic_reported_only_for_the_counted_source(tmp_path, monkeypatch):
 
 @pytest.mark.parametrize("name", ["gemm_bf16_tn", "gemm_bf16x3_tn", "gemm_fp8r_tn", "gemm_f32_simt",
                                   "gemm_fp6x3_tn", "split_a_bf16", "quant_fp8_bt", "quant_mx6_a",
-                                  "quant_mx6_bt", "quant_fp8_ab", "quant_mx6_ab"])
+                                  "quant_mx6_bt", "quant_fp8_ab", "quant_mx6_ab", "split_bf16_ab",
+                                  "split_bf16_hilo_ab"])
 def test_roofline_work_per_launch(name):
     import bench
     bound, work, peak, unit = bench.kernel_roofline(name, 256, 512, 128)
@@ -50,6 +51,8 @@ def test_roofline_work_per_launch(name):
               "quant_fp8_bt": 4 * 128 * 512 + 2 * 512 * 128, "quant_mx6_a": 4 * 256 * 128 + 1.5625 * 256 * 128,
               "quant_mx6_bt": 4 * 128 * 512 + 1.5625 * 512 * 128,
               "quant_fp8_ab": 4 * (256 * 128 + 128 * 512) + 2 * (256 + 512) * 128,
-              "quant_mx6_ab": 4 * (256 * 128 + 128 * 512) + 1.5625 * (256 + 512) * 128}[name]
+              "quant_mx6_ab": 4 * (256 * 128 + 128 * 512) + 1.5625 * (256 + 512) * 128,
+              "split_bf16_ab": 4 * (256 * 128 + 128 * 512) + 2 * (256 + 512) * 128,
+              "split_bf16_hilo_ab": 4 * (256 * 128 + 128 * 512) + 4 * (256 + 512) * 128}[name]
     assert work == expect
     assert (bound == "hbm") == (unit == "GB/s")
