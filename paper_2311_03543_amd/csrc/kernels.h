@@ -56,15 +56,8 @@ hipError_t launch_scale_c(int64_t M, int64_t N, float beta, float* C, int64_t ld
 // layout of common.h (Mp, Np multiples of 256, Kp a multiple of 64):
 //   A  (M x K, ld lda)  ->  Ah / Al  (Mp rows x Kp bf16)
 //   B  (K x N, ld ldb)  ->  Bh / Bl  (Np rows x Kp bf16, i.e. B transposed)
-// Padding rows / columns are zero.  lo pointers may be null (bf16 only).
-hipError_t launch_split_a_bf16(int64_t M, int64_t K, const float* A, int64_t lda,
-                               int64_t Mp, int64_t Kp, uint16_t* hi, uint16_t* lo,
-                               hipStream_t stream);
-hipError_t launch_split_bt_bf16(int64_t K, int64_t N, const float* B, int64_t ldb,
-                                int64_t Np, int64_t Kp, uint16_t* hi, uint16_t* lo,
-                                hipStream_t stream);
-// Both operands' bf16 images in one launch, as launch_split_a_bf16 and
-// launch_split_bt_bf16 give them (al and bl both null: hi images only).
+// Padding rows / columns are zero.  Both operands' images come from one
+// launch (al and bl both null: hi images only, the one-term bf16 variant).
 hipError_t launch_split_bf16_pair(int64_t M, int64_t N, int64_t K, const float* A, int64_t lda,
                                  const float* B, int64_t ldb, int64_t Mp, int64_t Np, int64_t Kp,
                                  uint16_t* ah, uint16_t* al, uint16_t* bh, uint16_t* bl,

@@ -79,13 +79,6 @@ __device__ __forceinline__ void split_a(int64_t bx, int64_t gx, int64_t M, int64
     }
 }
 
-template <bool VEC>
-__global__ __launch_bounds__(256) void split_a_kernel(int64_t M, int64_t K, const float* __restrict__ A,
-                                                      int64_t lda, int64_t Mp, int64_t Kp,
-                                                      uint16_t* __restrict__ hi, uint16_t* __restrict__ lo) {
-    split_a<VEC>(blockIdx.x, gridDim.x, M, K, A, lda, Mp, Kp, hi, lo);
-}
-
 // B (K x N, ldb) -> hi/lo transposed panel images (Np rows, Kp bf16 per row);
 // one 64 x 64 tile per workgroup (tile `tile`), transposed through T.
 template <bool VEC>
@@ -152,14 +145,6 @@ __device__ __forceinline__ void split_bt(int64_t tile, int64_t K, int64_t N, con
             *reinterpret_cast<uint4*>(pl + (q ? o1 : o0)) = lv;
         }
     }
-}
-
-template <bool VEC>
-__global__ __launch_bounds__(256) void split_bt_kernel(int64_t K, int64_t N, const float* __restrict__ B,
-                                                       int64_t ldb, int64_t Kp, uint16_t* __restrict__ hi,
-                                                       uint16_t* __restrict__ lo) {
-    __shared__ float T[64][65];
-    split_bt<VEC>(blockIdx.x, K, N, B, ldb, Kp, hi, lo, T);
 }
 
 // Both operands' bf16 images in one launch: ga grid-stride workgroups of
@@ -466,32 +451,6 @@ hipError_t launch_split_bf16_pair(int64_t M, int64_t N, int64_t K, const float* 
     else if (va) go(split_pair_kernel<true, false>);
     else if (vb) go(split_pair_kernel<false, true>);
     else go(split_pair_kernel<false, false>);
-    return hipGetLastError();
-}
-
-hipError_t launch_split_a_bf16(int64_t M, int64_t K, const float* A, int64_t lda, int64_t Mp,
-                               int64_t Kp, uint16_t* hi, uint16_t* lo, hipStream_t stream) {
-    const bool vec = (lda % 4 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
-    const unsigned g = grid_for(Mp * (Kp / 8), 256);
-    if (vec)
-        hipLaunchKernelGGL(split_a_kernel<true>, dim3(g), dim3(256), 0, stream, M, K, A, lda, Mp,
-                           Kp, hi, lo);
-    else
-        hipLaunchKernelGGL(split_a_kernel<false>, dim3(g), dim3(256), 0, stream, M, K, A, lda, Mp,
-                           Kp, hi, lo);
-    return hipGetLastError();
-}
-
-hipError_t launch_split_bt_bf16(int64_t K, int64_t N, const float* B, int64_t ldb, int64_t Np,
-                                int64_t Kp, uint16_t* hi, uint16_t* lo, hipStream_t stream) {
-    const bool vec = (ldb % 4 == 0) && ((reinterpret_cast<uintptr_t>(B) & 15) == 0);
-    const unsigned g = (unsigned)((Np / 64) * (Kp / 64));
-    if (vec)
-        hipLaunchKernelGGL(split_bt_kernel<true>, dim3(g), dim3(256), 0, stream, K, N, B, ldb, Kp,
-                           hi, lo);
-    else
-        hipLaunchKernelGGL(split_bt_kernel<false>, dim3(g), dim3(256), 0, stream, K, N, B, ldb,
-                           Kp, hi, lo);
     return hipGetLastError();
 }
 
