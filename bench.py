@@ -60,18 +60,6 @@ def kernel_roofline(name: str, M: int, N: int, K: int):
     if name == "gemm_fp6x3_tn":
         return "mfma", 3 * 2.0 * M * N * K, PEAK["fp6"], "TFLOP/s"
     # pre-pass kernels: bytes read + written (HBM-bound)
-    if name == "split_a_bf16":
-        return "hbm", 4.0 * M * K + 2.0 * M * Kp64, PEAK["hbm_gbs"], "GB/s"
-    if name == "split_a_bf16_hilo":
-        return "hbm", 4.0 * M * K + 4.0 * M * Kp64, PEAK["hbm_gbs"], "GB/s"
-    if name == "split_bt_bf16":
-        return "hbm", 4.0 * K * N + 2.0 * N * Kp64, PEAK["hbm_gbs"], "GB/s"
-    if name == "split_bt_bf16_hilo":
-        return "hbm", 4.0 * K * N + 4.0 * N * Kp64, PEAK["hbm_gbs"], "GB/s"
-    if name == "quant_fp8_a":
-        return "hbm", 4.0 * M * K + 2.0 * M * Kp128, PEAK["hbm_gbs"], "GB/s"
-    if name == "quant_fp8_bt":
-        return "hbm", 4.0 * K * N + 2.0 * N * Kp128, PEAK["hbm_gbs"], "GB/s"
     if name == "split_bf16_ab":       # both operands in one launch
         return "hbm", 4.0 * (M * K + K * N) + 2.0 * (M + N) * Kp64, PEAK["hbm_gbs"], "GB/s"
     if name == "split_bf16_hilo_ab":
@@ -81,10 +69,6 @@ def kernel_roofline(name: str, M: int, N: int, K: int):
     # MX fp6 images: 3/4 byte per K value and level, plus 4 scale bytes per 64 K values
     if name == "quant_mx6_ab":
         return "hbm", 4.0 * (M * K + K * N) + 1.5625 * (M + N) * Kp64, PEAK["hbm_gbs"], "GB/s"
-    if name == "quant_mx6_a":
-        return "hbm", 4.0 * M * K + 1.5625 * M * Kp64, PEAK["hbm_gbs"], "GB/s"
-    if name == "quant_mx6_bt":
-        return "hbm", 4.0 * K * N + 1.5625 * N * Kp64, PEAK["hbm_gbs"], "GB/s"
     return None
 
 

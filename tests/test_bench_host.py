@@ -33,23 +33,20 @@ def test_traffic_reported_only_for_the_counted_source(tmp_path, monkeypatch):
     assert bench.measured_traffic("gemm_bf16_tn", 64) == 123.0
     # another size, another kernel, or a changed source: no figure
     assert bench.measured_traffic("gemm_bf16_tn", 128) is None
-    assert bench.measured_traffic("split_a_bf16", 64) is None
+    assert bench.measured_traffic("split_bf16_ab", 64) is None
     (fake_root / src_rel).write_bytes(b"// changed\n")
     assert bench.measured_traffic("gemm_bf16_tn", 64) is None
 
 
 @pytest.mark.parametrize("name", ["gemm_bf16_tn", "gemm_bf16x3_tn", "gemm_fp8r_tn", "gemm_f32_simt",
-                                  "gemm_fp6x3_tn", "split_a_bf16", "quant_fp8_bt", "quant_mx6_a",
-                                  "quant_mx6_bt", "quant_fp8_ab", "quant_mx6_ab", "split_bf16_ab",
+                                  "gemm_fp6x3_tn", "quant_fp8_ab", "quant_mx6_ab", "split_bf16_ab",
                                   "split_bf16_hilo_ab"])
 def test_roofline_work_per_launch(name):
     import bench
     bound, work, peak, unit = bench.kernel_roofline(name, 256, 512, 128)
     mnk = 256 * 512 * 128
     expect = {"gemm_bf16_tn": 2 * mnk, "gemm_bf16x3_tn": 6 * mnk, "gemm_fp8r_tn": 8 * mnk,
-              "gemm_f32_simt": 2 * mnk, "gemm_fp6x3_tn": 6 * mnk, "split_a_bf16": 4 * 256 * 128 + 2 * 256 * 128,
-              "quant_fp8_bt": 4 * 128 * 512 + 2 * 512 * 128, "quant_mx6_a": 4 * 256 * 128 + 1.5625 * 256 * 128,
-              "quant_mx6_bt": 4 * 128 * 512 + 1.5625 * 512 * 128,
+              "gemm_f32_simt": 2 * mnk, "gemm_fp6x3_tn": 6 * mnk,
               "quant_fp8_ab": 4 * (256 * 128 + 128 * 512) + 2 * (256 + 512) * 128,
               "quant_mx6_ab": 4 * (256 * 128 + 128 * 512) + 1.5625 * (256 + 512) * 128,
               "split_bf16_ab": 4 * (256 * 128 + 128 * 512) + 2 * (256 + 512) * 128,
