@@ -320,7 +320,8 @@ def main():
 
 def vendor_reference(torch, n):
     """Context only: torch.mm (hipBLASLt) on contiguous n x n operands in bf16 (bf16 output) and
-    in fp32, median of 20 timed calls after 3 warm-ups."""
+    in fp32, median of 20 timed calls after 3 warm-ups; and a plain 512 MiB device copy (the HBM
+    rate a read-and-write kernel reaches)."""
     res = {}
     g = torch.Generator(device="cuda").manual_seed(12)
     for name, dt in (("bf16", torch.bfloat16), ("f32", torch.float32)):
@@ -340,8 +341,27 @@ def vendor_reference(torch, n):
         med = float(np.median(ts))
         res[f"torch_mm_{name}"] = dict(median_ms=med, tflops=2.0 * n ** 3 / (med * 1e-3) / 1e12)
         del A, B
+    # a plain device copy (read + write of 512 MiB): the HBM rate the pre-pass kernels compare with
+    src = torch.empty(128 << 20, dtype=torch.float32, device="cuda").normal_()
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(20):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    med = float(np.median(ts))
+    copy = dict(median_ms=med, bytes=2.0 * src.numel() * 4, gbs=2.0 * src.numel() * 4 / (med * 1e-3) / 1e9)
+    del src, dst
     torch.cuda.empty_cache()
-    log("vendor reference: " + ", ".join(f"{k} {v['median_ms']:.3f} ms {v['tflops']:.0f} TF" for k, v in res.items()))
+    log("vendor reference: " + ", ".join(f"{k} {v['median_ms']:.3f} ms {v['tflops']:.0f} TF" for k, v in res.items())
+        + f", device copy {copy['gbs']:.0f} GB/s")
+    res["torch_copy_512MiB"] = copy
     return res
 
 
