@@ -83,6 +83,26 @@ def test_integer_exact(cx, name, M, N, K):
     assert np.array_equal(C.astype(np.float64), ref)
 
 
+# Unsplit K over many operand-image blocks: each workgroup of an MFMA kernel then
+# copies K blocks far past its first one, which automatic split-K (at least four
+# blocks per slice on shapes with few tiles) never reaches on the shapes above.
+UNSPLIT_SHAPES = [(256, 256, 2048), (300, 520, 1000), (512, 768, 777)]
+
+
+@pytest.mark.parametrize("name", ["bf16x3", "fp8r", "bf16", "fp6x3"])
+@pytest.mark.parametrize("M,N,K", UNSPLIT_SHAPES)
+def test_integer_exact_unsplit_long_k(cx, name, M, N, K):
+    A = synth.int_matrix(M, K, M * 13 + K)
+    B = synth.int_matrix(K, N, N * 17 + K)
+    cx.set_split_k(1)
+    try:
+        C = run(cx, name, A, B)
+    finally:
+        cx.set_split_k(0)
+    ref = A.astype(np.float64) @ B.astype(np.float64)
+    assert np.array_equal(C.astype(np.float64), ref)
+
+
 # ---- random operands: stated bound and entrywise rounding bound ----------------
 
 def e4m3_place(codes, scale_bytes):
