@@ -1868,6 +1868,9 @@ CMP_API int cmp_history_load(cmp_ctx* c, const char* path, int force) {
         HistRow r{};
         if (!(ss >> M >> N >> K >> name >> r.reps >> r.med >> r.mn >> r.mean))
             return fail(c, CMP_EINVAL, "malformed history line: %s", line.c_str());
+        // the same rules as cmp_history_add: positive shape, finite positive median
+        if (M <= 0 || N <= 0 || K <= 0 || !(r.med > 0) || !std::isfinite(r.med))
+            return fail(c, CMP_EINVAL, "invalid history line: %s", line.c_str());
         r.M = M;
         r.N = N;
         r.K = K;
@@ -2186,6 +2189,9 @@ CMP_API int cmp_mlp_load(cmp_ctx* c, const char* path, int force) {
         if (rows[k].size() != 4) return fail(c, CMP_EINVAL, "%s: %s needs 4 values", path, k);
     if (rows["params"].size() != (size_t)kMlpP)
         return fail(c, CMP_EINVAL, "%s holds %zu parameters, the network has %d", path, rows["params"].size(), kMlpP);
+    for (const char* k : {"mu_x", "sd_x", "mu_y", "sd_y", "params"})
+        for (float x : rows[k])
+            if (!std::isfinite(x)) return fail(c, CMP_EINVAL, "%s: %s holds a non-finite value", path, k);
     for (int j = 0; j < 4; ++j)
         if (!(rows["sd_x"][j] > 0) || !(rows["sd_y"][j] > 0))
             return fail(c, CMP_EINVAL, "%s: deviations must be > 0", path);

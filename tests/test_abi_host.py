@@ -330,12 +330,32 @@ def test_history_roundtrip_and_signature(tmp_path):
     assert e.history_load(q, force=True) == 0
     open(q, "w").write("garbage\n")
     assert e.history_load(q) == pa.CMP_EINVAL
+    # rows that cmp_history_add would refuse are refused on load too, and nothing is added
+    lines = open(p).read().splitlines()
+    first = next(i for i, l in enumerate(lines) if l and not l.startswith("#"))
+    for bad in ("0", "-5"):
+        f = lines[:first] + [re.sub(r"^\S+", bad, lines[first])] + lines[first + 1:]
+        open(q, "w").write("\n".join(f) + "\n")
+        g = host_ctx()
+        register_fakes(g)
+        assert g.history_load(q) == pa.CMP_EINVAL
+        assert g.history() == []
+    for med in ("nan", "-1", "0", "inf"):
+        cols = lines[first].split()
+        cols[5] = med
+        f = lines[:first] + [" ".join(cols)] + lines[first + 1:]
+        open(q, "w").write("\n".join(f) + "\n")
+        g = host_ctx()
+        register_fakes(g)
+        assert g.history_load(q) == pa.CMP_EINVAL, med
+        assert g.history() == []
 
 
 def test_mlp_checkpoint_roundtrip_and_errors(tmp_path):
     """The selector network and its normalisation statistics survive a save and a load bit for
     bit (Section 3.2 trains the network once and reuses it); a file from another device, a
-    malformed file or one with the wrong parameter count is refused and changes nothing."""
+    malformed file, one with a non-finite value or one with the wrong parameter count is refused
+    and changes nothing."""
     rng = np.random.default_rng(7)
     c = host_ctx()
     p = str(tmp_path / "net.txt")
@@ -371,6 +391,8 @@ def test_mlp_checkpoint_roundtrip_and_errors(tmp_path):
         "short": re.sub(r"(?m)^(params(?: \S+){%d}).*$" % (n - 1), r"\1", text),
         "value": text.replace("sd_x ", "sd_x x", 1),
         "sd": re.sub(r"(?m)^sd_y \S+", "sd_y 0", text),
+        "nan": re.sub(r"(?m)^(params(?: \S+){5}) \S+", r"\1 nan", text),
+        "inf": re.sub(r"(?m)^mu_x \S+", "mu_x inf", text),
         "header": "\n".join(l for l in text.splitlines() if not l.startswith("# compar-mlp")),
         "garbage": "garbage\n",
     }
