@@ -506,7 +506,9 @@ def selector_experiment(cx, pa, torch, args):
 
 
 def grouped_experiment(cx, pa, torch, args):
-    """1024 problems, M, N, K log-uniform in [32, 1024] (seed 4), normal(0,1) FP32 operands."""
+    """1024 problems, M, N, K log-uniform in [32, 1024] (seed 4), normal(0,1) FP32 operands.
+    The separate launches run f32_simt per problem; the grouped plan's autotuner picks among the
+    FP32 SIMT tiles and the bf16x3 MFMA configuration (both in the 1e-5 class)."""
     count = args.grouped_problems
     shapes = synth.log_uniform_shapes(count, 32, 1024, 4)
     g = torch.Generator(device="cuda").manual_seed(5)
@@ -553,16 +555,18 @@ def grouped_experiment(cx, pa, torch, args):
     t_grp_graph = timed(plan.graph_launch)
     plan.destroy()
     cfgs = pa.grouped_configs()
+    arith = [("f32_simt", "bf16x3")[pa.grouped_config_variant(i)] for i in range(len(cfgs))]
     res = dict(problems=count, gflop=flops / 1e9,
                separate_ms=t_sep, separate_graph_ms=t_sep_graph,
                grouped_ms=t_grp, grouped_graph_ms=t_grp_graph,
                grouped_tflops=flops / (t_grp_graph * 1e-3) / 1e12,
                separate_tflops=flops / (t_sep * 1e-3) / 1e12,
                speedup_vs_separate=t_sep / t_grp_graph,
-               autotune_s=t_tune, tile=cfgs[info["config"]], tiles=info["tiles"], grid=info["grid"],
-               autotune_ms={f"{c[0]}x{c[1]}x{c[2]}": ms for c, ms in zip(cfgs, info["config_ms"])})
+               autotune_s=t_tune, tile=cfgs[info["config"]], arithmetic=arith[info["config"]],
+               tiles=info["tiles"], grid=info["grid"],
+               autotune_ms={f"{c[0]}x{c[1]}x{c[2]} {a}": ms for c, a, ms in zip(cfgs, arith, info["config_ms"])})
     log(f"grouped: separate {t_sep:.2f} ms, separate+graph {t_sep_graph:.2f} ms, grouped {t_grp:.2f} ms, "
-        f"grouped+graph {t_grp_graph:.2f} ms, tile {res['tile']}")
+        f"grouped+graph {t_grp_graph:.2f} ms, tile {res['tile']} {res['arithmetic']}")
     del probs
     torch.cuda.empty_cache()
     return res

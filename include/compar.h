@@ -491,24 +491,34 @@ int cmp_prepass_images(cmp_ctx *ctx, int id, const cmp_gemm_args *args, void *ou
 
 /* ---- grouped launches: many GEMMs of uneven shapes ---------------------- */
 
-/* A plan runs `count` independent gemm problems (FP32 SIMT arithmetic, each
- * problem's own alpha, beta and leading dimensions; device pointers owned by
- * the caller and fixed for the plan's lifetime) as ONE persistent kernel whose
+/* A plan runs `count` independent gemm problems (each problem's own alpha,
+ * beta and leading dimensions; device pointers owned by the caller and fixed
+ * for the plan's lifetime) as ONE persistent kernel whose
  * workgroups take tiles of the concatenated tile list from a device counter
  * as they finish their previous one, problems ordered by decreasing K (the
  * longest tiles first).  A launch zeroes the plan's counter first (a one-lane
  * kernel on the same stream, no memset, so the pair can be captured), and two
  * launches of one plan must not run at the same time (they would share the
- * counter and the problems' C).  The tile shape is one of cmp_grouped_config_count()
- * configurations; config < 0 runs the autotuner, which times every
- * configuration `reps` times on this group and keeps the fastest (it runs the
- * products, so C is overwritten: with beta != 0, re-initialise C afterwards).
- * The launch is also captured in a hipGraph (cmp_grouped_graph_launch).
- * Results are bit-identical to cmp_gemm_variant with "f32_simt" per problem.
- * The plan borrows the context: destroy it before cmp_terminate. */
+ * counter and the problems' C).  A configuration is a tile shape and an
+ * arithmetic, one of cmp_grouped_config_count(): the first ones are FP32 SIMT
+ * tiles, bit-identical to cmp_gemm_variant with "f32_simt" per problem; the
+ * last one runs the "bf16x3" variant's arithmetic (one launch splitting every
+ * problem's A and B into bf16 hi / lo images in a workspace the plan owns,
+ * then one persistent launch of 256 x 256 MFMA tiles), bit-identical to an
+ * unsplit (cmp_set_split_k(1)) "bf16x3" call per problem, and available only
+ * when every non-empty problem has alpha != 0 and K > 0 (otherwise
+ * CMP_EUNSUPPORTED).  Both arithmetics state the 1e-5 bound.
+ * cmp_grouped_config_variant gives the built-in variant id whose results a
+ * configuration reproduces.  config < 0 runs the autotuner, which times every
+ * available configuration `reps` times on this group (the bf16x3 one with its
+ * pre-pass) and keeps the fastest (it runs the products, so C is overwritten:
+ * with beta != 0, re-initialise C afterwards).  The launch is also captured in
+ * a hipGraph (cmp_grouped_graph_launch).  The plan borrows the context:
+ * destroy it before cmp_terminate. */
 typedef struct cmp_grouped_plan cmp_grouped_plan;
 int cmp_grouped_config_count(void);
 int cmp_grouped_config_info(int config, int *bm, int *bn, int *bk);
+int cmp_grouped_config_variant(int config, int *variant);
 int cmp_grouped_plan_create(cmp_ctx *ctx, int count, const cmp_gemm_args *problems, int config,
                             int reps, void *stream, cmp_grouped_plan **out);
 /* config_ms (may be NULL) receives the autotuner's median ms per configuration

@@ -464,6 +464,16 @@ def grouped_configs():
     return out
 
 
+def grouped_config_variant(config: int) -> int:
+    """Built-in variant id (0 f32_simt, 1 bf16x3) whose per-problem results a grouped
+    configuration reproduces bit for bit."""
+    v = C.c_int()
+    st = _lib.load().cmp_grouped_config_variant(config, C.byref(v))
+    if st:
+        raise ComparError(st, f"unknown grouped configuration {config}")
+    return v.value
+
+
 class GroupedPlan:
     """A grouped launch plan (cmp_grouped_plan_*); destroy before its context."""
 

@@ -132,6 +132,7 @@ SIGNATURES = {
     "cmp_prepass_images": (_I, [_P, _I, C.POINTER(cmp_gemm_args), _P, C.c_size_t, _P]),
     "cmp_grouped_config_count": (_I, []),
     "cmp_grouped_config_info": (_I, [_I, _IP, _IP, _IP]),
+    "cmp_grouped_config_variant": (_I, [_I, _IP]),
     "cmp_grouped_plan_create": (_I, [_P, _I, C.POINTER(cmp_gemm_args), _I, _I, _P, C.POINTER(_P)]),
     "cmp_grouped_plan_info": (_I, [_P, _IP, _IP, _IP, _IP, _FP]),
     "cmp_grouped_launch": (_I, [_P, _P]),

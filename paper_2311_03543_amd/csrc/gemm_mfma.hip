@@ -307,26 +307,23 @@ constexpr int read_order(int k) {
     return order[k];
 }
 
-__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(1, 1)))
-void gemm_bf16x3_slab4_kernel(int64_t M, int64_t N, int nkb, float alpha,
-                              const uint8_t* __restrict__ Ah, const uint8_t* __restrict__ Al,
-                              const uint8_t* __restrict__ Bh, const uint8_t* __restrict__ Bl,
-                              float beta, float* __restrict__ C, int64_t ldc, int tiles_m,
-                              int tiles_n, int kb_split, float* __restrict__ P) {
-    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+// One 256 x 256 tile (tm, tn) of the bf16x3 product over the K blocks
+// [kb0, kb0 + steps) of images with nkb blocks per panel; `smem` is the
+// 128 KiB LDS ring.  P != nullptr: the raw partial sums go to P (a split-K
+// slice, row pitch N); otherwise C = alpha * acc + beta * C.  Every copy has
+// landed when it returns (the ring may be reused after a workgroup barrier).
+__device__ __forceinline__ void bf16x3_tile(uint8_t* smem, int64_t M, int64_t N, int nkb, float alpha,
+                                            const uint8_t* __restrict__ Ah, const uint8_t* __restrict__ Al,
+                                            const uint8_t* __restrict__ Bh, const uint8_t* __restrict__ Bl,
+                                            float beta, float* __restrict__ C, int64_t ldc, int tm, int tn,
+                                            int kb0, int steps, float* __restrict__ P) {
     // LDS ring: slot i = four slabs at i * STAGE4
-
     const int t = threadIdx.x, lane = t & 63;
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);   // wave-uniform (SGPR)
     const int wm = wave >> 1, wn = wave & 1;
-    int tm, tn;
-    tile_coords(tiles_m, tiles_n, tm, tn);
     const int64_t m0 = (int64_t)tm * TM, n0 = (int64_t)tn * TN;
     const int64_t panel = (int64_t)nkb * SLAB;
     const int src_off = wave * 4096 + lane * 16;
-    // split-K: this workgroup's K blocks [kb0, kb0 + steps) (blockIdx.y = split)
-    const int kb0 = (int)blockIdx.y * kb_split;
-    const int steps = nkb - kb0 < kb_split ? nkb - kb0 : kb_split;
     const int64_t koff = (int64_t)kb0 * SLAB;
     const uint8_t* a_hi = Ah + tm * panel + koff + src_off;
     const uint8_t* b_hi = Bh + tn * panel + koff + src_off;
@@ -438,9 +435,68 @@ void gemm_bf16x3_slab4_kernel(int64_t M, int64_t N, int nkb, float alpha,
     one_stage(std::false_type{});
     __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 15));   // drain the trailing copies
     if (P)   // split-K: raw partial sums of this split, reduced by splitk_reduce_kernel
-        epilogue(acc, M, N, m0, n0, wm, wn, lane, 1.f, 0.f, P + (size_t)blockIdx.y * M * N, N);
+        epilogue(acc, M, N, m0, n0, wm, wn, lane, 1.f, 0.f, P, N);
     else
         epilogue(acc, M, N, m0, n0, wm, wn, lane, alpha, beta, C, ldc);
+}
+
+__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void gemm_bf16x3_slab4_kernel(int64_t M, int64_t N, int nkb, float alpha,
+                              const uint8_t* __restrict__ Ah, const uint8_t* __restrict__ Al,
+                              const uint8_t* __restrict__ Bh, const uint8_t* __restrict__ Bl,
+                              float beta, float* __restrict__ C, int64_t ldc, int tiles_m,
+                              int tiles_n, int kb_split, float* __restrict__ P) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    int tm, tn;
+    tile_coords(tiles_m, tiles_n, tm, tn);
+    // split-K: this workgroup's K blocks [kb0, kb0 + steps) (blockIdx.y = split)
+    const int kb0 = (int)blockIdx.y * kb_split;
+    const int steps = nkb - kb0 < kb_split ? nkb - kb0 : kb_split;
+    bf16x3_tile(smem, M, N, nkb, alpha, Ah, Al, Bh, Bl, beta, C, ldc, tm, tn, kb0, steps,
+                P ? P + (size_t)blockIdx.y * M * N : nullptr);
+}
+
+// Many bf16x3 problems in one persistent launch (the grouped plan's MFMA
+// configuration): the tile list is the concatenation of every problem's
+// 256 x 256 tiles (desc[p].tile_start = first tile of problem p, problems in
+// decreasing order of K).  Workgroup b starts with tile b and each workgroup
+// that finishes a tile claims the next unclaimed one from `counter` (zeroed
+// by grouped_mfma_reset_kernel right before, on the same stream).  The tile
+// index lives in the 16 bytes past the ring, so the LDS request is kSmem + 16.
+__global__ void grouped_mfma_reset_kernel(unsigned* counter) {
+    if (threadIdx.x == 0) *counter = 0u;
+}
+
+__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void gemm_bf16x3_grouped_kernel(const GroupedMfmaDesc* __restrict__ desc, int count, int total_tiles,
+                                unsigned* __restrict__ counter) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    int* next_tile = reinterpret_cast<int*>(smem + kSmem);
+    typedef const __attribute__((address_space(1))) GroupedMfmaDesc* gdesc;
+    const gdesc dg = (gdesc)desc;
+    for (int tile = blockIdx.x; tile < total_tiles;) {
+        int lo = 0, hi = count - 1;            // last problem whose first tile is <= tile
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (dg[mid].tile_start <= tile) lo = mid;
+            else hi = mid - 1;
+        }
+        const int local = tile - dg[lo].tile_start;
+        const int tn_count = dg[lo].tiles_n;
+        const int tm = local / tn_count, tn = local - tm * tn_count;
+        const int nkb = (int)(dg[lo].Kp * 2 / kPanelRowBytes);
+        bf16x3_tile(smem, dg[lo].M, dg[lo].N, nkb, dg[lo].alpha, (const uint8_t*)dg[lo].ah,
+                    (const uint8_t*)dg[lo].al, (const uint8_t*)dg[lo].bh, (const uint8_t*)dg[lo].bl,
+                    dg[lo].beta, dg[lo].C, dg[lo].ldc, tm, tn, 0, nkb, nullptr);
+        __syncthreads();                       // every wave is done with the ring and next_tile
+        if (threadIdx.x == 0) {
+            const unsigned ticket = atomicAdd(counter, 1u);
+            const unsigned left = (unsigned)total_tiles - gridDim.x;   // grid <= total_tiles
+            *next_tile = ticket < left ? (int)(gridDim.x + ticket) : total_tiles;
+        }
+        __syncthreads();
+        tile = __builtin_amdgcn_readfirstlane(*next_tile);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -926,6 +982,18 @@ hipError_t launch_gemm_bf16_tn(int64_t M, int64_t N, int64_t Kp, int nterms, flo
                            alpha, (const uint8_t*)Ah, (const uint8_t*)Bh, beta, C, ldc, tiles_m,
                            tiles_n, kbs, P);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_bf16x3_grouped(const GroupedMfmaDesc* desc, int count, int total_tiles, int grid,
+                                      unsigned* counter, hipStream_t stream) {
+    if (total_tiles <= 0) return hipSuccess;
+    if (grid < 1 || grid > total_tiles || !counter || !desc || count < 1) return hipErrorInvalidValue;
+    static std::atomic<uint64_t> lds_g{0};
+    if (hipError_t e = allow_lds(gemm_bf16x3_grouped_kernel, lds_g, kSmem + 16)) return e;
+    hipLaunchKernelGGL(grouped_mfma_reset_kernel, dim3(1), dim3(64), 0, stream, counter);
+    hipLaunchKernelGGL(gemm_bf16x3_grouped_kernel, dim3(grid), dim3(THREADS), kSmem + 16, stream, desc, count,
+                       total_tiles, counter);
     return hipGetLastError();
 }
 

@@ -36,12 +36,32 @@ struct GroupedDesc {
 struct GroupedConfig {
     int bm, bn, bk;
 };
+// One problem of a grouped bf16x3 launch: the operands, the problem's
+// bf16 hi / lo panel images (Mp x Kp of A, Np x Kp of B^T, in the plan's
+// workspace), the pre-pass workgroups of A (ga) and B (gb) from pre_start on,
+// and the problem's 256 x 256 tiles from tile_start on.  vec: bit 0 A, bit 1 B
+// can be read with 16-byte loads.
+struct GroupedMfmaDesc {
+    int64_t M, N, K, lda, ldb, ldc, Mp, Np, Kp;
+    float alpha, beta;
+    const float* A;
+    const float* B;
+    float* C;
+    uint16_t *ah, *al, *bh, *bl;
+    int ga, gb, pre_start, tile_start, tiles_n, vec;
+};
 constexpr int kNumGroupedConfigs = 10;
 extern const GroupedConfig kGroupedConfigs[kNumGroupedConfigs];
 // One persistent launch over the problems of `desc` (tile list in desc order,
 // 1 <= grid <= total_tiles workgroups), preceded by a one-lane kernel that
 // zeroes `counter` (device, 4 bytes), the tile queue the workgroups claim from;
 // launches of one counter must not overlap.
+// Grouped bf16x3: the hi / lo images of every problem in one launch (pre_total
+// workgroups), then every problem's tiles in one persistent launch.
+hipError_t launch_split_grouped(const GroupedMfmaDesc* desc, int count, int64_t pre_total,
+                                hipStream_t stream);
+hipError_t launch_gemm_bf16x3_grouped(const GroupedMfmaDesc* desc, int count, int total_tiles, int grid,
+                                      unsigned* counter, hipStream_t stream);
 hipError_t launch_gemm_f32_grouped(int config, const GroupedDesc* desc, int count, int total_tiles,
                                    int grid, unsigned* counter, hipStream_t stream);
 // Resident workgroups per CU of the grouped kernel for a configuration.

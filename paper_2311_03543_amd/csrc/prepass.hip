@@ -37,11 +37,12 @@ __device__ __forceinline__ void split1(float x, uint16_t& hi, uint16_t& lo) {
 // A (M x K, lda) -> hi/lo panel images (Mp rows, Kp bf16 per row).  One lane
 // per 16-byte image chunk (8 consecutive k), lanes in image order: the writes
 // are contiguous and each group of 4 lanes reads 32 consecutive floats of a row.
-// Workgroup bx of gx (256 lanes each, grid-stride over the chunks).
+// Workgroup bx of gx (256 lanes each, grid-stride over the chunks).  Rows at
+// or past Mw are not written (Mw = Mp: the whole image, padding rows zero).
 template <bool VEC>
 __device__ __forceinline__ void split_a(int64_t bx, int64_t gx, int64_t M, int64_t K,
                                         const float* __restrict__ A, int64_t lda, int64_t Mp, int64_t Kp,
-                                        uint16_t* __restrict__ hi, uint16_t* __restrict__ lo) {
+                                        uint16_t* __restrict__ hi, uint16_t* __restrict__ lo, int64_t Mw) {
     const int64_t nkb = Kp * 2 / kPanelRowBytes;
     const int64_t total = Mp * (Kp / 8);
     for (int64_t e = bx * 256 + threadIdx.x; e < total; e += gx * 256) {
@@ -49,6 +50,7 @@ __device__ __forceinline__ void split_a(int64_t bx, int64_t gx, int64_t M, int64
         const int w = (int)(e & 1023), rr = w >> 2, pos = w & 3;
         const int64_t rb = blk / nkb, kb = blk - rb * nkb;
         const int64_t r = rb * kPanelRows + rr;
+        if (r >= Mw) continue;
         const int64_t k = kb * 32 + (int64_t)((pos ^ ((rr >> 2) & 3)) * 8);
         float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         if (r < M) {
@@ -160,8 +162,38 @@ __global__ __launch_bounds__(256) void split_pair_kernel(SplitPair p) {
     __shared__ float T[64][65];
     int64_t w;
     const int kind = paired_kind(blockIdx.x, p.ga, p.gb, &w);
-    if (kind == 0) split_a<VA>(w, p.ga, p.M, p.K, p.A, p.lda, p.Mp, p.Kp, p.ah, p.al);
+    if (kind == 0) split_a<VA>(w, p.ga, p.M, p.K, p.A, p.lda, p.Mp, p.Kp, p.ah, p.al, p.Mp);
     else if (kind == 1) split_bt<VB>(w, p.K, p.N, p.B, p.ldb, p.Kp, p.bh, p.bl, T);
+}
+
+// The hi / lo images of every problem of a grouped bf16x3 plan in one launch:
+// workgroup w belongs to the problem p with desc[p].pre_start <= w (problems
+// in list order, each A's ga workgroups then B's gb), one split_a chunk pass
+// or one split_bt tile per workgroup.  Only rows below M (A) and the 64-row
+// tiles that start below N (B^T) are written: padding rows of an image feed
+// only output rows and columns past the problem, which the GEMM never stores,
+// while padding K inside the written rows is zero as the products need.
+__global__ __launch_bounds__(256) void split_grouped_kernel(const GroupedMfmaDesc* __restrict__ desc,
+                                                            int count) {
+    __shared__ float T[64][65];
+    typedef const __attribute__((address_space(1))) GroupedMfmaDesc* gdesc;
+    const gdesc dg = (gdesc)desc;
+    const int w = (int)blockIdx.x;
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (dg[mid].pre_start <= w) lo = mid;
+        else hi = mid - 1;
+    }
+    const __attribute__((address_space(1))) GroupedMfmaDesc& d = dg[lo];
+    const int local = w - d.pre_start;
+    if (local < d.ga) {
+        if (d.vec & 1) split_a<true>(local, d.ga, d.M, d.K, d.A, d.lda, d.Mp, d.Kp, d.ah, d.al, d.M);
+        else split_a<false>(local, d.ga, d.M, d.K, d.A, d.lda, d.Mp, d.Kp, d.ah, d.al, d.M);
+    } else if (local - d.ga < d.gb) {
+        if (d.vec & 2) split_bt<true>(local - d.ga, d.K, d.N, d.B, d.ldb, d.Kp, d.bh, d.bl, T);
+        else split_bt<false>(local - d.ga, d.K, d.N, d.B, d.ldb, d.Kp, d.bh, d.bl, T);
+    }
 }
 
 __global__ void split_plain_kernel(int64_t rows, int64_t cols, const float* __restrict__ X,
@@ -430,6 +462,14 @@ hipError_t launch_quant_fp8_pair(int64_t M, int64_t N, int64_t K, const float* A
     else if (va) go(quant_fp8_pair_kernel<true, false>);
     else if (vb) go(quant_fp8_pair_kernel<false, true>);
     else go(quant_fp8_pair_kernel<false, false>);
+    return hipGetLastError();
+}
+
+hipError_t launch_split_grouped(const GroupedMfmaDesc* desc, int count, int64_t pre_total,
+                                hipStream_t stream) {
+    if (pre_total <= 0) return hipSuccess;
+    if (!desc || count < 1 || pre_total >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(split_grouped_kernel, dim3((unsigned)pre_total), dim3(256), 0, stream, desc, count);
     return hipGetLastError();
 }
 

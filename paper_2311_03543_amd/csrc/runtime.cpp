@@ -2380,6 +2380,9 @@ struct cmp_grouped_plan {
     int total_tiles = 0;
     int grid = 0;
     cmp::GroupedDesc* desc = nullptr;     // device: the descriptors, then the tile-queue counter
+    cmp::GroupedMfmaDesc* mdesc = nullptr;   // the same for the bf16x3 configuration
+    void* images = nullptr;               // device: that configuration's bf16 hi / lo images
+    int64_t pre_total = 0;                // its pre-pass workgroups
     unsigned* counter = nullptr;          // device, inside the descriptor allocation
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -2444,15 +2447,142 @@ int grouped_grid(cmp_ctx* c, int config, int total_tiles) {
     return std::max(1, std::min(total_tiles, per_cu * c->props.multiProcessorCount));
 }
 
+// The configurations after the FP32 SIMT tiles: kGroupedMfma runs every
+// problem with the bf16x3 variant's arithmetic (its pre-pass and its 256 x 256
+// MFMA tile), bit-identical to one unsplit bf16x3 call per problem.
+constexpr int kGroupedMfma = cmp::kNumGroupedConfigs;
+constexpr int kGroupedAll = kGroupedMfma + 1;
+
+// The bf16x3 configuration needs every problem to read A and B: alpha == 0 or
+// K == 0 (C = beta C, operands never read) is left to the SIMT configurations.
+bool mfma_eligible(const std::vector<cmp_gemm_args>& probs) {
+    for (const auto& a : probs)
+        if (a.M > 0 && a.N > 0 && (a.alpha == 0.f || a.K == 0)) return false;
+    return true;
+}
+
+void free_plan_buffers(cmp_grouped_plan* pl) {
+    if (pl->desc) (void)hipFree(pl->desc);
+    if (pl->mdesc) (void)hipFree(pl->mdesc);
+    if (pl->images) (void)hipFree(pl->images);
+    pl->desc = nullptr;
+    pl->mdesc = nullptr;
+    pl->images = nullptr;
+    pl->counter = nullptr;
+    pl->pre_total = 0;
+}
+
+// Descriptors, images and counter of the bf16x3 configuration (problem order
+// as in build_descs).
+int build_mfma(cmp_ctx* c, cmp_grouped_plan* pl, const std::vector<cmp_gemm_args>& probs, hipStream_t s) {
+    std::vector<int> order;
+    for (int i = 0; i < (int)probs.size(); ++i)
+        if (probs[i].M > 0 && probs[i].N > 0) order.push_back(i);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        if (probs[x].K != probs[y].K) return probs[x].K > probs[y].K;
+        return (double)probs[x].M * probs[x].N > (double)probs[y].M * probs[y].N;
+    });
+    std::vector<cmp::GroupedMfmaDesc> d;
+    std::vector<size_t> img_off;              // per problem: offset of its four images
+    size_t img_bytes = 0;
+    int64_t pre = 0, tiles = 0;
+    for (int i : order) {
+        const cmp_gemm_args& a = probs[i];
+        cmp::GroupedMfmaDesc g{};
+        g.M = a.M; g.N = a.N; g.K = a.K;
+        g.lda = a.lda; g.ldb = a.ldb; g.ldc = a.ldc;
+        g.Mp = round_up(a.M, cmp::kMfmaTileM);
+        g.Np = round_up(a.N, cmp::kMfmaTileN);
+        g.Kp = round_up(a.K, cmp::kBf16TileK);
+        g.alpha = a.alpha; g.beta = a.beta;
+        g.A = a.A; g.B = a.B; g.C = a.C;
+        g.ga = (int)((g.Mp * (g.Kp / 8) + 255) / 256);
+        g.gb = (int)(((a.N + 63) / 64) * (g.Kp / 64));   // the 64-row tiles of B^T below N
+        g.pre_start = (int)pre;
+        g.tile_start = (int)tiles;
+        g.tiles_n = (int)(g.Np / cmp::kMfmaTileN);
+        g.vec = ((a.lda % 4 == 0) && ((reinterpret_cast<uintptr_t>(a.A) & 15) == 0) ? 1 : 0) |
+                ((a.ldb % 4 == 0) && ((reinterpret_cast<uintptr_t>(a.B) & 15) == 0) ? 2 : 0);
+        pre += (int64_t)g.ga + g.gb;
+        tiles += (g.Mp / cmp::kMfmaTileM) * (g.Np / cmp::kMfmaTileN);
+        // (a workgroup's copy offsets reach its panel's K blocks: 64 bytes of K x 256 rows each)
+        if (pre > INT32_MAX || tiles > INT32_MAX || g.Kp * 2 / 64 * 16384 > INT32_MAX)
+            return fail(c, CMP_EINVAL, "grouped bf16x3 launch too large");
+        img_off.push_back(img_bytes);
+        img_bytes += (size_t)round_up(g.Mp * g.Kp * 2, 256) * 2 + (size_t)round_up(g.Np * g.Kp * 2, 256) * 2;
+        d.push_back(g);
+    }
+    if (img_bytes) HIP_TRY(c, hipMalloc(&pl->images, img_bytes));
+    for (size_t p = 0; p < d.size(); ++p) {
+        uint8_t* base = reinterpret_cast<uint8_t*>(pl->images) + img_off[p];
+        const size_t as = (size_t)round_up(d[p].Mp * d[p].Kp * 2, 256), bs = (size_t)round_up(d[p].Np * d[p].Kp * 2, 256);
+        d[p].ah = reinterpret_cast<uint16_t*>(base);
+        d[p].al = reinterpret_cast<uint16_t*>(base + as);
+        d[p].bh = reinterpret_cast<uint16_t*>(base + 2 * as);
+        d[p].bl = reinterpret_cast<uint16_t*>(base + 2 * as + bs);
+    }
+    const size_t dbytes = (size_t)round_up((int64_t)(std::max<size_t>(d.size(), 1) * sizeof(cmp::GroupedMfmaDesc)), 256);
+    HIP_TRY(c, hipMalloc(&pl->mdesc, dbytes + 256));
+    pl->counter = reinterpret_cast<unsigned*>(reinterpret_cast<uint8_t*>(pl->mdesc) + dbytes);
+    if (!d.empty())
+        HIP_TRY(c, hipMemcpyAsync(pl->mdesc, d.data(), d.size() * sizeof(cmp::GroupedMfmaDesc),
+                                  hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    pl->count = (int)d.size();
+    pl->total_tiles = (int)tiles;
+    pl->pre_total = pre;
+    pl->grid = std::max(1, std::min((int)tiles, c->props.multiProcessorCount));   // one 128 KiB ring per CU
+    return CMP_OK;
+}
+
+// Buffers and launch shape of configuration cfg (the previous ones freed).
+int setup_config(cmp_ctx* c, cmp_grouped_plan* pl, const std::vector<cmp_gemm_args>& probs, int cfg,
+                 hipStream_t s) {
+    free_plan_buffers(pl);
+    pl->config = cfg;
+    if (cfg == kGroupedMfma) return build_mfma(c, pl, probs, s);
+    std::vector<cmp::GroupedDesc> d;
+    int total = 0, st;
+    if ((st = build_descs(c, probs, cfg, &d, &total))) return st;
+    if ((st = upload_descs(c, pl, d, s))) return st;
+    pl->count = (int)d.size();
+    pl->total_tiles = total;
+    pl->grid = grouped_grid(c, cfg, total);
+    return CMP_OK;
+}
+
+hipError_t plan_launch(cmp_grouped_plan* pl, hipStream_t s) {
+    if (pl->config == kGroupedMfma) {
+        hipError_t e = cmp::launch_split_grouped(pl->mdesc, pl->count, pl->pre_total, s);
+        if (e == hipSuccess)
+            e = cmp::launch_gemm_bf16x3_grouped(pl->mdesc, pl->count, pl->total_tiles, pl->grid, pl->counter, s);
+        return e;
+    }
+    return cmp::launch_gemm_f32_grouped(pl->config, pl->desc, pl->count, pl->total_tiles, pl->grid,
+                                        pl->counter, s);
+}
+
 }  // namespace
 
-CMP_API int cmp_grouped_config_count(void) { return cmp::kNumGroupedConfigs; }
+CMP_API int cmp_grouped_config_count(void) { return kGroupedAll; }
 
 CMP_API int cmp_grouped_config_info(int config, int* bm, int* bn, int* bk) {
-    if (config < 0 || config >= cmp::kNumGroupedConfigs) return CMP_EINVAL;
+    if (config < 0 || config >= kGroupedAll) return CMP_EINVAL;
+    if (config == kGroupedMfma) {
+        if (bm) *bm = cmp::kMfmaTileM;
+        if (bn) *bn = cmp::kMfmaTileN;
+        if (bk) *bk = 32;                  // bf16 values per 64-byte K block of the images
+        return CMP_OK;
+    }
     if (bm) *bm = cmp::kGroupedConfigs[config].bm;
     if (bn) *bn = cmp::kGroupedConfigs[config].bn;
     if (bk) *bk = cmp::kGroupedConfigs[config].bk;
+    return CMP_OK;
+}
+
+CMP_API int cmp_grouped_config_variant(int config, int* variant) {
+    if (config < 0 || config >= kGroupedAll || !variant) return CMP_EINVAL;
+    *variant = config == kGroupedMfma ? 1 : 0;     // built-in ids: 0 f32_simt, 1 bf16x3
     return CMP_OK;
 }
 
@@ -2462,41 +2592,47 @@ CMP_API int cmp_grouped_plan_create(cmp_ctx* c, int count, const cmp_gemm_args* 
     *out = nullptr;
     if (!c->gpu) return fail(c, CMP_EUNSUPPORTED, "needs a GPU context");
     if (count < 0 || (count > 0 && !probs)) return fail(c, CMP_EINVAL, "bad problem list");
-    if (config >= cmp::kNumGroupedConfigs) return fail(c, CMP_EINVAL, "unknown tile configuration %d", config);
+    if (config >= kGroupedAll) return fail(c, CMP_EINVAL, "unknown tile configuration %d", config);
     if (reps < 1) return fail(c, CMP_EINVAL, "reps must be >= 1");
     std::vector<cmp_gemm_args> pv(probs, probs + count);
     for (int i = 0; i < count; ++i) {
         int st = check_gemm_args(c, &pv[i]);
         if (st) return fail(c, st, "problem %d: %s", i, c->last_error.c_str());
     }
+    const bool mfma_ok = mfma_eligible(pv);
+    if (config == kGroupedMfma && !mfma_ok)
+        return fail(c, CMP_EUNSUPPORTED, "the bf16x3 configuration needs alpha != 0 and K > 0 in every problem");
     auto s = (hipStream_t)stream;
     auto* pl = new (std::nothrow) cmp_grouped_plan();
     if (!pl) return fail(c, CMP_ENOMEM, "plan");
     pl->ctx = c;
-    pl->config_ms.assign(cmp::kNumGroupedConfigs, NAN);
+    pl->config_ms.assign(kGroupedAll, NAN);
     auto cleanup = [&](int st) {
-        if (pl->desc) (void)hipFree(pl->desc);
+        free_plan_buffers(pl);
         delete pl;
         return st;
     };
-    std::vector<cmp::GroupedDesc> d;
-    int total = 0, st;
+    int st;
     if (config < 0) {
-        // autotuner: time every tile configuration on this very group, keep the fastest
+        // autotuner: time every configuration on this very group (the bf16x3 one with
+        // its pre-pass) and keep the fastest
         hipEvent_t e0, e1;
         HIP_TRY(c, hipEventCreate(&e0));
         HIP_TRY(c, hipEventCreate(&e1));
         float best = INFINITY;
         int best_cfg = 0;
-        for (int cfg = 0; cfg < cmp::kNumGroupedConfigs; ++cfg) {
-            if ((st = build_descs(c, pv, cfg, &d, &total))) return cleanup(st);
-            if ((st = upload_descs(c, pl, d, s))) return cleanup(st);
-            const int grid = grouped_grid(c, cfg, total);
+        for (int cfg = 0; cfg < kGroupedAll; ++cfg) {
+            if (cfg == kGroupedMfma && !mfma_ok) continue;
+            if ((st = setup_config(c, pl, pv, cfg, s))) {
+                (void)hipEventDestroy(e0);
+                (void)hipEventDestroy(e1);
+                return cleanup(st);
+            }
             std::vector<float> t(reps);
-            hipError_t he = cmp::launch_gemm_f32_grouped(cfg, pl->desc, (int)d.size(), total, grid, pl->counter, s);
+            hipError_t he = plan_launch(pl, s);
             for (int r = 0; r < reps && he == hipSuccess; ++r) {
                 (void)hipEventRecord(e0, s);
-                he = cmp::launch_gemm_f32_grouped(cfg, pl->desc, (int)d.size(), total, grid, pl->counter, s);
+                he = plan_launch(pl, s);
                 (void)hipEventRecord(e1, s);
                 if (he == hipSuccess) he = hipEventSynchronize(e1);
                 if (he == hipSuccess) he = hipEventElapsedTime(&t[r], e0, e1);
@@ -2517,19 +2653,13 @@ CMP_API int cmp_grouped_plan_create(cmp_ctx* c, int count, const cmp_gemm_args* 
         (void)hipEventDestroy(e1);
         config = best_cfg;
     }
-    if ((st = build_descs(c, pv, config, &d, &total))) return cleanup(st);
-    if ((st = upload_descs(c, pl, d, s))) return cleanup(st);
-    pl->config = config;
-    pl->count = (int)d.size();
-    pl->total_tiles = total;
-    pl->grid = grouped_grid(c, config, total);
+    if ((st = setup_config(c, pl, pv, config, s))) return cleanup(st);
     // capture the launch into a graph on a private stream
     hipStream_t cap = nullptr;
     hipError_t he = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
     if (he == hipSuccess) he = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (he == hipSuccess) {
-        hipError_t le = cmp::launch_gemm_f32_grouped(pl->config, pl->desc, pl->count, pl->total_tiles,
-                                                     pl->grid, pl->counter, cap);
+        hipError_t le = plan_launch(pl, cap);
         he = hipStreamEndCapture(cap, &pl->graph);
         if (he == hipSuccess) he = le;
     }
@@ -2552,15 +2682,14 @@ CMP_API int cmp_grouped_plan_info(const cmp_grouped_plan* pl, int* config, int* 
     if (tiles) *tiles = pl->total_tiles;
     if (grid) *grid = pl->grid;
     if (config_ms)
-        for (int i = 0; i < cmp::kNumGroupedConfigs; ++i) config_ms[i] = pl->config_ms[i];
+        for (int i = 0; i < kGroupedAll; ++i) config_ms[i] = pl->config_ms[i];
     return CMP_OK;
 }
 
 CMP_API int cmp_grouped_launch(cmp_grouped_plan* pl, void* stream) {
     if (!pl) return CMP_EINVAL;
     cmp_ctx* c = pl->ctx;
-    HIP_TRY(c, cmp::launch_gemm_f32_grouped(pl->config, pl->desc, pl->count, pl->total_tiles, pl->grid,
-                                            pl->counter, (hipStream_t)stream));
+    HIP_TRY(c, plan_launch(pl, (hipStream_t)stream));
     return CMP_OK;
 }
 
@@ -2576,7 +2705,7 @@ CMP_API int cmp_grouped_plan_destroy(cmp_grouped_plan* pl) {
     (void)hipDeviceSynchronize();
     if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
     if (pl->graph) (void)hipGraphDestroy(pl->graph);
-    if (pl->desc) (void)hipFree(pl->desc);
+    free_plan_buffers(pl);
     delete pl;
     return CMP_OK;
 }

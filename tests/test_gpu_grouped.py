@@ -1,7 +1,9 @@
-"""Grouped launches of many GEMMs of uneven shapes: every tile configuration and the autotuned
-plan give results bit-identical to one f32_simt launch per problem (each entry is the same
-chain of FP32 FMAs over k), within 1e-5 of the FP64 oracle per problem; the captured graph
-replays correctly several times with eager work in between."""
+"""Grouped launches of many GEMMs of uneven shapes: every configuration gives results
+bit-identical to one launch per problem of the variant whose arithmetic it uses (the FP32 SIMT
+tiles: f32_simt, each entry the same chain of FP32 FMAs over k; the MFMA configuration: an
+unsplit bf16x3 call, the same pre-pass images and the same tile code), the autotuned plan is
+within 1e-5 of the FP64 oracle per problem, and the captured graph replays correctly several
+times with eager work in between."""
 import numpy as np
 import pytest
 
@@ -31,13 +33,19 @@ def _problems(count, seed, lo=32, hi=1024):
     return probs
 
 
-def _run_separate(cx, dprobs):
+def _run_separate(cx, dprobs, variant=0):
+    """One launch per problem of built-in variant `variant` (unsplit: the grouped MFMA
+    configuration runs every problem's whole K range in one tile)."""
     import torch
     outs = []
-    for dA, dB in dprobs:
-        dC = torch.zeros((dA.shape[0], dB.shape[1]), device="cuda")
-        cx.gemm_variant(0, dA, dB, dC)
-        outs.append(dC)
+    cx.set_split_k(1)
+    try:
+        for dA, dB in dprobs:
+            dC = torch.zeros((dA.shape[0], dB.shape[1]), device="cuda")
+            cx.gemm_variant(variant, dA, dB, dC)
+            outs.append(dC)
+    finally:
+        cx.set_split_k(0)
     return [host(o) for o in outs]
 
 
@@ -46,10 +54,15 @@ def test_every_config_bit_identical_to_separate(cx):
     import paper_2311_03543_amd as pa
     probs = _problems(40, 1, 32, 600)
     dprobs = [(dev(A), dev(B)) for A, B in probs]
-    ref = _run_separate(cx, dprobs)
+    refs = {}
+    assert sorted({pa.grouped_config_variant(c) for c in range(len(pa.grouped_configs()))}) == [0, 1]
     for cfg in range(len(pa.grouped_configs())):
+        v = pa.grouped_config_variant(cfg)
+        if v not in refs:
+            refs[v] = _run_separate(cx, dprobs, v)
+        ref = refs[v]
         outs = [torch.zeros((A.shape[0], B.shape[1]), device="cuda") for A, B in probs]
-        say(f"  grouped config {cfg} {pa.grouped_configs()[cfg]}")
+        say(f"  grouped config {cfg} {pa.grouped_configs()[cfg]} (variant {v})")
         plan = cx.grouped_plan([(a, b, o) for (a, b), o in zip(dprobs, outs)], config=cfg)
         try:
             plan.launch()
@@ -115,15 +128,17 @@ def test_degenerate_problems_in_a_group(cx):
         plan.destroy()
 
 
-@pytest.mark.parametrize("cfg", [0, 4, 7])
+@pytest.mark.parametrize("cfg", [0, 4, 7, 10])
 def test_tile_queue_with_many_more_tiles_than_workgroups(cx, cfg):
     """A group with several times more tiles than resident workgroups, so that most tiles are
-    claimed from the plan's counter: every problem bit-identical to its own f32_simt launch, on
-    an eager launch, a second eager launch (the counter is zeroed again) and a graph replay."""
+    claimed from the plan's counter: every problem bit-identical to its own launch of the
+    configuration's variant, on an eager launch, a second eager launch (the counter is zeroed
+    again) and a graph replay."""
     import torch
+    import paper_2311_03543_amd as pa
     probs = _problems(300, 7, 192, 1024)
     dprobs = [(dev(A), dev(B)) for A, B in probs]
-    ref = _run_separate(cx, dprobs)
+    ref = _run_separate(cx, dprobs, pa.grouped_config_variant(cfg))
     outs = [torch.zeros((A.shape[0], B.shape[1]), device="cuda") for A, B in probs]
     plan = cx.grouped_plan([(a, b, o) for (a, b), o in zip(dprobs, outs)], config=cfg)
     try:
@@ -140,3 +155,29 @@ def test_tile_queue_with_many_more_tiles_than_workgroups(cx, cfg):
                 assert np.array_equal(g_.view(np.uint32), r.view(np.uint32)), how
     finally:
         plan.destroy()
+
+
+def test_mfma_configuration_needs_operands_read(cx):
+    """The bf16x3 configuration reads A and B of every problem, so a group holding a problem
+    with alpha = 0 or K = 0 (C = beta C, operands never read) is refused for it, and the
+    autotuner leaves it out; the SIMT configurations serve such a group."""
+    import torch
+    import paper_2311_03543_amd as pa
+    mfma = [c for c in range(len(pa.grouped_configs())) if pa.grouped_config_variant(c) == 1]
+    assert len(mfma) == 1
+    A, B = synth.gemm_operands(70, 90, 50, seed=5)
+    C0 = synth.normal_matrix(70, 90, 6)
+    dA, dB = dev(A), dev(B)
+    for extra in ((dA, dB, dev(C0), 0.0, 2.0),
+                  (torch.zeros((70, 0), device="cuda"), torch.zeros((0, 90), device="cuda"), dev(C0), 1.0, 0.5)):
+        group = [(dA, dB, torch.zeros((70, 90), device="cuda")), extra]
+        with pytest.raises(pa.ComparError) as err:
+            cx.grouped_plan(group, config=mfma[0])
+        assert err.value.status == pa.CMP_EUNSUPPORTED
+        plan = cx.grouped_plan(group, config=-1, reps=2)
+        try:
+            info = plan.info()
+            assert info["config_ms"][mfma[0]] is None and info["config"] != mfma[0]
+            assert all(v is not None for i, v in enumerate(info["config_ms"]) if i != mfma[0])
+        finally:
+            plan.destroy()
