@@ -169,8 +169,9 @@ __global__ __launch_bounds__(256) void split_pair_kernel(SplitPair p) {
 // The hi / lo images of every problem of a grouped bf16x3 plan in one launch:
 // workgroup w belongs to the problem p with desc[p].pre_start <= w (problems
 // in list order, each A's ga workgroups then B's gb), one split_a chunk pass
-// or one split_bt tile per workgroup.  Only rows below M (A) and the 64-row
-// tiles that start below N (B^T) are written: padding rows of an image feed
+// or one split_bt tile per workgroup.  Only rows below M (A, whose idle
+// 64-row quarters get no workgroup) and the 64-row tiles that start below N
+// (B^T) are written: padding rows of an image feed
 // only output rows and columns past the problem, which the GEMM never stores,
 // while padding K inside the written rows is zero as the products need.
 __global__ __launch_bounds__(256) void split_grouped_kernel(const GroupedMfmaDesc* __restrict__ desc,
@@ -188,8 +189,19 @@ __global__ __launch_bounds__(256) void split_grouped_kernel(const GroupedMfmaDes
     const __attribute__((address_space(1))) GroupedMfmaDesc& d = dg[lo];
     const int local = w - d.pre_start;
     if (local < d.ga) {
-        if (d.vec & 1) split_a<true>(local, d.ga, d.M, d.K, d.A, d.lda, d.Mp, d.Kp, d.ah, d.al, d.M);
-        else split_a<false>(local, d.ga, d.M, d.K, d.A, d.lda, d.Mp, d.Kp, d.ah, d.al, d.M);
+        // split_a workgroup bx covers rows 64 (bx % 4) .. + 63 of block bx / 4 (block =
+        // row panel x K block): the ga workgroups here are those whose rows start below M,
+        // the full panels' (four quarters per block) and then the last panel's nq quarters
+        const int64_t nkb = d.Kp * 2 / kPanelRowBytes;
+        const int64_t full = d.M / kPanelRows, nq = ((d.M % kPanelRows) + 63) / 64;
+        int64_t bx = local;
+        if (bx >= full * nkb * 4) {
+            const int64_t c = bx - full * nkb * 4;
+            bx = (full * nkb + c / nq) * 4 + c % nq;
+        }
+        const int64_t gx = d.Mp * (d.Kp / 8) / 256;   // every chunk pass: one iteration each
+        if (d.vec & 1) split_a<true>(bx, gx, d.M, d.K, d.A, d.lda, d.Mp, d.Kp, d.ah, d.al, d.M);
+        else split_a<false>(bx, gx, d.M, d.K, d.A, d.lda, d.Mp, d.Kp, d.ah, d.al, d.M);
     } else if (local - d.ga < d.gb) {
         if (d.vec & 2) split_bt<true>(local - d.ga, d.K, d.N, d.B, d.ldb, d.Kp, d.bh, d.bl, T);
         else split_bt<false>(local - d.ga, d.K, d.N, d.B, d.ldb, d.Kp, d.bh, d.bl, T);

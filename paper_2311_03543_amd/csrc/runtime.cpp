@@ -2496,7 +2496,8 @@ int build_mfma(cmp_ctx* c, cmp_grouped_plan* pl, const std::vector<cmp_gemm_args
         g.Kp = round_up(a.K, cmp::kBf16TileK);
         g.alpha = a.alpha; g.beta = a.beta;
         g.A = a.A; g.B = a.B; g.C = a.C;
-        g.ga = (int)((g.Mp * (g.Kp / 8) + 255) / 256);
+        // A: one workgroup per 64-row quarter of a 256-row x 64-byte block below M
+        g.ga = (int)((a.M / 256 * 4 + (a.M % 256 + 63) / 64) * (g.Kp * 2 / 64));
         g.gb = (int)(((a.N + 63) / 64) * (g.Kp / 64));   // the 64-row tiles of B^T below N
         g.pre_start = (int)pre;
         g.tile_start = (int)tiles;
