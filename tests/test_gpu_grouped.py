@@ -181,3 +181,40 @@ def test_mfma_configuration_needs_operands_read(cx):
             assert all(v is not None for i, v in enumerate(info["config_ms"]) if i != mfma[0])
         finally:
             plan.destroy()
+
+
+def test_mfma_configuration_unaligned_operands(cx):
+    """The bf16x3 configuration on operands that are column slices of wider tensors (leading
+    dimensions that are not multiples of 4, first elements off 16-byte alignment), with alpha and
+    beta general: the pre-pass takes its element-wise load paths, and every problem stays
+    bit-identical to its own unsplit bf16x3 call."""
+    import torch
+    import paper_2311_03543_amd as pa
+    mfma = next(c for c in range(len(pa.grouped_configs())) if pa.grouped_config_variant(c) == 1)
+    g = synth.rng(31)
+    shapes = [(77, 130, 45), (300, 257, 129), (5, 600, 70), (513, 33, 300)]
+    group, refs, outs = [], [], []
+    for i, (M, N, K) in enumerate(shapes):
+        Aw = dev(g.standard_normal((M, K + 3), dtype=np.float32))
+        Bw = dev(g.standard_normal((K, N + 5), dtype=np.float32))
+        C0 = g.standard_normal((M, N), dtype=np.float32)
+        A, B = Aw[:, 1:K + 1], Bw[:, 3:N + 3]          # lda = K + 3, ldb = N + 5, misaligned starts
+        alpha, beta = (1.0, 0.0) if i % 2 == 0 else (-0.75, 0.5)
+        ref = dev(C0)
+        cx.set_split_k(1)
+        try:
+            cx.gemm_variant(1, A, B, ref, alpha, beta)
+        finally:
+            cx.set_split_k(0)
+        refs.append(host(ref))
+        out = dev(C0)
+        outs.append(out)
+        group.append((A, B, out, alpha, beta))
+    plan = cx.grouped_plan(group, config=mfma)
+    try:
+        say("  grouped bf16x3 on sliced operands")
+        plan.launch()
+        for o, r in zip(outs, refs):
+            assert np.array_equal(host(o).view(np.uint32), r.view(np.uint32))
+    finally:
+        plan.destroy()
