@@ -521,3 +521,26 @@ c.close()
     import json
     recs = [json.loads(l) for l in open(path).read().splitlines()]
     assert len(recs) == 1 and recs[0]["variant"] == "host_f32" and recs[0]["M"] == 8
+
+
+def test_grouped_configuration_table():
+    """The grouped configurations (no GPU needed): the FP32 SIMT tiles reproduce f32_simt
+    (variant 0), the last one bf16x3 (variant 1) with the 256 x 256 MFMA tile and a 32-value
+    K block; out-of-range indices and a null output are refused."""
+    L = _lib.load()
+    n = L.cmp_grouped_config_count()
+    assert n >= 2
+    v = C.c_int()
+    variants = []
+    for i in range(n):
+        assert L.cmp_grouped_config_variant(i, C.byref(v)) == pa.CMP_OK
+        variants.append(v.value)
+    assert variants == [0] * (n - 1) + [1]
+    bm, bn, bk = C.c_int(), C.c_int(), C.c_int()
+    assert L.cmp_grouped_config_info(n - 1, C.byref(bm), C.byref(bn), C.byref(bk)) == pa.CMP_OK
+    assert (bm.value, bn.value, bk.value) == (256, 256, 32)
+    for bad in (-1, n):
+        assert L.cmp_grouped_config_variant(bad, C.byref(v)) == pa.CMP_EINVAL
+        assert L.cmp_grouped_config_info(bad, C.byref(bm), C.byref(bn), C.byref(bk)) == pa.CMP_EINVAL
+    assert L.cmp_grouped_config_variant(0, None) == pa.CMP_EINVAL
+    assert [pa.grouped_config_variant(i) for i in range(n)] == variants
